@@ -1,0 +1,244 @@
+/*
+ * libspmv -- CRS sparse matrix-vector multiplication for AMD MI355X (gfx950).
+ *
+ * The operation is the Compressed Row Storage product of the paper's
+ * Sect. 1.2: the nonzeros of A are held row by row in `val`, their column
+ * indices in `col_idx` and the start offset of every row in `row_ptr`, and
+ *
+ *     C(i) = sum_{j = row_ptr(i)}^{row_ptr(i+1)-1} val(j) * B(col_idx(j))
+ *
+ * with C overwritten (the listing accumulates into a C that starts at zero).
+ *
+ * Conventions for every entry point:
+ *  - Indices are 0-based. row_ptr and col_idx are int32 (the paper's 4-byte
+ *    index), so nnz < 2^31; larger inputs return SPMV_ERR_UNSUPPORTED.
+ *  - Every array argument is a DEVICE pointer owned by the caller unless the
+ *    comment says "host". A handle BORROWS the matrix arrays and the
+ *    workspace: they must stay alive and unchanged until the handle is
+ *    destroyed. The library never allocates device memory for a matrix; all
+ *    per-matrix device state lives in the caller's workspace.
+ *  - `stream` is a hipStream_t passed as void*; NULL is the null stream.
+ *    Apply calls are asynchronous on that stream, never synchronise, never
+ *    allocate, and may be captured into a HIP graph. They are const on the
+ *    handle: concurrent applies on different streams with disjoint C are
+ *    safe. B and C must not overlap.
+ *  - Results are deterministic run to run: no floating-point atomics; each
+ *    output element is reduced by one thread group in a fixed order.
+ *  - Errors are returned as negative status codes; nothing is thrown across
+ *    the ABI. spmv_last_error() gives a thread-local description of the last
+ *    failure on the calling thread.
+ *  - Accuracy: each row is a sum of the products val(j)*B(col_idx(j)) in
+ *    float64 (fused multiply-add allowed), so |C - C_exact| is at most about
+ *    nnz_row * 2^-53 * sum_j |val(j) B(col_idx(j))|. Float32-stored val and B
+ *    are widened exactly; their products are exact in float64, so only the
+ *    float64 summation error remains.
+ */
+#ifndef SPMV_H
+#define SPMV_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ------------------------------------------------------------------ types */
+
+typedef struct spmv_plan* spmv_handle;        /* one analysed matrix */
+typedef struct spmv_batch* spmv_batch_handle; /* an uneven batch of matrices */
+typedef struct spmv_graph* spmv_graph_handle; /* an instantiated HIP graph */
+
+typedef enum { SPMV_F64 = 0, SPMV_F32 = 1 } spmv_dtype;
+
+typedef enum {
+  SPMV_OK = 0,
+  SPMV_ERR_INVALID_ARG = -1, /* null pointer, negative size, bad enum, ldb < k ... */
+  SPMV_ERR_BAD_CRS = -2,     /* row_ptr/col_idx violate the CRS definition */
+  SPMV_ERR_UNSUPPORTED = -3, /* size or dtype combination not supported */
+  SPMV_ERR_WORKSPACE = -4,   /* workspace missing, too small or misaligned */
+  SPMV_ERR_HIP = -5,         /* a HIP runtime call failed */
+  SPMV_ERR_STATE = -6        /* call not valid in the current state */
+} spmv_status;
+
+/* Kernel variants: the same product with different thread-to-work maps. */
+typedef enum {
+  SPMV_V0_THREAD_ROW = 0, /* one lane per row */
+  SPMV_V1_LANES4 = 1,     /* 4 lanes per row, DPP reduction */
+  SPMV_V2_LANES16 = 2,    /* 16 lanes per row, DPP reduction */
+  SPMV_V3_WAVE_ROW = 3,   /* one 64-lane wavefront per row */
+  SPMV_V4_LDS_BLOCK = 4,  /* nnz-balanced row blocks staged through LDS */
+  SPMV_V5_BINNED = 5,     /* row-length bins, one launch per non-empty bin */
+  SPMV_NUM_VARIANTS = 6
+} spmv_variant;
+
+/* spmv_create flags. The low byte selects how the variant is chosen. */
+#define SPMV_SELECT_DEFAULT 0x0u  /* MLP selector if loaded, else V4 */
+#define SPMV_SELECT_MLP 0x1u      /* MLP selector; fall back to autotune when unsure */
+#define SPMV_SELECT_AUTOTUNE 0x2u /* time every variant, keep the fastest */
+#define SPMV_SELECT_FIXED 0x3u    /* use the variant in bits 8..11 */
+#define SPMV_FLAG_VARIANT(v) (SPMV_SELECT_FIXED | ((uint32_t)(v) << 8))
+#define SPMV_FLAG_SKIP_VALIDATE 0x10000u /* trust the CRS arrays (no device check) */
+
+#define SPMV_NUM_FEATURES 16
+#define SPMV_MLP_PARAMS 5638 /* 16->64->64->6: W1 b1 W2 b2 W3 b3, [out,in] row-major */
+
+/* ---------------------------------------------------------- single matrix */
+
+/*
+ * Bytes of device workspace spmv_create needs for this shape (host call, no
+ * device work). The workspace holds the row-block table, the row-length bin
+ * lists, the analysis counters and the selector scratch. It depends only on
+ * (n_rows, nnz) and is stable across calls. `bytes` is a host pointer.
+ */
+int spmv_workspace_size(int64_t n_rows, int64_t n_cols, int64_t nnz, uint32_t flags,
+                        size_t* bytes);
+
+/*
+ * Analyse a CRS matrix and build a plan (the paper's point that the
+ * bookkeeping of a sparsity pattern is done once and reused, Sect. 3.1).
+ *  h        host out: the new handle
+ *  n_rows, n_cols >= 0; nnz = row_ptr[n_rows] >= 0, nnz < 2^31
+ *  row_ptr  int32[n_rows+1], col_idx int32[nnz], val float64 or float32 [nnz]
+ *  val_dtype SPMV_F64 or SPMV_F32
+ *  workspace device, >= spmv_workspace_size() bytes, 256-byte aligned
+ *  flags    SPMV_SELECT_* | SPMV_FLAG_SKIP_VALIDATE
+ *  stream   the stream for the analysis kernels
+ * Unless SPMV_FLAG_SKIP_VALIDATE is set, the CRS arrays are checked on the
+ * device (row_ptr[0]=0, nondecreasing, row_ptr[n_rows]=nnz, 0<=col<n_cols)
+ * and SPMV_ERR_BAD_CRS is returned on violation. This call synchronises the
+ * stream once (to read back the analysis); it is the only call that does.
+ */
+int spmv_create(spmv_handle* h, int64_t n_rows, int64_t n_cols, int64_t nnz,
+                const int32_t* row_ptr, const int32_t* col_idx, const void* val,
+                int val_dtype, void* workspace, size_t ws_bytes, uint32_t flags, void* stream);
+
+/*
+ * C = A*B (Sect. 1.2). B: n_cols entries of b_dtype; C: float64[n_rows].
+ * b_dtype must equal the handle's val_dtype (float64 with float64, or
+ * float32 val with float32 B: float64 accumulation and output either way).
+ */
+int spmv_apply(spmv_handle h, const void* B, int b_dtype, double* C, void* stream);
+
+/*
+ * Multi-RHS form, row-major blocks: C[i*ldc + c] = sum_j val(j) B[col_idx(j)*ldb + c]
+ * for 0 <= c < k. Requires k >= 1, ldb >= k, ldc >= k. The matrix stream is
+ * read once for all k columns.
+ */
+int spmm_apply(spmv_handle h, int32_t k, const void* B, int64_t ldb, int b_dtype, double* C,
+               int64_t ldc, void* stream);
+
+/* Variant in use (host out). */
+int spmv_get_variant(spmv_handle h, int* variant);
+/* Switch the variant of an existing plan (all variants' tables are built at create). */
+int spmv_set_variant(spmv_handle h, int variant);
+/* The 16 row-statistics features computed at create (host out, float64[16]). */
+int spmv_get_features(spmv_handle h, double* features);
+/* The selector's 6 predicted relative log2 times from create (host out, float[6]);
+ * SPMV_ERR_STATE if no selector was run. */
+int spmv_get_predictions(spmv_handle h, float* pred);
+/* Per-variant median times in microseconds measured by SPMV_SELECT_AUTOTUNE
+ * (host out, double[6]); SPMV_ERR_STATE if autotune did not run. */
+int spmv_get_autotune_times(spmv_handle h, double* us);
+/* Number of row blocks of the LDS-block variant (host out). */
+int spmv_get_num_blocks(spmv_handle h, int64_t* nblocks);
+int spmv_destroy(spmv_handle h);
+
+/*
+ * Split local/remote product (the paper's Sect. 3.1 naive-overlap kernel
+ * structure, eq. (2)) on one device: columns [col_lo, col_hi) are "local".
+ * pass 0 writes C = A_local * B; pass 1 adds C += A_remote * B, where
+ * A_remote are the entries with columns outside [col_lo, col_hi). C is
+ * written twice, which is the extra traffic eq. (2) models.
+ */
+int spmv_apply_split(spmv_handle h, int pass, int64_t col_lo, int64_t col_hi, const void* B,
+                     int b_dtype, double* C, void* stream);
+
+/* ----------------------------------------------------------- uneven batch */
+
+/*
+ * Many independent small matrices, multiplied by one persistent launch.
+ * All array-of-pointer arguments are DEVICE arrays (of device pointers);
+ * `n_rows`, `n_cols` and `nnz` are HOST arrays of length `count`.
+ * The matrices are split into nnz-balanced row tiles whose (matrix, rows)
+ * list is built on the device at create. All matrices share val_dtype.
+ */
+int spmv_batch_workspace_size(int32_t count, int64_t total_rows, int64_t total_nnz,
+                              size_t* bytes);
+int spmv_batch_create(spmv_batch_handle* h, int32_t count, const int64_t* n_rows,
+                      const int64_t* n_cols, const int64_t* nnz,
+                      const int32_t* const* row_ptrs, const int32_t* const* col_idxs,
+                      const void* const* vals, int val_dtype, void* workspace, size_t ws_bytes,
+                      void* stream);
+/* C^m = A^m B^m for every m, one launch. Bs / Cs: device arrays of `count`
+ * device pointers. */
+int spmv_batch_apply(spmv_batch_handle h, const void* const* Bs, double* const* Cs,
+                     int b_dtype, void* stream);
+/* The same product as `count` separate launches (host arrays of device
+ * pointers), for comparison with the persistent launch. */
+int spmv_batch_apply_each(spmv_batch_handle h, const void* const* Bs_host,
+                          double* const* Cs_host, int b_dtype, void* stream);
+int spmv_batch_get_num_tiles(spmv_batch_handle h, int64_t* ntiles);
+int spmv_batch_destroy(spmv_batch_handle h);
+
+/* ------------------------------------------------------------- HIP graphs */
+
+/* Start capturing the calls issued on `stream` (thread-local capture mode).
+ * Only apply-type calls may be issued until spmv_graph_end. */
+int spmv_graph_begin(void* stream);
+/* End the capture and instantiate it into *g. */
+int spmv_graph_end(void* stream, spmv_graph_handle* g);
+int spmv_graph_launch(spmv_graph_handle g, void* stream);
+int spmv_graph_destroy(spmv_graph_handle g);
+
+/* ---------------------------------------------------------------- selector */
+
+/*
+ * Load the selector network on the current device (host arrays):
+ *  params   float[SPMV_MLP_PARAMS] in the layout above
+ *  feat_mu, feat_sigma  float[16]: inputs are (feature - mu) / sigma
+ *  feat_lo, feat_hi     float[16]: training range; a feature outside
+ *                       [lo, hi] makes SPMV_SELECT_MLP fall back to autotune
+ *  margin   minimum predicted gap (log2 units) between the best two variants
+ *           below which SPMV_SELECT_MLP falls back to autotune
+ */
+int spmv_selector_load(const float* params, const float* feat_mu, const float* feat_sigma,
+                       const float* feat_lo, const float* feat_hi, float margin);
+int spmv_selector_loaded(int* loaded);
+
+/*
+ * Selector network kernels (device arrays, float32), used by the trainer.
+ *  forward:  X[nb,16] -> Y[nb,6]; Z1, Z2 [nb,64] keep pre-activations
+ *  backward: mean-squared-error loss against T[nb,6] -> grad[SPMV_MLP_PARAMS];
+ *            dz scratch: float[nb*(64+64+6)]
+ *  adam:     one Adam step t>=1 on theta with moments m, v (all [SPMV_MLP_PARAMS])
+ */
+int spmv_mlp_forward(const float* theta, const float* X, int32_t nb, float* Y, float* Z1,
+                     float* Z2, void* stream);
+int spmv_mlp_backward(const float* theta, const float* X, const float* Z1, const float* Z2,
+                      const float* Y, const float* T, int32_t nb, float* dz_scratch,
+                      float* grad, void* stream);
+int spmv_mlp_adam(float* theta, const float* grad, float* m, float* v, int32_t t, float lr,
+                  float beta1, float beta2, float eps, void* stream);
+
+/* ------------------------------------------------------------ measurement */
+
+/* STREAM-style triad a[i] = b[i] + s*c[i] over float64[n] (the paper's
+ * practical bandwidth ceiling, Sect. 2), for the roofline denominator. */
+int spmv_stream_triad(double* a, const double* b, const double* c, double s, int64_t n,
+                      void* stream);
+/* Plain copy dst[i] = src[i] over float64[n] (counter calibration). */
+int spmv_stream_copy(double* dst, const double* src, int64_t n, void* stream);
+
+/* ------------------------------------------------------------------- misc */
+
+const char* spmv_status_string(int status);
+const char* spmv_last_error(void);
+/* Library version, e.g. "1.0.0". */
+const char* spmv_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SPMV_H */
