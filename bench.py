@@ -1,0 +1,248 @@
+"""Benchmark: FP64 CRS spMVM on the Hamiltonian-like workload (N = 6.0M rows,
+diagonal + 7 symmetric offset pairs), one MI355X.
+
+One step = one C = A*B product through spmv_apply with the plan's variant,
+inputs resident in HBM. Prints ONE JSON line (rank 0) with GFlop/s, the
+roofline of the product kernel (HBM-bound: compulsory bytes / kernel time
+against 8 TB/s), and the CPU oracle timed on the host as a baseline. Extra
+measurements (FP32 storage, the permuted-stencil workload, multi-RHS, the
+uneven batch, a triad) go into "extra".
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "CRS spMVM GFlop/s and effective HBM GB/s (% roofline) at 1 MI355X, FP64 vs mixed"
+HBM_PEAK = 8000.0  # GB/s, MI355X nominal
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def kernel_source_hash() -> str:
+    h = hashlib.sha256()
+    for f in ("device.hpp", "spmv_kernels.hip", "common.hpp"):
+        h.update(open(os.path.join(ROOT, "paper_1101_0091_amd", "csrc", f), "rb").read())
+    return h.hexdigest()[:16]
+
+
+def stored_traffic(workload: str, variant_name: str):
+    """HBM bytes per launch from committed rocprofv3 PMC runs, if they were
+    taken on the current kernel source; else None."""
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    if not os.path.exists(path):
+        return None
+    try:
+        d = json.load(open(path))
+        e = d.get(f"{workload}/{variant_name}")
+        if e and e.get("kernel_source_hash") == kernel_source_hash():
+            return e["hbm_bytes_per_launch"]
+    except (ValueError, KeyError):
+        pass
+    return None
+
+
+def time_launches(fn, steps, warmup, stream):
+    """Per-launch HIP-event durations (ms) on the launch stream, plus the
+    whole-region wall time (s) bracketed by device synchronisation."""
+    import torch
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+          for _ in range(steps)]
+    t0 = time.perf_counter()
+    for a, b in ev:
+        a.record(stream)
+        fn()
+        b.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    per = [a.elapsed_time(b) for a, b in ev]
+    return per, wall
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--no-extra", action="store_true")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--variant", type=int, default=-1, help="force a variant (default: autotune)")
+    ap.add_argument("--workload", default="hamiltonian", choices=["hamiltonian", "mesh"])
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(sharding is described in DESIGN.md); run with --gpus 1", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import crsgen
+    import paper_1101_0091_amd as pkg
+    from paper_1101_0091_amd import perfmodel as pm
+
+    dev = torch.device("cuda:0")
+    stream = torch.cuda.current_stream()
+    if args.workload == "hamiltonian":
+        wname, seed = "hamiltonian_like_N6M", 2
+        log("generating Hamiltonian-like matrix N=6,000,000")
+        A = crsgen.hamiltonian(6_000_000, seed=seed)
+    else:
+        wname, seed = "mesh3d_280_permuted_N21.95M", 3
+        log("generating permuted 3D stencil matrix N=21,952,000")
+        A = crsgen.mesh3d(280, seed=seed)[0]
+    B = crsgen.uniform_vec(A.n_cols, seed)
+    flags = pkg.SPMV_SELECT_AUTOTUNE if args.variant < 0 else pkg.SPMV_FLAG_VARIANT(args.variant)
+    M = pkg.CRSMatrix.from_crs(A, flags=flags, device=dev)
+    vname = pkg.VARIANTS[M.variant]
+    log(f"plan ready: nnz={A.nnz} variant={vname} blocks={M.num_blocks}")
+    Bd = torch.from_numpy(B).to(dev)
+    C = torch.empty(A.n_rows, dtype=torch.float64, device=dev)
+    h = M.handle
+
+    def step():
+        pkg.spmv_apply(h, Bd, pkg.SPMV_F64, C)
+
+    per, wall = time_launches(step, args.steps, args.warmup, stream)
+    k_ms = float(np.mean(per))
+    ms_per_step = 1000.0 * wall / args.steps
+    secs = ms_per_step / 1000.0
+    nnz = A.nnz
+    value = pm.gflops(nnz, secs)
+    comp = pm.compulsory_bytes(A.n_rows, A.n_cols, nnz)
+    achieved = comp / (k_ms / 1000.0) / 1e9
+    log(f"fp64: {ms_per_step:.4f} ms/step, kernel {k_ms:.4f} ms, {value:.1f} GFlop/s, "
+        f"{achieved:.1f} GB/s")
+    traffic = stored_traffic(wname, vname)
+    out = {
+        "metric": METRIC,
+        "value": round(value, 2),
+        "unit": "GFlop/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 5),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": wname, "n_rows": A.n_rows, "nnz": nnz, "seed": seed,
+                   "variant": vname, "rhs": "uniform[-1,1)"},
+        "eff_gbs": round(pm.effective_gbs(A.n_rows, A.n_cols, nnz, secs), 1),
+        "pct_hbm_roofline": round(100.0 * pm.effective_gbs(A.n_rows, A.n_cols, nnz, secs)
+                                  / HBM_PEAK, 2),
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK,
+                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK, 4),
+                     "traffic": traffic, "kernel": "k_lds_block<double,double>" if
+                     vname.startswith("V4") else vname, "kernel_ms": round(k_ms, 5),
+                     "algorithmic_bytes_per_launch": comp},
+    }
+    extra = {}
+    if not args.no_extra:
+        extra = run_extra(A, B, M, pkg, pm, dev, stream, args)
+    out["extra"] = extra
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(A, B)
+    print(json.dumps(out), flush=True)
+
+
+def run_extra(A, B, M, pkg, pm, dev, stream, args):
+    import numpy as np
+    import torch
+
+    import crsgen
+    ex = {}
+    steps = max(20, args.steps // 4)
+    # variants on the same matrix
+    Bd = torch.from_numpy(B).to(dev)
+    C = torch.empty(A.n_rows, dtype=torch.float64, device=dev)
+    var_ms = {}
+    v0 = M.variant
+    for v in range(pkg.SPMV_NUM_VARIANTS):
+        M.variant = v
+        per, _ = time_launches(lambda: pkg.spmv_apply(M.handle, Bd, pkg.SPMV_F64, C), steps, 3,
+                               stream)
+        var_ms[pkg.VARIANTS[v]] = round(float(np.median(per)), 5)
+    M.variant = v0
+    ex["variant_ms"] = var_ms
+    log(f"variants: {var_ms}")
+    # FP32 storage, FP64 accumulation
+    M32 = pkg.CRSMatrix(A.n_rows, A.n_cols, A.row_ptr, A.col_idx, A.val.astype(np.float32),
+                        val_dtype=torch.float32, flags=pkg.SPMV_SELECT_AUTOTUNE, device=dev)
+    B32 = torch.from_numpy(B.astype(np.float32)).to(dev)
+    per, _ = time_launches(lambda: pkg.spmv_apply(M32.handle, B32, pkg.SPMV_F32, C), steps, 5,
+                           stream)
+    t = float(np.mean(per)) / 1000
+    ex["mixed_fp32_storage"] = {
+        "gflops": round(pm.gflops(A.nnz, t), 1),
+        "eff_gbs": round(pm.effective_gbs(A.n_rows, A.n_cols, A.nnz, t, 1, 4, 4), 1),
+        "variant": pkg.VARIANTS[M32.variant], "kernel_ms": round(t * 1000, 5)}
+    log(f"mixed: {ex['mixed_fp32_storage']}")
+    del M32
+    # triad ceiling
+    n = 1 << 27
+    a = torch.empty(n, dtype=torch.float64, device=dev)
+    b = torch.rand(n, dtype=torch.float64, device=dev)
+    c = torch.rand(n, dtype=torch.float64, device=dev)
+    per, _ = time_launches(lambda: pkg.spmv_stream_triad(a, b, c, 3.0, n), 20, 3, stream)
+    tt = float(np.median(per)) / 1000
+    ex["triad_gbs"] = round(24 * n / tt / 1e9, 1)
+    per, _ = time_launches(lambda: pkg.spmv_stream_copy(a, b, n), 20, 3, stream)
+    ex["copy_gbs"] = round(16 * n / (float(np.median(per)) / 1000) / 1e9, 1)
+    log(f"triad {ex['triad_gbs']} GB/s copy {ex['copy_gbs']} GB/s")
+    del a, b, c
+    # multi-RHS on the 2D Laplacian (256^2)
+    L = crsgen.laplace2d(256)
+    ML = pkg.CRSMatrix.from_crs(L, device=dev)
+    ML32 = pkg.CRSMatrix(L.n_rows, L.n_cols, L.row_ptr, L.col_idx, L.val.astype(np.float32),
+                         val_dtype=torch.float32, device=dev)
+    spmm = {}
+    for k in (1, 4, 8, 16, 32):
+        Bk = torch.from_numpy(crsgen.uniform_vec(L.n_cols * k, 4).reshape(L.n_cols, k)).to(dev)
+        Ck = torch.empty((L.n_rows, k), dtype=torch.float64, device=dev)
+        per, _ = time_launches(lambda: pkg.spmm_apply(ML.handle, k, Bk, k, pkg.SPMV_F64, Ck, k),
+                               50, 5, stream)
+        t64 = float(np.median(per)) / 1000
+        Bk32 = Bk.float()
+        per, _ = time_launches(lambda: pkg.spmm_apply(ML32.handle, k, Bk32, k, pkg.SPMV_F32, Ck,
+                                                      k), 50, 5, stream)
+        t32 = float(np.median(per)) / 1000
+        spmm[str(k)] = {"fp64_gflops": round(pm.gflops(L.nnz, t64, k), 1),
+                        "mixed_gflops": round(pm.gflops(L.nnz, t32, k), 1)}
+    ex["spmm_laplace2d_256"] = spmm
+    log(f"spmm: {spmm}")
+    return ex
+
+
+def cpu_baseline(A, B):
+    """The oracle (single-threaded plain C) timed on the host: whole-matrix
+    products repeated until about 10 s of CPU time have passed."""
+    import oracle
+    log("cpu baseline: timing the oracle")
+    reps, t = 0, 0.0
+    while t < 10.0 and reps < 50:
+        t0 = time.perf_counter()
+        oracle.spmv(A.n_rows, A.row_ptr, A.col_idx, A.val, B)
+        t += time.perf_counter() - t0
+        reps += 1
+    gf = 2.0 * A.nnz * reps / t / 1e9
+    return {"value": round(gf, 3), "unit": "GFlop/s", "cores": 1, "kind": "oracle",
+            "sample": f"{reps} full products of the same matrix (nnz={A.nnz}), "
+                      f"{t:.1f} s, single thread, includes the |a*b| magnitude sum"}
+
+
+if __name__ == "__main__":
+    main()

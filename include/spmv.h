@@ -144,16 +144,6 @@ int spmv_get_autotune_times(spmv_handle h, double* us);
 int spmv_get_num_blocks(spmv_handle h, int64_t* nblocks);
 int spmv_destroy(spmv_handle h);
 
-/*
- * Split local/remote product (the paper's Sect. 3.1 naive-overlap kernel
- * structure, eq. (2)) on one device: columns [col_lo, col_hi) are "local".
- * pass 0 writes C = A_local * B; pass 1 adds C += A_remote * B, where
- * A_remote are the entries with columns outside [col_lo, col_hi). C is
- * written twice, which is the extra traffic eq. (2) models.
- */
-int spmv_apply_split(spmv_handle h, int pass, int64_t col_lo, int64_t col_hi, const void* B,
-                     int b_dtype, double* C, void* stream);
-
 /* ----------------------------------------------------------- uneven batch */
 
 /*

@@ -1,0 +1,609 @@
+// C ABI of libspmv (declared in include/spmv.h).
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "common.hpp"
+
+namespace spmv {
+
+namespace {
+thread_local std::string g_err;
+
+struct SelectorHost {
+  float mu[SPMV_NUM_FEATURES];
+  float sigma[SPMV_NUM_FEATURES];
+  float lo[SPMV_NUM_FEATURES];
+  float hi[SPMV_NUM_FEATURES];
+  float margin = 0.0f;
+  bool have_norm = false;
+};
+SelectorHost g_sel;
+
+hipStream_t as_stream(void* s) { return static_cast<hipStream_t>(s); }
+
+int dtype_bytes(int dt) { return dt == SPMV_F64 ? 8 : 4; }
+bool dtype_ok(int dt) { return dt == SPMV_F64 || dt == SPMV_F32; }
+
+struct PlanLayout {
+  size_t header = 0, blocks = 0, bins = 0, at_B = 0, at_C = 0, total = 0;
+};
+
+PlanLayout plan_layout(int64_t n_rows, int64_t n_cols, int64_t nnz, uint32_t flags) {
+  PlanLayout L;
+  const int64_t nb = lds_block_count(n_rows, nnz);
+  size_t o = 0;
+  L.header = o;
+  o += kHeaderBytes;
+  L.blocks = o;
+  o += align256(sizeof(int32_t) * (size_t)(nb + 1));
+  L.bins = o;
+  o += align256(sizeof(int32_t) * (size_t)std::max<int64_t>(n_rows, 1));
+  const uint32_t mode = flags & 0xFFu;
+  if (mode == SPMV_SELECT_MLP || mode == SPMV_SELECT_AUTOTUNE) {
+    L.at_B = o;
+    o += align256(8 * (size_t)std::max<int64_t>(n_cols, 1));
+    L.at_C = o;
+    o += align256(8 * (size_t)std::max<int64_t>(n_rows, 1));
+  }
+  L.total = o;
+  return L;
+}
+
+int check_shape(int64_t n_rows, int64_t n_cols, int64_t nnz) {
+  if (n_rows < 0 || n_cols < 0 || nnz < 0) return fail(SPMV_ERR_INVALID_ARG, "negative size");
+  if (nnz > INT32_MAX - 1 || n_rows > INT32_MAX - 1 || n_cols > INT32_MAX)
+    return fail(SPMV_ERR_UNSUPPORTED, "sizes must fit int32 indices (nnz < 2^31)");
+  return SPMV_OK;
+}
+
+int autotune(Plan& p, hipStream_t s) {
+  if (!p.at_B || !p.at_C)
+    return fail(SPMV_ERR_WORKSPACE, "autotune needs the workspace size of an autotune/MLP plan");
+  int st = launch_fill(p.at_B, p.vdt, p.n_cols, 1.0, s);
+  if (st) return st;
+  hipEvent_t e0, e1;
+  SPMV_HIP(hipEventCreate(&e0));
+  SPMV_HIP(hipEventCreate(&e1));
+  constexpr int kReps = 5;
+  for (int v = 0; v < SPMV_NUM_VARIANTS; ++v) {
+    st = launch_spmv(p, v, p.at_B, p.at_C, s);
+    if (st) break;
+    float ms[kReps];
+    for (int r = 0; r < kReps && !st; ++r) {
+      hipEventRecord(e0, s);
+      st = launch_spmv(p, v, p.at_B, p.at_C, s);
+      hipEventRecord(e1, s);
+      if (hipEventSynchronize(e1) != hipSuccess) st = fail(SPMV_ERR_HIP, "event sync");
+      hipEventElapsedTime(&ms[r], e0, e1);
+    }
+    if (st) break;
+    std::sort(ms, ms + kReps);
+    p.at_us[v] = 1000.0 * ms[kReps / 2];
+  }
+  hipEventDestroy(e0);
+  hipEventDestroy(e1);
+  if (st) return st;
+  p.have_autotune = true;
+  p.variant = (int)(std::min_element(p.at_us, p.at_us + SPMV_NUM_VARIANTS) - p.at_us);
+  return SPMV_OK;
+}
+
+bool selector_confident(const Plan& p) {
+  float best = p.pred[0], second = INFINITY;
+  for (int v = 1; v < SPMV_NUM_VARIANTS; ++v) {
+    if (p.pred[v] < best) {
+      second = best;
+      best = p.pred[v];
+    } else if (p.pred[v] < second) {
+      second = p.pred[v];
+    }
+  }
+  if (second - best < g_sel.margin) return false;
+  for (int q = 0; q < SPMV_NUM_FEATURES; ++q)
+    if (p.features[q] < g_sel.lo[q] || p.features[q] > g_sel.hi[q]) return false;
+  return true;
+}
+
+int argmin6(const float* x) {
+  int b = 0;
+  for (int v = 1; v < SPMV_NUM_VARIANTS; ++v)
+    if (x[v] < x[b]) b = v;
+  return b;
+}
+
+}  // namespace
+
+void set_error(const std::string& msg) { g_err = msg; }
+int fail(int status, const std::string& msg) {
+  g_err = msg;
+  return status;
+}
+int hip_fail(hipError_t e, const char* what) {
+  g_err = std::string(what) + ": " + hipGetErrorString(e);
+  return SPMV_ERR_HIP;
+}
+
+}  // namespace spmv
+
+using namespace spmv;
+
+struct spmv_plan {
+  Plan p;
+};
+struct spmv_batch {
+  Batch b;
+};
+struct spmv_graph {
+  hipGraphExec_t exec = nullptr;
+};
+
+extern "C" {
+
+const char* spmv_version(void) { return "1.0.0"; }
+
+const char* spmv_status_string(int status) {
+  switch (status) {
+    case SPMV_OK: return "ok";
+    case SPMV_ERR_INVALID_ARG: return "invalid argument";
+    case SPMV_ERR_BAD_CRS: return "malformed CRS arrays";
+    case SPMV_ERR_UNSUPPORTED: return "unsupported size or dtype";
+    case SPMV_ERR_WORKSPACE: return "workspace missing, too small or misaligned";
+    case SPMV_ERR_HIP: return "HIP runtime error";
+    case SPMV_ERR_STATE: return "invalid state";
+    default: return "unknown status";
+  }
+}
+
+const char* spmv_last_error(void) { return g_err.c_str(); }
+
+int spmv_workspace_size(int64_t n_rows, int64_t n_cols, int64_t nnz, uint32_t flags,
+                        size_t* bytes) {
+  if (!bytes) return fail(SPMV_ERR_INVALID_ARG, "bytes is null");
+  int st = check_shape(n_rows, n_cols, nnz);
+  if (st) return st;
+  *bytes = plan_layout(n_rows, n_cols, nnz, flags).total;
+  return SPMV_OK;
+}
+
+int spmv_create(spmv_handle* h, int64_t n_rows, int64_t n_cols, int64_t nnz,
+                const int32_t* row_ptr, const int32_t* col_idx, const void* val, int val_dtype,
+                void* workspace, size_t ws_bytes, uint32_t flags, void* stream) {
+  if (!h) return fail(SPMV_ERR_INVALID_ARG, "handle pointer is null");
+  *h = nullptr;
+  int st = check_shape(n_rows, n_cols, nnz);
+  if (st) return st;
+  if (!dtype_ok(val_dtype)) return fail(SPMV_ERR_INVALID_ARG, "val_dtype must be SPMV_F64 or SPMV_F32");
+  if (!row_ptr) return fail(SPMV_ERR_INVALID_ARG, "row_ptr is null");
+  if (nnz > 0 && (!col_idx || !val)) return fail(SPMV_ERR_INVALID_ARG, "col_idx or val is null");
+  const uint32_t mode = flags & 0xFFu;
+  const int fixed = (int)((flags >> 8) & 0xFu);
+  if (mode > SPMV_SELECT_FIXED) return fail(SPMV_ERR_INVALID_ARG, "unknown selection mode");
+  if (mode == SPMV_SELECT_FIXED && fixed >= SPMV_NUM_VARIANTS)
+    return fail(SPMV_ERR_INVALID_ARG, "variant out of range");
+  if (flags & ~(0xFFFu | SPMV_FLAG_SKIP_VALIDATE)) return fail(SPMV_ERR_INVALID_ARG, "unknown flag bits");
+  const PlanLayout L = plan_layout(n_rows, n_cols, nnz, flags);
+  if (!workspace) return fail(SPMV_ERR_WORKSPACE, "workspace is null");
+  if (reinterpret_cast<uintptr_t>(workspace) % 256)
+    return fail(SPMV_ERR_WORKSPACE, "workspace must be 256-byte aligned");
+  if (ws_bytes < L.total)
+    return fail(SPMV_ERR_WORKSPACE, "workspace too small: need " + std::to_string(L.total) +
+                                        " bytes, got " + std::to_string(ws_bytes));
+  hipStream_t s = as_stream(stream);
+  auto* H = new (std::nothrow) spmv_plan;
+  if (!H) return fail(SPMV_ERR_INVALID_ARG, "host allocation failed");
+  Plan& p = H->p;
+  p.n_rows = n_rows;
+  p.n_cols = n_cols;
+  p.nnz = nnz;
+  p.row_ptr = row_ptr;
+  p.col_idx = col_idx;
+  p.val = val;
+  p.vdt = val_dtype;
+  p.ws = static_cast<char*>(workspace);
+  p.ws_bytes = ws_bytes;
+  p.hdr = reinterpret_cast<WsHeader*>(p.ws + L.header);
+  p.blocks = reinterpret_cast<int32_t*>(p.ws + L.blocks);
+  p.nblocks = lds_block_count(n_rows, nnz);
+  p.bin_rows = reinterpret_cast<int32_t*>(p.ws + L.bins);
+  if (L.at_B) {
+    p.at_B = p.ws + L.at_B;
+    p.at_C = reinterpret_cast<double*>(p.ws + L.at_C);
+  }
+  hipGetDevice(&p.device);
+
+  const float* theta = selector_theta_device();
+  const bool run_mlp =
+      theta && (mode == SPMV_SELECT_MLP || mode == SPMV_SELECT_DEFAULT) && g_sel.have_norm;
+  WsHeader hh;
+  st = launch_zero_header(p.hdr, s);
+  if (!st && !(flags & SPMV_FLAG_SKIP_VALIDATE)) st = launch_validate(p, s);
+  if (!st) st = launch_analysis(p, run_mlp ? g_sel.mu : nullptr, run_mlp ? g_sel.sigma : nullptr, s);
+  if (!st && run_mlp)
+    st = launch_mlp_forward(theta, p.hdr->x_std, 1, p.hdr->pred, p.hdr->z1, p.hdr->z2, s);
+  if (!st) {
+    hipError_t e = hipMemcpyAsync(&hh, p.hdr, sizeof(WsHeader), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) st = hip_fail(e, "analysis readback");
+  }
+  if (!st && hh.err) {
+    std::string why;
+    if (hh.err & 4) why += " row_ptr[0]!=0;";
+    if (hh.err & 1) why += " row_ptr decreases;";
+    if (hh.err & 8) why += " row_ptr[n_rows]!=nnz;";
+    if (hh.err & 2) why += " col_idx out of [0,n_cols);";
+    st = fail(SPMV_ERR_BAD_CRS, "invalid CRS:" + why);
+  }
+  if (st) {
+    delete H;
+    return st;
+  }
+  std::memcpy(p.features, hh.features, sizeof(p.features));
+  for (int b = 0; b < kNumBins; ++b) {
+    p.bin_count[b] = hh.bin_count[b];
+    p.bin_offset[b] = hh.bin_offset[b];
+  }
+  if (run_mlp) {
+    std::memcpy(p.pred, hh.pred, sizeof(p.pred));
+    p.have_pred = true;
+  }
+  if (mode == SPMV_SELECT_FIXED) {
+    p.variant = fixed;
+  } else if (mode == SPMV_SELECT_AUTOTUNE) {
+    st = autotune(p, s);
+  } else if (mode == SPMV_SELECT_MLP) {
+    if (p.have_pred && selector_confident(p))
+      p.variant = argmin6(p.pred);
+    else
+      st = autotune(p, s);
+  } else {  // default
+    p.variant = p.have_pred ? argmin6(p.pred) : SPMV_V4_LDS_BLOCK;
+  }
+  if (st) {
+    delete H;
+    return st;
+  }
+  *h = H;
+  return SPMV_OK;
+}
+
+int spmv_apply(spmv_handle h, const void* B, int b_dtype, double* C, void* stream) {
+  if (!h) return fail(SPMV_ERR_INVALID_ARG, "handle is null");
+  const Plan& p = h->p;
+  if (b_dtype != p.vdt) return fail(SPMV_ERR_UNSUPPORTED, "b_dtype must equal the plan's val_dtype");
+  if ((!B && p.n_cols > 0 && p.nnz > 0) || (!C && p.n_rows > 0))
+    return fail(SPMV_ERR_INVALID_ARG, "B or C is null");
+  return launch_spmv(p, p.variant, B, C, as_stream(stream));
+}
+
+int spmm_apply(spmv_handle h, int32_t k, const void* B, int64_t ldb, int b_dtype, double* C,
+               int64_t ldc, void* stream) {
+  if (!h) return fail(SPMV_ERR_INVALID_ARG, "handle is null");
+  const Plan& p = h->p;
+  if (k < 1) return fail(SPMV_ERR_INVALID_ARG, "k must be >= 1");
+  if (ldb < k || ldc < k) return fail(SPMV_ERR_INVALID_ARG, "ldb and ldc must be >= k");
+  if (b_dtype != p.vdt) return fail(SPMV_ERR_UNSUPPORTED, "b_dtype must equal the plan's val_dtype");
+  if ((!B && p.n_cols > 0 && p.nnz > 0) || (!C && p.n_rows > 0))
+    return fail(SPMV_ERR_INVALID_ARG, "B or C is null");
+  if ((int64_t)p.n_rows * ldc > INT64_MAX / 2) return fail(SPMV_ERR_UNSUPPORTED, "C too large");
+  return launch_spmm(p, k, B, ldb, C, ldc, as_stream(stream));
+}
+
+int spmv_get_variant(spmv_handle h, int* variant) {
+  if (!h || !variant) return fail(SPMV_ERR_INVALID_ARG, "null argument");
+  *variant = h->p.variant;
+  return SPMV_OK;
+}
+
+int spmv_set_variant(spmv_handle h, int variant) {
+  if (!h) return fail(SPMV_ERR_INVALID_ARG, "handle is null");
+  if (variant < 0 || variant >= SPMV_NUM_VARIANTS) return fail(SPMV_ERR_INVALID_ARG, "variant out of range");
+  h->p.variant = variant;
+  return SPMV_OK;
+}
+
+int spmv_get_features(spmv_handle h, double* f) {
+  if (!h || !f) return fail(SPMV_ERR_INVALID_ARG, "null argument");
+  std::memcpy(f, h->p.features, sizeof(h->p.features));
+  return SPMV_OK;
+}
+
+int spmv_get_predictions(spmv_handle h, float* pred) {
+  if (!h || !pred) return fail(SPMV_ERR_INVALID_ARG, "null argument");
+  if (!h->p.have_pred) return fail(SPMV_ERR_STATE, "the selector did not run for this plan");
+  std::memcpy(pred, h->p.pred, sizeof(h->p.pred));
+  return SPMV_OK;
+}
+
+int spmv_get_autotune_times(spmv_handle h, double* us) {
+  if (!h || !us) return fail(SPMV_ERR_INVALID_ARG, "null argument");
+  if (!h->p.have_autotune) return fail(SPMV_ERR_STATE, "autotune did not run for this plan");
+  std::memcpy(us, h->p.at_us, sizeof(h->p.at_us));
+  return SPMV_OK;
+}
+
+int spmv_get_num_blocks(spmv_handle h, int64_t* nblocks) {
+  if (!h || !nblocks) return fail(SPMV_ERR_INVALID_ARG, "null argument");
+  *nblocks = h->p.nblocks;
+  return SPMV_OK;
+}
+
+int spmv_destroy(spmv_handle h) {
+  delete h;
+  return SPMV_OK;
+}
+
+// ------------------------------------------------------------------ batch
+
+namespace {
+struct BatchLayout {
+  size_t err = 0, tiles = 0, toff = 0, nr = 0, nc = 0, nz = 0, total = 0;
+};
+BatchLayout batch_layout(int32_t count, int64_t max_tiles) {
+  BatchLayout L;
+  size_t o = 0;
+  L.err = o;
+  o += 256;
+  L.tiles = o;
+  o += align256(sizeof(int32_t) * 3 * (size_t)std::max<int64_t>(max_tiles, 1));
+  L.toff = o;
+  o += align256(sizeof(int64_t) * (size_t)(count + 1));
+  L.nr = o;
+  o += align256(sizeof(int64_t) * (size_t)count);
+  L.nc = o;
+  o += align256(sizeof(int64_t) * (size_t)count);
+  L.nz = o;
+  o += align256(sizeof(int64_t) * (size_t)count);
+  L.total = o;
+  return L;
+}
+__global__ void k_batch_err_init(int32_t* e) {
+  e[0] = 0;
+  e[1] = INT32_MAX;
+}
+}  // namespace
+
+int spmv_batch_workspace_size(int32_t count, int64_t total_rows, int64_t total_nnz,
+                              size_t* bytes) {
+  if (!bytes) return fail(SPMV_ERR_INVALID_ARG, "bytes is null");
+  if (count < 1 || total_rows < 0 || total_nnz < 0)
+    return fail(SPMV_ERR_INVALID_ARG, "count must be >= 1 and totals >= 0");
+  const int64_t max_tiles = (total_nnz + total_rows) / kBlockBudget + count;
+  *bytes = batch_layout(count, max_tiles).total;
+  return SPMV_OK;
+}
+
+int spmv_batch_create(spmv_batch_handle* h, int32_t count, const int64_t* n_rows,
+                      const int64_t* n_cols, const int64_t* nnz, const int32_t* const* row_ptrs,
+                      const int32_t* const* col_idxs, const void* const* vals, int val_dtype,
+                      void* workspace, size_t ws_bytes, void* stream) {
+  if (!h) return fail(SPMV_ERR_INVALID_ARG, "handle pointer is null");
+  *h = nullptr;
+  if (count < 1 || !n_rows || !n_cols || !nnz || !row_ptrs || !col_idxs || !vals)
+    return fail(SPMV_ERR_INVALID_ARG, "null array or count < 1");
+  if (!dtype_ok(val_dtype)) return fail(SPMV_ERR_INVALID_ARG, "bad val_dtype");
+  std::vector<int64_t> toff((size_t)count + 1, 0);
+  for (int32_t m = 0; m < count; ++m) {
+    int st = check_shape(n_rows[m], n_cols[m], nnz[m]);
+    if (st) return fail(st, "matrix " + std::to_string(m) + ": " + spmv_last_error());
+    toff[m + 1] = toff[m] + lds_block_count(n_rows[m], nnz[m]);
+  }
+  const int64_t ntiles = toff[count];
+  if (ntiles > INT32_MAX) return fail(SPMV_ERR_UNSUPPORTED, "too many tiles");
+  const BatchLayout L = batch_layout(count, ntiles);
+  if (!workspace || reinterpret_cast<uintptr_t>(workspace) % 256)
+    return fail(SPMV_ERR_WORKSPACE, "workspace null or not 256-byte aligned");
+  if (ws_bytes < L.total)
+    return fail(SPMV_ERR_WORKSPACE, "workspace too small: need " + std::to_string(L.total));
+  hipStream_t s = as_stream(stream);
+  char* ws = static_cast<char*>(workspace);
+  auto* H = new (std::nothrow) spmv_batch;
+  if (!H) return fail(SPMV_ERR_INVALID_ARG, "host allocation failed");
+  Batch& b = H->b;
+  b.count = count;
+  b.vdt = val_dtype;
+  b.row_ptrs = row_ptrs;
+  b.col_idxs = col_idxs;
+  b.vals = vals;
+  b.tiles = reinterpret_cast<int32_t*>(ws + L.tiles);
+  b.ntiles = ntiles;
+  b.err = reinterpret_cast<int32_t*>(ws + L.err);
+  int dev = 0;
+  hipGetDevice(&dev);
+  b.grid = batch_grid(dev);
+  b.tile_offset_host = new int64_t[(size_t)count + 1];
+  std::memcpy(b.tile_offset_host, toff.data(), sizeof(int64_t) * ((size_t)count + 1));
+  b.rp_host = new const int32_t*[(size_t)count];
+  b.ci_host = new const int32_t*[(size_t)count];
+  b.val_host = new const void*[(size_t)count];
+  int64_t* d_toff = reinterpret_cast<int64_t*>(ws + L.toff);
+  int64_t* d_nr = reinterpret_cast<int64_t*>(ws + L.nr);
+  int64_t* d_nc = reinterpret_cast<int64_t*>(ws + L.nc);
+  int64_t* d_nz = reinterpret_cast<int64_t*>(ws + L.nz);
+  int st = SPMV_OK;
+  hipError_t e = hipMemcpyAsync(d_toff, toff.data(), sizeof(int64_t) * (count + 1),
+                                hipMemcpyHostToDevice, s);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(d_nr, n_rows, sizeof(int64_t) * count, hipMemcpyHostToDevice, s);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(d_nc, n_cols, sizeof(int64_t) * count, hipMemcpyHostToDevice, s);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(d_nz, nnz, sizeof(int64_t) * count, hipMemcpyHostToDevice, s);
+  if (e != hipSuccess) st = hip_fail(e, "batch upload");
+  if (!st) {
+    k_batch_err_init<<<1, 1, 0, s>>>(b.err);
+    e = hipGetLastError();
+    if (e != hipSuccess) st = hip_fail(e, "batch init");
+  }
+  if (!st) st = launch_batch_build(b, d_toff, d_nr, d_nc, d_nz, s);
+  int32_t herr[2] = {0, 0};
+  if (!st) {
+    e = hipMemcpyAsync(herr, b.err, sizeof(herr), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess)
+      e = hipMemcpyAsync(b.rp_host, row_ptrs, sizeof(void*) * count, hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess)
+      e = hipMemcpyAsync(b.ci_host, col_idxs, sizeof(void*) * count, hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess)
+      e = hipMemcpyAsync(b.val_host, vals, sizeof(void*) * count, hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) st = hip_fail(e, "batch readback");
+  }
+  if (!st && herr[0])
+    st = fail(SPMV_ERR_BAD_CRS, "invalid CRS in batch matrix " + std::to_string(herr[1]));
+  if (st) {
+    spmv_batch_destroy(H);
+    return st;
+  }
+  *h = H;
+  return SPMV_OK;
+}
+
+int spmv_batch_apply(spmv_batch_handle h, const void* const* Bs, double* const* Cs,
+                     int b_dtype, void* stream) {
+  if (!h || !Bs || !Cs) return fail(SPMV_ERR_INVALID_ARG, "null argument");
+  if (b_dtype != h->b.vdt) return fail(SPMV_ERR_UNSUPPORTED, "b_dtype must equal val_dtype");
+  return launch_batch_apply(h->b, 0, h->b.ntiles, Bs, Cs, nullptr, nullptr, as_stream(stream));
+}
+
+int spmv_batch_apply_each(spmv_batch_handle h, const void* const* Bs_host,
+                          double* const* Cs_host, int b_dtype, void* stream) {
+  if (!h || !Bs_host || !Cs_host) return fail(SPMV_ERR_INVALID_ARG, "null argument");
+  const Batch& b = h->b;
+  if (b_dtype != b.vdt) return fail(SPMV_ERR_UNSUPPORTED, "b_dtype must equal val_dtype");
+  for (int32_t m = 0; m < b.count; ++m) {
+    int st = launch_batch_apply(b, b.tile_offset_host[m], b.tile_offset_host[m + 1], nullptr,
+                                nullptr, Bs_host[m], Cs_host[m], as_stream(stream));
+    if (st) return st;
+  }
+  return SPMV_OK;
+}
+
+int spmv_batch_get_num_tiles(spmv_batch_handle h, int64_t* ntiles) {
+  if (!h || !ntiles) return fail(SPMV_ERR_INVALID_ARG, "null argument");
+  *ntiles = h->b.ntiles;
+  return SPMV_OK;
+}
+
+int spmv_batch_destroy(spmv_batch_handle h) {
+  if (!h) return SPMV_OK;
+  delete[] h->b.tile_offset_host;
+  delete[] h->b.rp_host;
+  delete[] h->b.ci_host;
+  delete[] h->b.val_host;
+  delete h;
+  return SPMV_OK;
+}
+
+// ------------------------------------------------------------------ graphs
+
+int spmv_graph_begin(void* stream) {
+  if (!stream) return fail(SPMV_ERR_INVALID_ARG, "graph capture needs a non-null stream");
+  SPMV_HIP(hipStreamBeginCapture(as_stream(stream), hipStreamCaptureModeThreadLocal));
+  return SPMV_OK;
+}
+
+int spmv_graph_end(void* stream, spmv_graph_handle* g) {
+  if (!stream || !g) return fail(SPMV_ERR_INVALID_ARG, "null argument");
+  *g = nullptr;
+  hipGraph_t graph = nullptr;
+  SPMV_HIP(hipStreamEndCapture(as_stream(stream), &graph));
+  hipGraphExec_t exec = nullptr;
+  hipError_t e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+  hipGraphDestroy(graph);
+  if (e != hipSuccess) return hip_fail(e, "hipGraphInstantiate");
+  auto* G = new (std::nothrow) spmv_graph;
+  if (!G) {
+    hipGraphExecDestroy(exec);
+    return fail(SPMV_ERR_INVALID_ARG, "host allocation failed");
+  }
+  G->exec = exec;
+  *g = G;
+  return SPMV_OK;
+}
+
+int spmv_graph_launch(spmv_graph_handle g, void* stream) {
+  if (!g) return fail(SPMV_ERR_INVALID_ARG, "graph is null");
+  SPMV_HIP(hipGraphLaunch(g->exec, as_stream(stream)));
+  return SPMV_OK;
+}
+
+int spmv_graph_destroy(spmv_graph_handle g) {
+  if (!g) return SPMV_OK;
+  hipGraphExecDestroy(g->exec);
+  delete g;
+  return SPMV_OK;
+}
+
+// ---------------------------------------------------------------- selector
+
+int spmv_selector_load(const float* params, const float* mu, const float* sigma,
+                       const float* lo, const float* hi, float margin) {
+  if (!params || !mu || !sigma || !lo || !hi) return fail(SPMV_ERR_INVALID_ARG, "null argument");
+  for (int q = 0; q < SPMV_NUM_FEATURES; ++q)
+    if (!(sigma[q] > 0.0f) || !std::isfinite(mu[q]) || lo[q] > hi[q])
+      return fail(SPMV_ERR_INVALID_ARG, "bad standardisation or range");
+  for (int i = 0; i < SPMV_MLP_PARAMS; ++i)
+    if (!std::isfinite(params[i])) return fail(SPMV_ERR_INVALID_ARG, "non-finite weight");
+  int st = selector_upload(params);
+  if (st) return st;
+  std::memcpy(g_sel.mu, mu, sizeof(g_sel.mu));
+  std::memcpy(g_sel.sigma, sigma, sizeof(g_sel.sigma));
+  std::memcpy(g_sel.lo, lo, sizeof(g_sel.lo));
+  std::memcpy(g_sel.hi, hi, sizeof(g_sel.hi));
+  g_sel.margin = margin;
+  g_sel.have_norm = true;
+  return SPMV_OK;
+}
+
+int spmv_selector_loaded(int* loaded) {
+  if (!loaded) return fail(SPMV_ERR_INVALID_ARG, "null argument");
+  *loaded = (selector_theta_device() != nullptr && g_sel.have_norm) ? 1 : 0;
+  return SPMV_OK;
+}
+
+int spmv_mlp_forward(const float* theta, const float* X, int32_t nb, float* Y, float* Z1,
+                     float* Z2, void* stream) {
+  if (nb < 0) return fail(SPMV_ERR_INVALID_ARG, "nb < 0");
+  if (nb > 0 && (!theta || !X || !Y || !Z1 || !Z2)) return fail(SPMV_ERR_INVALID_ARG, "null argument");
+  return launch_mlp_forward(theta, X, nb, Y, Z1, Z2, as_stream(stream));
+}
+
+int spmv_mlp_backward(const float* theta, const float* X, const float* Z1, const float* Z2,
+                      const float* Y, const float* T, int32_t nb, float* dz_scratch,
+                      float* grad, void* stream) {
+  if (nb < 0) return fail(SPMV_ERR_INVALID_ARG, "nb < 0");
+  if (nb > 0 && (!theta || !X || !Z1 || !Z2 || !Y || !T || !dz_scratch || !grad))
+    return fail(SPMV_ERR_INVALID_ARG, "null argument");
+  return launch_mlp_backward(theta, X, Z1, Z2, Y, T, nb, dz_scratch, grad, as_stream(stream));
+}
+
+int spmv_mlp_adam(float* theta, const float* grad, float* m, float* v, int32_t t, float lr,
+                  float beta1, float beta2, float eps, void* stream) {
+  if (!theta || !grad || !m || !v) return fail(SPMV_ERR_INVALID_ARG, "null argument");
+  if (t < 1) return fail(SPMV_ERR_INVALID_ARG, "t must be >= 1");
+  return launch_mlp_adam(theta, grad, m, v, t, lr, beta1, beta2, eps, as_stream(stream));
+}
+
+// ------------------------------------------------------------- measurement
+
+int spmv_stream_triad(double* a, const double* b, const double* c, double s, int64_t n,
+                      void* stream) {
+  if (n < 0) return fail(SPMV_ERR_INVALID_ARG, "n < 0");
+  if (n > 0 && (!a || !b || !c)) return fail(SPMV_ERR_INVALID_ARG, "null argument");
+  if ((reinterpret_cast<uintptr_t>(a) | reinterpret_cast<uintptr_t>(b) |
+       reinterpret_cast<uintptr_t>(c)) % 16)
+    return fail(SPMV_ERR_INVALID_ARG, "arrays must be 16-byte aligned");
+  return launch_triad(a, b, c, s, n, as_stream(stream));
+}
+
+int spmv_stream_copy(double* dst, const double* src, int64_t n, void* stream) {
+  if (n < 0) return fail(SPMV_ERR_INVALID_ARG, "n < 0");
+  if (n > 0 && (!dst || !src)) return fail(SPMV_ERR_INVALID_ARG, "null argument");
+  if ((reinterpret_cast<uintptr_t>(dst) | reinterpret_cast<uintptr_t>(src)) % 16)
+    return fail(SPMV_ERR_INVALID_ARG, "arrays must be 16-byte aligned");
+  return launch_copy(dst, src, n, as_stream(stream));
+}
+
+}  // extern "C"

@@ -1,0 +1,137 @@
+// Internal declarations shared by the translation units of libspmv.
+// gfx950 (CDNA4) only: 64-lane wavefronts, DPP row operations on 16-lane rows.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+#include <string>
+
+#include "../../include/spmv.h"
+
+namespace spmv {
+
+// ---------------------------------------------------------------- constants
+
+constexpr int kWG = 256;          // threads per workgroup for the streaming kernels
+constexpr int kBlockBudget = 2048;  // rows + in-chunk nonzeros of one LDS row block
+constexpr int kNumXCD = 8;        // MI355X: 8 accelerator complex dies, one L2 each
+constexpr int kNumBins = 5;       // row-length bins of the binned variant
+constexpr int kCounters = 32;     // u64 analysis counters in the workspace header
+
+// Workspace header (first kHeaderBytes of every plan workspace).
+struct alignas(256) WsHeader {
+  int32_t err;                 // CRS violation bits (validate)
+  int32_t pad0[15];
+  unsigned long long cnt[kCounters];  // analysis counters (stats)
+  double features[SPMV_NUM_FEATURES];
+  float x_std[SPMV_NUM_FEATURES];      // standardised selector input
+  float pred[8];                       // selector output (6 used)
+  float z1[64], z2[64];                // selector forward scratch
+  int32_t bin_count[8];
+  int32_t bin_offset[8];
+  int32_t bin_cursor[8];
+};
+constexpr size_t kHeaderBytes = (sizeof(WsHeader) + 255) / 256 * 256;
+
+// Counter slots inside WsHeader::cnt
+enum : int {
+  C_SUMSQ = 0, C_LMAX = 1, C_LMIN = 2, C_BIN0 = 3,  // feature bins C_BIN0..C_BIN0+5
+  C_LONGNNZ = 9, C_DISTLOG = 10, C_NEAR = 11, C_NNZ = 12
+};
+
+// ---------------------------------------------------------------- plan
+
+struct Plan {
+  int64_t n_rows = 0, n_cols = 0, nnz = 0;
+  const int32_t* row_ptr = nullptr;
+  const int32_t* col_idx = nullptr;
+  const void* val = nullptr;
+  int vdt = SPMV_F64;
+  char* ws = nullptr;
+  size_t ws_bytes = 0;
+  WsHeader* hdr = nullptr;        // device
+  int32_t* blocks = nullptr;      // device int32[nblocks+1]
+  int64_t nblocks = 0;
+  int32_t* bin_rows = nullptr;    // device int32[n_rows]
+  int32_t bin_count[kNumBins] = {0, 0, 0, 0, 0};
+  int32_t bin_offset[kNumBins] = {0, 0, 0, 0, 0};
+  void* at_B = nullptr;           // autotune scratch (device) or null
+  double* at_C = nullptr;
+  int variant = SPMV_V4_LDS_BLOCK;
+  double features[SPMV_NUM_FEATURES] = {};
+  float pred[6] = {};
+  bool have_pred = false;
+  double at_us[6] = {};
+  bool have_autotune = false;
+  int device = 0;
+};
+
+struct Batch {
+  int32_t count = 0;
+  int vdt = SPMV_F64;
+  const int32_t* const* row_ptrs = nullptr;  // device arrays of device pointers
+  const int32_t* const* col_idxs = nullptr;
+  const void* const* vals = nullptr;
+  int32_t* tiles = nullptr;   // device int32[3 * ntiles]: matrix, row begin, row end
+  int64_t ntiles = 0;
+  int32_t* err = nullptr;     // device
+  int64_t* tile_offset_host = nullptr;  // host [count+1]
+  const int32_t** rp_host = nullptr;    // host copies of the device pointer arrays
+  const int32_t** ci_host = nullptr;
+  const void** val_host = nullptr;
+  int grid = 0;
+};
+
+// ---------------------------------------------------------------- errors
+
+void set_error(const std::string& msg);
+int fail(int status, const std::string& msg);
+int hip_fail(hipError_t e, const char* what);
+
+#define SPMV_HIP(call)                                  \
+  do {                                                  \
+    hipError_t e_ = (call);                             \
+    if (e_ != hipSuccess) return spmv::hip_fail(e_, #call); \
+  } while (0)
+
+inline size_t align256(size_t x) { return (x + 255) / 256 * 256; }
+
+inline int64_t lds_block_count(int64_t n_rows, int64_t nnz) {
+  if (n_rows <= 0) return 0;
+  return (nnz + n_rows + kBlockBudget - 1) / kBlockBudget;
+}
+
+// ---------------------------------------------------------------- launchers
+// analysis.hip
+int launch_zero_header(WsHeader* h, hipStream_t s);
+int launch_validate(const Plan& p, hipStream_t s);
+int launch_analysis(Plan& p, const float* mu, const float* sigma, hipStream_t s);
+// spmv_kernels.hip
+int launch_spmv(const Plan& p, int variant, const void* B, double* C, hipStream_t s);
+int launch_spmm(const Plan& p, int k, const void* B, int64_t ldb, double* C, int64_t ldc,
+                hipStream_t s);
+int launch_fill(void* dst, int dtype, int64_t n, double value, hipStream_t s);
+// batch.hip
+int launch_batch_build(Batch& b, const int64_t* tile_offset_dev, const int64_t* n_rows_dev,
+                       const int64_t* n_cols_dev, const int64_t* nnz_dev, hipStream_t s);
+int launch_batch_apply(const Batch& b, int64_t t0, int64_t t1, const void* const* Bs,
+                       double* const* Cs, const void* B1, double* C1, hipStream_t s);
+int batch_grid(int device);
+// mlp.hip
+int launch_mlp_forward(const float* theta, const float* X, int nb, float* Y, float* Z1,
+                       float* Z2, hipStream_t s);
+int launch_mlp_backward(const float* theta, const float* X, const float* Z1, const float* Z2,
+                        const float* Y, const float* T, int nb, float* scratch, float* grad,
+                        hipStream_t s);
+int launch_mlp_adam(float* theta, const float* grad, float* m, float* v, int t, float lr,
+                    float b1, float b2, float eps, hipStream_t s);
+int selector_upload(const float* params);
+const float* selector_theta_device();  // null if not loaded on the current device
+// stream.hip
+int launch_triad(double* a, const double* b, const double* c, double s, int64_t n,
+                 hipStream_t st);
+int launch_copy(double* dst, const double* src, int64_t n, hipStream_t st);
+
+}  // namespace spmv

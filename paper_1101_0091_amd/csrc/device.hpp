@@ -1,0 +1,189 @@
+// Device-side building blocks: lane-group reductions with DPP, the XCD-aware
+// workgroup remap, streaming loads, and the LDS row-block product that both
+// the single-matrix and the batched kernels use.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "common.hpp"
+
+namespace spmv {
+namespace dev {
+
+// ------------------------------------------------------------ reductions
+// DPP controls of the GCN/CDNA data-parallel-primitive word (gfx9 family).
+constexpr int kQuadXor1 = 0xB1;     // quad_perm [1,0,3,2]
+constexpr int kQuadXor2 = 0x4E;     // quad_perm [2,3,0,1]
+constexpr int kRowHalfMirror = 0x141;
+constexpr int kRowMirror = 0x140;
+
+template <int CTRL>
+__device__ __forceinline__ double dpp(double x) {
+  uint64_t u = __builtin_bit_cast(uint64_t, x);
+  int lo = __builtin_amdgcn_update_dpp(0, (int)(uint32_t)u, CTRL, 0xF, 0xF, false);
+  int hi = __builtin_amdgcn_update_dpp(0, (int)(uint32_t)(u >> 32), CTRL, 0xF, 0xF, false);
+  return __builtin_bit_cast(double, ((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo);
+}
+
+__device__ __forceinline__ double swz_xor16(double x) {
+  // ds_swizzle bit-mask mode inside 32-lane halves: and 0x1F, or 0, xor 0x10
+  uint64_t u = __builtin_bit_cast(uint64_t, x);
+  int lo = __builtin_amdgcn_ds_swizzle((int)(uint32_t)u, 0x401F);
+  int hi = __builtin_amdgcn_ds_swizzle((int)(uint32_t)(u >> 32), 0x401F);
+  return __builtin_bit_cast(double, ((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo);
+}
+
+__device__ __forceinline__ double perm_xor32(double x) {
+  int addr = (int)((__lane_id() ^ 32u) << 2);
+  uint64_t u = __builtin_bit_cast(uint64_t, x);
+  int lo = __builtin_amdgcn_ds_bpermute(addr, (int)(uint32_t)u);
+  int hi = __builtin_amdgcn_ds_bpermute(addr, (int)(uint32_t)(u >> 32));
+  return __builtin_bit_cast(double, ((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo);
+}
+
+// Sum over an aligned group of G lanes (G a power of two <= 64). Each step
+// adds the value of the partner lane l^s; IEEE addition is commutative, so
+// every lane of the group ends with the same bits (deterministic).
+template <int G>
+__device__ __forceinline__ double group_sum(double x) {
+  if constexpr (G >= 2) x += dpp<kQuadXor1>(x);
+  if constexpr (G >= 4) x += dpp<kQuadXor2>(x);
+  if constexpr (G >= 8) x += dpp<kRowHalfMirror>(x);
+  if constexpr (G >= 16) x += dpp<kRowMirror>(x);
+  if constexpr (G >= 32) x += swz_xor16(x);
+  if constexpr (G >= 64) x += perm_xor32(x);
+  return x;
+}
+
+// ------------------------------------------------------------ loads
+template <typename T>
+__device__ __forceinline__ T ld_stream(const T* p) {
+  return __builtin_nontemporal_load(p);
+}
+
+template <typename T>
+__device__ __forceinline__ double widen(T x) {
+  return (double)x;
+}
+
+// ------------------------------------------------------------ XCD remap
+// Workgroups are dispatched round-robin over the 8 XCDs (w -> XCD w % 8).
+// Map them so that each XCD walks one contiguous range of tiles, which keeps
+// the B entries a tile range gathers inside one L2.
+__device__ __forceinline__ int64_t xcd_remap(int64_t w, int64_t n) {
+  int64_t x = w % kNumXCD, k = w / kNumXCD;
+  int64_t q = n / kNumXCD, r = n % kNumXCD;
+  return x * q + (x < r ? x : r) + k;
+}
+
+// ------------------------------------------------------------ LDS row block
+// One workgroup multiplies rows [r0, r1) of a CRS matrix. The rows were cut
+// so that (rows + nonzeros) of the block stay within kBlockBudget, hence all
+// rows but the last lie inside the chunk [S, S + kBlockBudget) of the
+// val/col_idx streams, S = row_ptr[r0]. Phase 1 streams that chunk with
+// coalesced loads and stores the products in LDS; phase 2 reduces each row
+// with a lane group whose width G adapts to the rows per block; phase 3
+// streams the remainder of the last row (a row longer than the budget) with
+// the whole workgroup.
+struct BlockLds {
+  double prod[kBlockBudget];
+  double wsum[kWG / 64];
+  double last_part;
+};
+
+template <int G>
+__device__ __forceinline__ void block_rows(const BlockLds& L, const int32_t* __restrict__ rp,
+                                           int32_t r0, int32_t r1, int32_t S, int32_t cend,
+                                           bool tail, double* __restrict__ C,
+                                           double* last_part) {
+  const int tid = threadIdx.x;
+  const int lane = tid & (G - 1);
+  const int group = tid / G;
+  constexpr int ngroups = kWG / G;
+  for (int32_t r = r0 + group; r < r1; r += ngroups) {
+    const int32_t a = rp[r] - S;
+    int32_t z = rp[r + 1];
+    z = (z < cend ? z : cend) - S;
+    double part = 0.0;
+    for (int32_t k = a + lane; k < z; k += G) part += L.prod[k];
+    const double sum = group_sum<G>(part);
+    if (lane == 0) {
+      if (tail && r == r1 - 1)
+        *last_part = sum;
+      else
+        C[r] = sum;
+    }
+  }
+}
+
+template <typename VT, typename BT>
+__device__ __forceinline__ void lds_block(BlockLds& L, const int32_t* __restrict__ rp,
+                                          const int32_t* __restrict__ ci,
+                                          const VT* __restrict__ val, const BT* __restrict__ B,
+                                          double* __restrict__ C, int32_t r0, int32_t r1) {
+  const int tid = threadIdx.x;
+  const int32_t S = rp[r0];
+  const int32_t E = rp[r1];
+  const int32_t cend = (E - S > kBlockBudget) ? S + kBlockBudget : E;
+  const int32_t nin = cend - S;
+  const bool tail = E > cend;
+
+  // phase 1: products of the chunk into LDS; all loads issued before use
+  constexpr int kPer = kBlockBudget / kWG;
+  VT v[kPer];
+  int32_t c[kPer];
+#pragma unroll
+  for (int u = 0; u < kPer; ++u) {
+    const int k = tid + u * kWG;
+    if (k < nin) {
+      v[u] = ld_stream(val + S + k);
+      c[u] = ld_stream(ci + S + k);
+    }
+  }
+  BT b[kPer];
+#pragma unroll
+  for (int u = 0; u < kPer; ++u) {
+    const int k = tid + u * kWG;
+    if (k < nin) b[u] = B[c[u]];
+  }
+#pragma unroll
+  for (int u = 0; u < kPer; ++u) {
+    const int k = tid + u * kWG;
+    if (k < nin) L.prod[k] = widen(v[u]) * widen(b[u]);
+  }
+  __syncthreads();
+
+  // phase 2: lane groups of width G reduce rows from LDS
+  const int32_t nrows = r1 - r0;
+  if (nrows * 64 <= kWG)
+    block_rows<64>(L, rp, r0, r1, S, cend, tail, C, &L.last_part);
+  else if (nrows * 32 <= kWG)
+    block_rows<32>(L, rp, r0, r1, S, cend, tail, C, &L.last_part);
+  else if (nrows * 16 <= kWG)
+    block_rows<16>(L, rp, r0, r1, S, cend, tail, C, &L.last_part);
+  else if (nrows * 8 <= kWG)
+    block_rows<8>(L, rp, r0, r1, S, cend, tail, C, &L.last_part);
+  else if (nrows * 4 <= kWG)
+    block_rows<4>(L, rp, r0, r1, S, cend, tail, C, &L.last_part);
+  else if (nrows * 2 <= kWG)
+    block_rows<2>(L, rp, r0, r1, S, cend, tail, C, &L.last_part);
+  else
+    block_rows<1>(L, rp, r0, r1, S, cend, tail, C, &L.last_part);
+
+  // phase 3: remainder of a long last row, streamed by the whole workgroup
+  if (tail) {
+    double part = 0.0;
+    for (int32_t j = cend + tid; j < E; j += kWG)
+      part = fma(widen(ld_stream(val + j)), widen(B[ld_stream(ci + j)]), part);
+    part = group_sum<64>(part);
+    if ((tid & 63) == 0) L.wsum[tid >> 6] = part;
+    __syncthreads();
+    if (tid == 0)
+      C[r1 - 1] = L.last_part + ((L.wsum[0] + L.wsum[1]) + (L.wsum[2] + L.wsum[3]));
+  }
+}
+
+}  // namespace dev
+}  // namespace spmv

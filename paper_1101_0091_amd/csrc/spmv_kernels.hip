@@ -1,0 +1,325 @@
+// CRS product kernels: variants V0..V5 and the multi-RHS form.
+//
+// All compute C(i) = sum_j val(j) * B(col_idx(j)) (the paper's Sect. 1.2
+// loop) with float64 accumulation; they differ only in how rows and nonzeros
+// are mapped onto lanes. Each output element is reduced by one lane group in
+// an order fixed by the matrix structure, so results are reproducible.
+#include "common.hpp"
+#include "device.hpp"
+
+namespace spmv {
+namespace {
+
+using dev::group_sum;
+using dev::ld_stream;
+using dev::widen;
+
+// ---------------------------------------------------------------- V0
+// One lane per row. LIST: rows come from a row list (binned variant).
+template <typename VT, typename BT, bool LIST>
+__global__ __launch_bounds__(kWG) void k_thread_row(int32_t nrows, const int32_t* __restrict__ list,
+                                                    const int32_t* __restrict__ rp,
+                                                    const int32_t* __restrict__ ci,
+                                                    const VT* __restrict__ val,
+                                                    const BT* __restrict__ B,
+                                                    double* __restrict__ C) {
+  const int64_t t = (int64_t)blockIdx.x * kWG + threadIdx.x;
+  if (t >= nrows) return;
+  const int32_t r = LIST ? list[t] : (int32_t)t;
+  const int32_t s = rp[r], e = rp[r + 1];
+  double acc = 0.0;
+  int32_t j = s;
+  for (; j + 4 <= e; j += 4) {
+    VT v0 = ld_stream(val + j), v1 = ld_stream(val + j + 1), v2 = ld_stream(val + j + 2),
+       v3 = ld_stream(val + j + 3);
+    int32_t c0 = ld_stream(ci + j), c1 = ld_stream(ci + j + 1), c2 = ld_stream(ci + j + 2),
+            c3 = ld_stream(ci + j + 3);
+    BT b0 = B[c0], b1 = B[c1], b2 = B[c2], b3 = B[c3];
+    acc = fma(widen(v0), widen(b0), acc);
+    acc = fma(widen(v1), widen(b1), acc);
+    acc = fma(widen(v2), widen(b2), acc);
+    acc = fma(widen(v3), widen(b3), acc);
+  }
+  for (; j < e; ++j) acc = fma(widen(ld_stream(val + j)), widen(B[ld_stream(ci + j)]), acc);
+  C[r] = acc;
+}
+
+// ---------------------------------------------------------------- V1/V2/V3
+// G lanes per row (4, 16 or 64): lane l takes nonzeros s+l, s+l+G, ...;
+// coalesced segments of the val/col_idx streams; DPP reduction.
+template <typename VT, typename BT, int G, bool LIST>
+__global__ __launch_bounds__(kWG) void k_group_row(int32_t nrows, const int32_t* __restrict__ list,
+                                                   const int32_t* __restrict__ rp,
+                                                   const int32_t* __restrict__ ci,
+                                                   const VT* __restrict__ val,
+                                                   const BT* __restrict__ B,
+                                                   double* __restrict__ C) {
+  const int64_t g = ((int64_t)blockIdx.x * kWG + threadIdx.x) / G;
+  const int lane = threadIdx.x & (G - 1);
+  if (g >= nrows) return;  // whole groups leave together
+  const int32_t r = LIST ? list[g] : (int32_t)g;
+  const int32_t s = rp[r], e = rp[r + 1];
+  double part = 0.0;
+  int32_t j = s + lane;
+  for (; j + G < e; j += 2 * G) {
+    VT v0 = ld_stream(val + j), v1 = ld_stream(val + j + G);
+    int32_t c0 = ld_stream(ci + j), c1 = ld_stream(ci + j + G);
+    BT b0 = B[c0], b1 = B[c1];
+    part = fma(widen(v0), widen(b0), part);
+    part = fma(widen(v1), widen(b1), part);
+  }
+  if (j < e) part = fma(widen(ld_stream(val + j)), widen(B[ld_stream(ci + j)]), part);
+  const double sum = group_sum<G>(part);
+  if (lane == 0) C[r] = sum;
+}
+
+// Whole workgroup per row (very long rows of the binned variant).
+template <typename VT, typename BT>
+__global__ __launch_bounds__(kWG) void k_block_row(int32_t nrows, const int32_t* __restrict__ list,
+                                                   const int32_t* __restrict__ rp,
+                                                   const int32_t* __restrict__ ci,
+                                                   const VT* __restrict__ val,
+                                                   const BT* __restrict__ B,
+                                                   double* __restrict__ C) {
+  __shared__ double wsum[kWG / 64];
+  const int32_t r = list[blockIdx.x];
+  const int32_t s = rp[r], e = rp[r + 1];
+  double part = 0.0;
+  for (int32_t j = s + threadIdx.x; j < e; j += kWG)
+    part = fma(widen(ld_stream(val + j)), widen(B[ld_stream(ci + j)]), part);
+  part = group_sum<64>(part);
+  if ((threadIdx.x & 63) == 0) wsum[threadIdx.x >> 6] = part;
+  __syncthreads();
+  if (threadIdx.x == 0) C[r] = (wsum[0] + wsum[1]) + (wsum[2] + wsum[3]);
+  (void)nrows;
+}
+
+// ---------------------------------------------------------------- V4
+template <typename VT, typename BT>
+__global__ __launch_bounds__(kWG) void k_lds_block(int64_t nblocks, const int32_t* __restrict__ blocks,
+                                                   const int32_t* __restrict__ rp,
+                                                   const int32_t* __restrict__ ci,
+                                                   const VT* __restrict__ val,
+                                                   const BT* __restrict__ B,
+                                                   double* __restrict__ C) {
+  __shared__ dev::BlockLds L;
+  const int64_t b = dev::xcd_remap(blockIdx.x, nblocks);
+  const int32_t r0 = blocks[b], r1 = blocks[b + 1];
+  if (r0 >= r1) return;
+  dev::lds_block<VT, BT>(L, rp, ci, val, B, C, r0, r1);
+}
+
+// ---------------------------------------------------------------- SpMM
+// LPR lanes per row; lane l owns columns [c0, c0+CPL) with c0 = l*CPL + t*LPR*CPL.
+// Each gathered B row segment is a contiguous CPL-wide vector load.
+template <typename T, int N>
+struct Vec;
+template <>
+struct Vec<double, 1> { using type = double; };
+template <>
+struct Vec<double, 2> { using type = double2; };
+template <>
+struct Vec<float, 1> { using type = float; };
+template <>
+struct Vec<float, 4> { using type = float4; };
+
+template <typename BT, int CPL>
+__device__ __forceinline__ void load_vec(const BT* p, double (&out)[CPL]) {
+  using V = typename Vec<BT, CPL>::type;
+  V x = *reinterpret_cast<const V*>(p);
+  if constexpr (CPL == 1) {
+    out[0] = (double)x;
+  } else if constexpr (CPL == 2) {
+    out[0] = (double)x.x; out[1] = (double)x.y;
+  } else {
+    out[0] = (double)x.x; out[1] = (double)x.y; out[2] = (double)x.z; out[3] = (double)x.w;
+  }
+}
+
+template <typename VT, typename BT, int LPR, int CPL>
+__global__ __launch_bounds__(kWG) void k_spmm(int32_t nrows, int32_t k,
+                                              const int32_t* __restrict__ rp,
+                                              const int32_t* __restrict__ ci,
+                                              const VT* __restrict__ val,
+                                              const BT* __restrict__ B, int64_t ldb,
+                                              double* __restrict__ C, int64_t ldc) {
+  const int64_t row = ((int64_t)blockIdx.x * kWG + threadIdx.x) / LPR;
+  const int lane = threadIdx.x & (LPR - 1);
+  if (row >= nrows) return;
+  const int32_t s = rp[row], e = rp[row + 1];
+  for (int32_t c0 = lane * CPL; c0 < k; c0 += LPR * CPL) {
+    double acc[CPL];
+#pragma unroll
+    for (int t = 0; t < CPL; ++t) acc[t] = 0.0;
+    const bool full = c0 + CPL <= k;
+    int32_t j = s;
+    for (; j + 2 <= e; j += 2) {
+      const double v0 = widen(val[j]), v1 = widen(val[j + 1]);
+      const int64_t o0 = (int64_t)ci[j] * ldb + c0, o1 = (int64_t)ci[j + 1] * ldb + c0;
+      double b0[CPL], b1[CPL];
+      if (full) {
+        load_vec<BT, CPL>(B + o0, b0);
+        load_vec<BT, CPL>(B + o1, b1);
+      } else {
+#pragma unroll
+        for (int t = 0; t < CPL; ++t) {
+          b0[t] = c0 + t < k ? (double)B[o0 + t] : 0.0;
+          b1[t] = c0 + t < k ? (double)B[o1 + t] : 0.0;
+        }
+      }
+#pragma unroll
+      for (int t = 0; t < CPL; ++t) acc[t] = fma(v0, b0[t], acc[t]);
+#pragma unroll
+      for (int t = 0; t < CPL; ++t) acc[t] = fma(v1, b1[t], acc[t]);
+    }
+    if (j < e) {
+      const double v0 = widen(val[j]);
+      const int64_t o0 = (int64_t)ci[j] * ldb + c0;
+      double b0[CPL];
+      if (full) {
+        load_vec<BT, CPL>(B + o0, b0);
+      } else {
+#pragma unroll
+        for (int t = 0; t < CPL; ++t) b0[t] = c0 + t < k ? (double)B[o0 + t] : 0.0;
+      }
+#pragma unroll
+      for (int t = 0; t < CPL; ++t) acc[t] = fma(v0, b0[t], acc[t]);
+    }
+    double* out = C + row * ldc + c0;
+#pragma unroll
+    for (int t = 0; t < CPL; ++t)
+      if (c0 + t < k) out[t] = acc[t];
+  }
+}
+
+// ---------------------------------------------------------------- fill
+template <typename T>
+__global__ void k_fill(T* p, int64_t n, T v) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    p[i] = v;
+}
+
+inline unsigned grid_for(int64_t threads) {
+  return (unsigned)((threads + kWG - 1) / kWG);
+}
+
+template <typename VT, typename BT>
+int spmv_typed(const Plan& p, int variant, const BT* B, double* C, hipStream_t s) {
+  const VT* val = static_cast<const VT*>(p.val);
+  const int32_t n = (int32_t)p.n_rows;
+  if (n == 0) return SPMV_OK;
+  switch (variant) {
+    case SPMV_V0_THREAD_ROW:
+      k_thread_row<VT, BT, false><<<grid_for(n), kWG, 0, s>>>(n, nullptr, p.row_ptr, p.col_idx,
+                                                              val, B, C);
+      break;
+    case SPMV_V1_LANES4:
+      k_group_row<VT, BT, 4, false><<<grid_for((int64_t)n * 4), kWG, 0, s>>>(
+          n, nullptr, p.row_ptr, p.col_idx, val, B, C);
+      break;
+    case SPMV_V2_LANES16:
+      k_group_row<VT, BT, 16, false><<<grid_for((int64_t)n * 16), kWG, 0, s>>>(
+          n, nullptr, p.row_ptr, p.col_idx, val, B, C);
+      break;
+    case SPMV_V3_WAVE_ROW:
+      k_group_row<VT, BT, 64, false><<<grid_for((int64_t)n * 64), kWG, 0, s>>>(
+          n, nullptr, p.row_ptr, p.col_idx, val, B, C);
+      break;
+    case SPMV_V4_LDS_BLOCK:
+      if (p.nblocks > 0)
+        k_lds_block<VT, BT><<<(unsigned)p.nblocks, kWG, 0, s>>>(p.nblocks, p.blocks, p.row_ptr,
+                                                                p.col_idx, val, B, C);
+      break;
+    case SPMV_V5_BINNED: {
+      const int32_t* L = p.bin_rows;
+      const int32_t* o = p.bin_offset;
+      const int32_t* c = p.bin_count;
+      if (c[0])
+        k_thread_row<VT, BT, true><<<grid_for(c[0]), kWG, 0, s>>>(c[0], L + o[0], p.row_ptr,
+                                                                  p.col_idx, val, B, C);
+      if (c[1])
+        k_group_row<VT, BT, 4, true><<<grid_for((int64_t)c[1] * 4), kWG, 0, s>>>(
+            c[1], L + o[1], p.row_ptr, p.col_idx, val, B, C);
+      if (c[2])
+        k_group_row<VT, BT, 16, true><<<grid_for((int64_t)c[2] * 16), kWG, 0, s>>>(
+            c[2], L + o[2], p.row_ptr, p.col_idx, val, B, C);
+      if (c[3])
+        k_group_row<VT, BT, 64, true><<<grid_for((int64_t)c[3] * 64), kWG, 0, s>>>(
+            c[3], L + o[3], p.row_ptr, p.col_idx, val, B, C);
+      if (c[4])
+        k_block_row<VT, BT><<<(unsigned)c[4], kWG, 0, s>>>(c[4], L + o[4], p.row_ptr,
+                                                           p.col_idx, val, B, C);
+      break;
+    }
+    default:
+      return fail(SPMV_ERR_INVALID_ARG, "unknown variant");
+  }
+  SPMV_HIP(hipGetLastError());
+  return SPMV_OK;
+}
+
+template <typename VT, typename BT, int CPL>
+int spmm_lpr(const Plan& p, int k, const BT* B, int64_t ldb, double* C, int64_t ldc,
+             hipStream_t s) {
+  const VT* val = static_cast<const VT*>(p.val);
+  const int32_t n = (int32_t)p.n_rows;
+  int need = (k + CPL - 1) / CPL;
+  int lpr = 1;
+  while (lpr < need && lpr < 64) lpr *= 2;
+#define SPMM_CASE(L)                                                                       \
+  case L:                                                                                  \
+    k_spmm<VT, BT, L, CPL><<<grid_for((int64_t)n * L), kWG, 0, s>>>(n, k, p.row_ptr,       \
+                                                                   p.col_idx, val, B, ldb, \
+                                                                   C, ldc);                \
+    break;
+  switch (lpr) {
+    SPMM_CASE(1)
+    SPMM_CASE(2)
+    SPMM_CASE(4)
+    SPMM_CASE(8)
+    SPMM_CASE(16)
+    SPMM_CASE(32)
+    SPMM_CASE(64)
+  }
+#undef SPMM_CASE
+  SPMV_HIP(hipGetLastError());
+  return SPMV_OK;
+}
+
+}  // namespace
+
+int launch_spmv(const Plan& p, int variant, const void* B, double* C, hipStream_t s) {
+  if (p.vdt == SPMV_F64)
+    return spmv_typed<double, double>(p, variant, static_cast<const double*>(B), C, s);
+  return spmv_typed<float, float>(p, variant, static_cast<const float*>(B), C, s);
+}
+
+int launch_spmm(const Plan& p, int k, const void* B, int64_t ldb, double* C, int64_t ldc,
+                hipStream_t s) {
+  if (p.n_rows == 0) return SPMV_OK;
+  const uintptr_t a = reinterpret_cast<uintptr_t>(B);
+  if (p.vdt == SPMV_F64) {
+    const double* b = static_cast<const double*>(B);
+    if (k >= 2 && a % 16 == 0 && ldb % 2 == 0)
+      return spmm_lpr<double, double, 2>(p, k, b, ldb, C, ldc, s);
+    return spmm_lpr<double, double, 1>(p, k, b, ldb, C, ldc, s);
+  }
+  const float* b = static_cast<const float*>(B);
+  if (k >= 4 && a % 16 == 0 && ldb % 4 == 0)
+    return spmm_lpr<float, float, 4>(p, k, b, ldb, C, ldc, s);
+  return spmm_lpr<float, float, 1>(p, k, b, ldb, C, ldc, s);
+}
+
+int launch_fill(void* dst, int dtype, int64_t n, double value, hipStream_t s) {
+  if (n <= 0) return SPMV_OK;
+  const unsigned g = (unsigned)std::min<int64_t>((n + kWG - 1) / kWG, 4096);
+  if (dtype == SPMV_F64)
+    k_fill<double><<<g, kWG, 0, s>>>(static_cast<double*>(dst), n, value);
+  else
+    k_fill<float><<<g, kWG, 0, s>>>(static_cast<float*>(dst), n, (float)value);
+  SPMV_HIP(hipGetLastError());
+  return SPMV_OK;
+}
+
+}  // namespace spmv

@@ -1,0 +1,148 @@
+"""Selector network kernels (forward, backward, Adam) against the float64
+oracle, and the selector inside plan creation."""
+import numpy as np
+import pytest
+
+import crsgen
+import oracle
+from oracle import mlp
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+import paper_1101_0091_amd as pkg  # noqa: E402
+
+DEV = "cuda:0"
+U32 = 2.0 ** -24
+
+
+def _theta32(seed):
+    rng = np.random.default_rng(seed)
+    parts = [rng.uniform(-0.4, 0.4, size=s) for s in mlp.SHAPES]
+    return mlp.pack(parts).astype(np.float32)
+
+
+def _inputs(nb, seed):
+    """theta, X, T in float32 such that no oracle pre-activation sits within
+    1e-3 of its magnitude bound of zero (ReLU masks then agree)."""
+    for s in range(seed, seed + 100):
+        th = _theta32(s)
+        rng = np.random.default_rng(s + 1000)
+        X = rng.standard_normal((nb, 16)).astype(np.float32)
+        T = rng.standard_normal((nb, 6)).astype(np.float32)
+        _, (x, z1, _, z2, _) = mlp.forward(th.astype(np.float64), X.astype(np.float64))
+        _, (_, m1, _, m2, _) = mlp.forward(np.abs(th.astype(np.float64)),
+                                           np.abs(X.astype(np.float64)))
+        if np.all(np.abs(z1) > 1e-3 * m1) and np.all(np.abs(z2) > 1e-3 * m2):
+            return th, X, T
+    raise RuntimeError("no well-separated inputs")
+
+
+def _abs_backward(th, cache, dYabs):
+    """Backward pass on magnitudes: sum of |terms| of every gradient entry."""
+    W1, b1, W2, b2, W3, b3 = mlp.unpack(np.abs(th))
+    X, z1, h1, z2, h2 = cache
+    X, h1, h2 = np.abs(X), np.abs(h1), np.abs(h2)
+    dz2 = (dYabs @ W3) * (z2 > 0)
+    dz1 = (dz2 @ W2) * (z1 > 0)
+    return mlp.pack([dz1.T @ X, dz1.sum(0), dz2.T @ h1, dz2.sum(0), dYabs.T @ h2,
+                     dYabs.sum(0)])
+
+
+def _run_forward(th, X):
+    nb = X.shape[0]
+    thd = torch.from_numpy(th).to(DEV)
+    Xd = torch.from_numpy(X).to(DEV)
+    Y = torch.empty((nb, 6), dtype=torch.float32, device=DEV)
+    Z1 = torch.empty((nb, 64), dtype=torch.float32, device=DEV)
+    Z2 = torch.empty((nb, 64), dtype=torch.float32, device=DEV)
+    pkg.spmv_mlp_forward(thd, Xd, nb, Y, Z1, Z2)
+    return thd, Xd, Y, Z1, Z2
+
+
+@pytest.mark.parametrize("nb", [1, 37, 384])
+def test_forward_and_backward_vs_oracle(nb):
+    th, X, T = _inputs(nb, 11 + nb)
+    th64, X64, T64 = th.astype(np.float64), X.astype(np.float64), T.astype(np.float64)
+    thd, Xd, Y, Z1, Z2 = _run_forward(th, X)
+    Yref, cache = mlp.forward(th64, X64)
+    Yabs, (_, M1, _, M2, _) = mlp.forward(np.abs(th64), np.abs(X64))
+    tolY = 3e-5 * Yabs
+    assert np.all(np.abs(Y.cpu().numpy() - Yref) <= tolY)
+    assert np.all(np.abs(Z1.cpu().numpy() - cache[1]) <= 3e-5 * M1)
+    assert np.all(np.abs(Z2.cpu().numpy() - cache[3]) <= 3e-5 * M2)
+    Td = torch.from_numpy(T).to(DEV)
+    scratch = torch.empty(nb * (6 + 64 + 64), dtype=torch.float32, device=DEV)
+    grad = torch.empty(mlp.N_PARAMS, dtype=torch.float32, device=DEV)
+    pkg.spmv_mlp_backward(thd, Xd, Z1, Z2, Y, Td, nb, scratch, grad)
+    gref = mlp.backward(th64, cache, Yref, T64)
+    dYabs = 2.0 * (np.abs(Yref - T64) + tolY) / (nb * 6)
+    gabs = _abs_backward(th64, cache, dYabs)
+    err = np.abs(grad.cpu().numpy() - gref)
+    assert np.all(err <= 1e-4 * gabs + 1e-30), float(np.max(err / (gabs + 1e-30)))
+
+
+def test_adam_step_vs_oracle():
+    rng = np.random.default_rng(3)
+    n = mlp.N_PARAMS
+    th = rng.standard_normal(n).astype(np.float32)
+    g = rng.standard_normal(n).astype(np.float32)
+    m = (0.1 * rng.standard_normal(n)).astype(np.float32)
+    v = np.abs(0.1 * rng.standard_normal(n)).astype(np.float32)
+    d = [torch.from_numpy(a.copy()).to(DEV) for a in (th, g, m, v)]
+    pkg.spmv_mlp_adam(d[0], d[1], d[2], d[3], 7, 1e-2, 0.9, 0.999, 1e-8)
+    th2, m2, v2 = mlp.adam_step(th.astype(np.float64), g.astype(np.float64),
+                                m.astype(np.float64), v.astype(np.float64), 7, lr=1e-2)
+    assert np.allclose(d[2].cpu().numpy(), m2, rtol=1e-6, atol=1e-7)
+    assert np.allclose(d[3].cpu().numpy(), v2, rtol=1e-6, atol=1e-9)
+    assert np.all(np.abs(d[0].cpu().numpy() - th2) <= 1e-6 * np.abs(th2) + 1e-5 * 1e-2)
+
+
+def test_training_reduces_loss():
+    """A few hundred Adam steps on a learnable target lower the loss."""
+    nb = 256
+    rng = np.random.default_rng(9)
+    X = rng.standard_normal((nb, 16)).astype(np.float32)
+    Wt = rng.standard_normal((16, 6)) / 4
+    T = np.tanh(X.astype(np.float64) @ Wt).astype(np.float32)
+    th = _theta32(5) * 0.5
+    thd = torch.from_numpy(th).to(DEV)
+    Xd, Td = torch.from_numpy(X).to(DEV), torch.from_numpy(T).to(DEV)
+    Y = torch.empty((nb, 6), dtype=torch.float32, device=DEV)
+    Z1 = torch.empty((nb, 64), dtype=torch.float32, device=DEV)
+    Z2 = torch.empty((nb, 64), dtype=torch.float32, device=DEV)
+    sc = torch.empty(nb * 134, dtype=torch.float32, device=DEV)
+    g = torch.empty(mlp.N_PARAMS, dtype=torch.float32, device=DEV)
+    m = torch.zeros_like(g)
+    v = torch.zeros_like(g)
+    losses = []
+    for t in range(1, 301):
+        pkg.spmv_mlp_forward(thd, Xd, nb, Y, Z1, Z2)
+        if t in (1, 300):
+            losses.append(float(((Y - Td) ** 2).mean()))
+        pkg.spmv_mlp_backward(thd, Xd, Z1, Z2, Y, Td, nb, sc, g)
+        pkg.spmv_mlp_adam(thd, g, m, v, t, 3e-3)
+    assert losses[1] < 0.3 * losses[0], losses
+
+
+def test_selector_in_create_matches_oracle_forward():
+    th = _theta32(21)
+    mu = np.linspace(-1, 1, 16).astype(np.float32)
+    sigma = np.linspace(0.5, 3, 16).astype(np.float32)
+    lo = np.full(16, -1e30, np.float32)
+    hi = np.full(16, 1e30, np.float32)
+    pkg.spmv_selector_load(th, mu, sigma, lo, hi, 0.0)
+    assert pkg.spmv_selector_loaded()
+    A = crsgen.mesh3d(30, seed=3)[0]
+    M = pkg.CRSMatrix.from_crs(A, device=DEV)  # default mode runs the selector
+    pred = pkg.spmv_get_predictions(M.handle)
+    f = oracle.row_features(A.n_rows, A.row_ptr, A.col_idx)
+    x = ((f.astype(np.float32) - mu) / sigma).astype(np.float64)
+    yref, _ = mlp.forward(th.astype(np.float64), x[None, :])
+    yabs, _ = mlp.forward(np.abs(th.astype(np.float64)), np.abs(x[None, :]))
+    assert np.all(np.abs(pred - yref[0]) <= 1e-4 * yabs[0] + 1e-6)
+    assert M.variant == int(np.argmin(pred))
+    # MLP mode with an unreachable margin falls back to autotune
+    pkg.spmv_selector_load(th, mu, sigma, lo, hi, 1e9)
+    M2 = pkg.CRSMatrix.from_crs(A, flags=pkg.SPMV_SELECT_MLP, device=DEV)
+    t = pkg.spmv_get_autotune_times(M2.handle)
+    assert M2.variant == int(np.argmin(t))

@@ -1,0 +1,268 @@
+"""GPU parity: every kernel variant, both storage precisions, multi-RHS, the
+uneven batch, graph replay and the analysis outputs against the CPU oracle,
+through the C ABI. Acceptance: |C_gpu - C_oracle| <= 8 nnz_row 2^-53 S_i per
+row; integer-valued inputs and FP32-stored integers bit-exact."""
+import numpy as np
+import pytest
+
+import crsgen
+import oracle
+from cases import CASES, rhs
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+import paper_1101_0091_amd as pkg  # noqa: E402
+
+DEV = "cuda:0"
+NV = pkg.SPMV_NUM_VARIANTS
+
+
+def _gpu(x, dtype=None):
+    t = torch.from_numpy(np.ascontiguousarray(x))
+    return t.to(DEV) if dtype is None else t.to(DEV, dtype)
+
+
+_cache = {}
+
+
+def case(name):
+    if name not in _cache:
+        A = CASES[name]()
+        _cache[name] = (A, rhs(A))
+    return _cache[name]
+
+
+@pytest.mark.parametrize("dt", ["f64", "f32"])
+@pytest.mark.parametrize("name", list(CASES))
+def test_all_variants_vs_oracle(name, dt):
+    A, B = case(name)
+    if dt == "f32":
+        val_h, B_h = A.val.astype(np.float32), B.astype(np.float32)
+        tdt = torch.float32
+    else:
+        val_h, B_h, tdt = A.val, B, torch.float64
+    Cref, S = oracle.spmv(A.n_rows, A.row_ptr, A.col_idx, val_h, B_h)
+    M = pkg.CRSMatrix(A.n_rows, A.n_cols, A.row_ptr, A.col_idx, val_h, val_dtype=tdt,
+                      flags=pkg.SPMV_FLAG_VARIANT(4), device=DEV)
+    Bd = _gpu(B_h)
+    for v in range(NV):
+        M.variant = v
+        C = torch.full((A.n_rows,), float("nan"), dtype=torch.float64, device=DEV)
+        M.apply(Bd, C)
+        ok, worst = oracle.bound_ok(C.cpu().numpy(), Cref, A.row_ptr, S)
+        assert ok, f"{name} {dt} variant {v}: worst/bound {worst}"
+
+
+@pytest.mark.parametrize("dt", ["f64", "f32"])
+def test_integer_inputs_bit_exact(dt):
+    A = crsgen.random_crs(30_000, 20_000, seed=41, max_len=3000, empty_frac=0.05,
+                          integer=True)
+    B = crsgen.int_vec(A.n_cols, 41, 0, -8, 8)
+    Cref, _ = oracle.spmv(A.n_rows, A.row_ptr, A.col_idx, A.val, B)
+    tdt = torch.float32 if dt == "f32" else torch.float64
+    M = pkg.CRSMatrix(A.n_rows, A.n_cols, A.row_ptr, A.col_idx, A.val, val_dtype=tdt,
+                      flags=pkg.SPMV_FLAG_VARIANT(0), device=DEV)
+    Bd = _gpu(B, tdt)
+    for v in range(NV):
+        M.variant = v
+        assert np.array_equal(M.apply(Bd).cpu().numpy(), Cref), v
+
+
+def test_diagonal_bit_exact():
+    n = 100_000
+    rng = np.random.default_rng(5)
+    d, B = rng.standard_normal(n), rng.standard_normal(n)
+    M = pkg.CRSMatrix(n, n, np.arange(n + 1), np.arange(n), d, device=DEV)
+    for v in range(NV):
+        M.variant = v
+        assert np.array_equal(M.apply(_gpu(B)).cpu().numpy(), d * B), v
+
+
+def test_deterministic_repeats():
+    A, B = case("powerlaw_60k")
+    M = pkg.CRSMatrix.from_crs(A, device=DEV)
+    Bd = _gpu(B)
+    for v in range(NV):
+        M.variant = v
+        first = M.apply(Bd).clone()
+        for _ in range(20):
+            assert torch.equal(M.apply(Bd), first), v
+
+
+@pytest.mark.parametrize("dt", ["f64", "f32"])
+@pytest.mark.parametrize("k", [1, 2, 3, 4, 5, 8, 16, 32, 33, 64, 100])
+def test_spmm_vs_oracle(k, dt):
+    A = crsgen.laplace2d(256) if k <= 32 else crsgen.random_crs(3000, 2000, seed=k, max_len=50)
+    Bh = crsgen.uniform_vec(A.n_cols * k, 4).reshape(A.n_cols, k)
+    tdt = torch.float32 if dt == "f32" else torch.float64
+    if dt == "f32":
+        Bh = Bh.astype(np.float32)
+        val = A.val.astype(np.float32)
+    else:
+        val = A.val
+    Cref, S = oracle.spmm(A.n_rows, A.row_ptr, A.col_idx, val, Bh)
+    M = pkg.CRSMatrix(A.n_rows, A.n_cols, A.row_ptr, A.col_idx, val, val_dtype=tdt, device=DEV)
+    C = M.spmm(_gpu(Bh)).cpu().numpy()
+    ok, worst = oracle.bound_ok(C, Cref, A.row_ptr, S)
+    assert ok, worst
+    # padded leading dimensions (ldb, ldc > k) take the scalar path
+    Bp = torch.zeros((A.n_cols, k + 3), dtype=tdt, device=DEV)
+    Bp[:, :k] = _gpu(Bh)
+    Cp = torch.full((A.n_rows, k + 1), 7.0, dtype=torch.float64, device=DEV)
+    pkg.spmm_apply(M.handle, k, Bp, k + 3, M.code, Cp, k + 1)
+    Cp = Cp.cpu().numpy()
+    assert oracle.bound_ok(Cp[:, :k], Cref, A.row_ptr, S)[0]
+    assert np.all(Cp[:, k] == 7.0)  # untouched padding column
+
+
+def test_full_size_hamiltonian_and_mesh():
+    """Workloads at full size (N = 6.0M and 21.95M), every row checked."""
+    for name, A in (("hamiltonian_6M", crsgen.hamiltonian(6_000_000, seed=2)),
+                    ("mesh3d_280", crsgen.mesh3d(280, seed=3)[0])):
+        B = crsgen.uniform_vec(A.n_cols, 2 if name.startswith("ham") else 3)
+        Cref, S = oracle.spmv(A.n_rows, A.row_ptr, A.col_idx, A.val, B)
+        M = pkg.CRSMatrix.from_crs(A, device=DEV)
+        Bd = _gpu(B)
+        for v in (4, 5, 1, 0):
+            M.variant = v
+            ok, worst = oracle.bound_ok(M.apply(Bd).cpu().numpy(), Cref, A.row_ptr, S)
+            assert ok, (name, v, worst)
+        # FP32 storage against the widened-input oracle
+        v32, b32 = A.val.astype(np.float32), B.astype(np.float32)
+        C32ref, S32 = oracle.spmv(A.n_rows, A.row_ptr, A.col_idx, v32, b32)
+        M32 = pkg.CRSMatrix(A.n_rows, A.n_cols, A.row_ptr, A.col_idx, v32,
+                            val_dtype=torch.float32, device=DEV)
+        ok, worst = oracle.bound_ok(M32.apply(_gpu(b32)).cpu().numpy(), C32ref, A.row_ptr, S32)
+        assert ok, (name, "f32", worst)
+        del M, M32
+        torch.cuda.empty_cache()
+
+
+@pytest.mark.parametrize("name", ["laplace2d_256", "powerlaw_60k", "mostly_empty", "hand",
+                                  "rect_wide", "nnz0", "rows0"])
+def test_features_vs_oracle(name):
+    A, _ = case(name)
+    M = pkg.CRSMatrix.from_crs(A, device=DEV)
+    f = M.features
+    ref = oracle.row_features(A.n_rows, A.row_ptr, A.col_idx)
+    assert np.allclose(f, ref, rtol=1e-12, atol=0), (f, ref)
+
+
+BAD = {
+    "row_ptr0": (3, 4, [1, 2, 2, 5], [0, 3, 1, 2, 3]),
+    "decreasing": (3, 4, [0, 3, 2, 5], [0, 3, 1, 2, 3]),
+    "last_ne_nnz": (3, 4, [0, 2, 2, 4], [0, 3, 1, 2, 3]),
+    "col_high": (3, 4, [0, 2, 2, 5], [0, 4, 1, 2, 3]),
+    "col_negative": (3, 4, [0, 2, 2, 5], [0, 3, -1, 2, 3]),
+}
+
+
+@pytest.mark.parametrize("name", list(BAD))
+def test_bad_crs_rejected(name):
+    n, nc, rp, ci = BAD[name]
+    with pytest.raises(pkg.SpmvError) as e:
+        pkg.CRSMatrix(n, nc, np.array(rp), np.array(ci), np.ones(len(ci)), device=DEV)
+    assert e.value.status == pkg.SPMV_ERR_BAD_CRS
+    # the device is still healthy afterwards
+    A = crsgen.laplace2d(8)
+    pkg.CRSMatrix.from_crs(A, device=DEV).apply(_gpu(rhs(A)))
+    torch.cuda.synchronize()
+
+
+def test_autotune_selects_fastest():
+    A, B = case("hamiltonian_200k")
+    M = pkg.CRSMatrix.from_crs(A, flags=pkg.SPMV_SELECT_AUTOTUNE, device=DEV)
+    t = pkg.spmv_get_autotune_times(M.handle)
+    assert np.all(t > 0) and M.variant == int(np.argmin(t))
+    Cref, S = oracle.spmv(A.n_rows, A.row_ptr, A.col_idx, A.val, B)
+    assert oracle.bound_ok(M.apply(_gpu(B)).cpu().numpy(), Cref, A.row_ptr, S)[0]
+
+
+# ------------------------------------------------------------------ batch
+
+def _batch_mats(count, seed, nlo=100, nhi=5000):
+    return [crsgen.family_matrix(seed, i, nlo, nhi)[0] for i in range(count)]
+
+
+@pytest.mark.parametrize("dt", ["f64", "f32"])
+def test_batch_vs_oracle_and_each(dt):
+    mats = _batch_mats(200, 6)
+    tdt = torch.float32 if dt == "f32" else torch.float64
+    if dt == "f32":
+        mats = [crsgen.CRS(m.n_rows, m.n_cols, m.row_ptr, m.col_idx, m.val.astype(np.float32))
+                for m in mats]
+    Bt = pkg.Batch(mats, val_dtype=tdt, device=DEV)
+    ncols = int(Bt.n_cols.sum())
+    Bh = crsgen.uniform_vec(ncols, 6)
+    if dt == "f32":
+        Bh = Bh.astype(np.float32)
+    B_all = _gpu(Bh)
+    C_all = torch.full((int(Bt.n_rows.sum()),), float("nan"), dtype=torch.float64, device=DEV)
+    Bd, Cd, bh, ch = Bt.pointers(B_all, C_all)
+    Bt.apply(Bd, Cd)
+    C1 = C_all.clone()
+    for m, A in enumerate(mats):
+        b = Bh[Bt.col_off[m]:Bt.col_off[m + 1]]
+        Cref, S = oracle.spmv(A.n_rows, A.row_ptr, A.col_idx, A.val, b)
+        got = C1[Bt.row_off[m]:Bt.row_off[m + 1]].cpu().numpy()
+        ok, worst = oracle.bound_ok(got, Cref, A.row_ptr, S)
+        assert ok, (m, worst)
+    C_all.fill_(float("nan"))
+    Bt.apply_each(bh, ch)
+    assert torch.equal(C_all, C1)  # same tiles, same order: bitwise
+
+
+def test_graph_replay_matches_eager():
+    mats = _batch_mats(300, 7)
+    Bt = pkg.Batch(mats, device=DEV)
+    B_all = _gpu(crsgen.uniform_vec(int(Bt.n_cols.sum()), 7))
+    C_all = torch.zeros(int(Bt.n_rows.sum()), dtype=torch.float64, device=DEV)
+    Bd, Cd, bh, ch = Bt.pointers(B_all, C_all)
+    Bt.apply(Bd, Cd)
+    eager = C_all.clone()
+    s = torch.cuda.Stream()
+    torch.cuda.synchronize()
+    with torch.cuda.stream(s):
+        pkg.spmv_graph_begin(s)
+        Bt.apply(Bd, Cd, stream=s)
+        g1 = pkg.spmv_graph_end(s)
+        pkg.spmv_graph_begin(s)
+        Bt.apply_each(bh, ch, stream=s)
+        g2 = pkg.spmv_graph_end(s)
+    try:
+        for g in (g1, g2, g1, g2, g1):
+            C_all.fill_(-1.0)
+            torch.cuda.synchronize()
+            pkg.spmv_graph_launch(g, s)
+            s.synchronize()
+            assert torch.equal(C_all, eager)
+            # eager work between replays
+            Bt.apply(Bd, Cd)
+            torch.cuda.synchronize()
+    finally:
+        pkg.spmv_graph_destroy(g1)
+        pkg.spmv_graph_destroy(g2)
+
+
+def test_single_matrix_graph_replay():
+    A, B = case("mesh3d_48_permuted")
+    M = pkg.CRSMatrix.from_crs(A, device=DEV)
+    Bd = _gpu(B)
+    C = torch.zeros(A.n_rows, dtype=torch.float64, device=DEV)
+    for v in range(NV):
+        M.variant = v
+        eager = M.apply(Bd).clone()
+        s = torch.cuda.Stream()
+        torch.cuda.synchronize()
+        pkg.spmv_graph_begin(s)
+        pkg.spmv_apply(M.handle, Bd, pkg.SPMV_F64, C, s)
+        g = pkg.spmv_graph_end(s)
+        for _ in range(3):
+            C.fill_(0.0)
+            torch.cuda.synchronize()
+            pkg.spmv_graph_launch(g, s)
+            s.synchronize()
+            assert torch.equal(C, eager), v
+            M.apply(Bd)
+        pkg.spmv_graph_destroy(g)
