@@ -80,6 +80,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--variant", type=int, default=-1, help="force a variant (default: autotune)")
     ap.add_argument("--workload", default="hamiltonian", choices=["hamiltonian", "mesh"])
+    ap.add_argument("--calib-copy", action="store_true",
+                    help="first run the plain copy kernel on 2 x 1 GiB (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -95,6 +97,15 @@ def main():
 
     dev = torch.device("cuda:0")
     stream = torch.cuda.current_stream()
+    if args.calib_copy:
+        n = 1 << 27  # 1 GiB of float64 read, 1 GiB written per launch
+        src = torch.ones(n, dtype=torch.float64, device=dev)
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            pkg.spmv_stream_copy(dst, src, n)
+        torch.cuda.synchronize()
+        del src, dst
+        log("copy calibration: 3 launches of k_copy over 1 GiB")
     if args.workload == "hamiltonian":
         wname, seed = "hamiltonian_like_N6M", 2
         log("generating Hamiltonian-like matrix N=6,000,000")
@@ -233,7 +244,7 @@ def cpu_baseline(A, B):
     import oracle
     log("cpu baseline: timing the oracle")
     reps, t = 0, 0.0
-    while t < 10.0 and reps < 50:
+    while t < 10.0 and reps < 1000:
         t0 = time.perf_counter()
         oracle.spmv(A.n_rows, A.row_ptr, A.col_idx, A.val, B)
         t += time.perf_counter() - t0

@@ -181,12 +181,13 @@ __global__ __launch_bounds__(kWG) void k_scatter_bins(int64_t n, int64_t nnz,
 // Row blocks: R_b = first row r with row_ptr[r] + r >= b * budget. The key
 // row_ptr[r] + r grows strictly with r, so every block holds at most `budget`
 // rows, and all its rows except the last lie in one budget-sized chunk.
+// Each entry also carries row_ptr[R_b], the start of the block's nonzeros.
 __global__ void k_blocks(int64_t n, int64_t nblocks, const int32_t* __restrict__ rp,
-                         int32_t* __restrict__ blocks) {
+                         int2* __restrict__ blocks) {
   const int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (b > nblocks) return;
   if (b == nblocks) {
-    blocks[b] = (int32_t)n;
+    blocks[b] = make_int2((int32_t)n, rp[n]);
     return;
   }
   const int64_t target = b * (int64_t)kBlockBudget;
@@ -198,7 +199,7 @@ __global__ void k_blocks(int64_t n, int64_t nblocks, const int32_t* __restrict__
     else
       lo = mid + 1;
   }
-  blocks[b] = (int32_t)lo;
+  blocks[b] = make_int2((int32_t)lo, rp[lo]);
 }
 
 inline unsigned grid_cap(int64_t threads, unsigned cap) {

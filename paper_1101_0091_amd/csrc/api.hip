@@ -38,7 +38,7 @@ PlanLayout plan_layout(int64_t n_rows, int64_t n_cols, int64_t nnz, uint32_t fla
   L.header = o;
   o += kHeaderBytes;
   L.blocks = o;
-  o += align256(sizeof(int32_t) * (size_t)(nb + 1));
+  o += align256(sizeof(int2) * (size_t)(nb + 1));
   L.bins = o;
   o += align256(sizeof(int32_t) * (size_t)std::max<int64_t>(n_rows, 1));
   const uint32_t mode = flags & 0xFFu;
@@ -205,7 +205,7 @@ int spmv_create(spmv_handle* h, int64_t n_rows, int64_t n_cols, int64_t nnz,
   p.ws = static_cast<char*>(workspace);
   p.ws_bytes = ws_bytes;
   p.hdr = reinterpret_cast<WsHeader*>(p.ws + L.header);
-  p.blocks = reinterpret_cast<int32_t*>(p.ws + L.blocks);
+  p.blocks = reinterpret_cast<int2*>(p.ws + L.blocks);
   p.nblocks = lds_block_count(n_rows, nnz);
   p.bin_rows = reinterpret_cast<int32_t*>(p.ws + L.bins);
   if (L.at_B) {
@@ -347,7 +347,7 @@ BatchLayout batch_layout(int32_t count, int64_t max_tiles) {
   L.err = o;
   o += 256;
   L.tiles = o;
-  o += align256(sizeof(int32_t) * 3 * (size_t)std::max<int64_t>(max_tiles, 1));
+  o += align256(sizeof(int32_t) * 6 * (size_t)std::max<int64_t>(max_tiles, 1));
   L.toff = o;
   o += align256(sizeof(int64_t) * (size_t)(count + 1));
   L.nr = o;

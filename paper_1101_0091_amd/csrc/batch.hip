@@ -63,10 +63,13 @@ __global__ __launch_bounds__(kWG) void k_batch_tiles(int32_t count,
   for (int64_t b = threadIdx.x; b < nb; b += kWG) {
     const int32_t r0 = first_row_at(rp, n, b * kBlockBudget);
     const int32_t r1 = (b + 1 == nb) ? (int32_t)n : first_row_at(rp, n, (b + 1) * kBlockBudget);
-    int32_t* t = tiles + 3 * (toff[m] + b);
+    int32_t* t = tiles + 6 * (toff[m] + b);
     t[0] = m;
     t[1] = r0;
     t[2] = r1;
+    t[3] = rp[r0];
+    t[4] = rp[r1];
+    t[5] = 0;
   }
 }
 
@@ -81,12 +84,14 @@ __global__ __launch_bounds__(kWG) void k_batch_apply(
   const int64_t n = t1 - t0, g = gridDim.x;
   const int64_t lo = t0 + (n * w) / g, hi = t0 + (n * (w + 1)) / g;
   for (int64_t t = lo; t < hi; ++t) {
-    const int32_t m = tiles[3 * t], r0 = tiles[3 * t + 1], r1 = tiles[3 * t + 2];
+    const int32_t* tl = tiles + 6 * t;
+    const int32_t m = tl[0], r0 = tl[1], r1 = tl[2], S = tl[3], E = tl[4];
     if (r0 >= r1) continue;
     const BT* B = Bs ? static_cast<const BT*>(Bs[m]) : B1;
     double* C = Cs ? Cs[m] : C1;
     __syncthreads();  // LDS of the previous tile is no longer read
-    dev::lds_block<VT, BT>(L, rps[m], cis[m], static_cast<const VT*>(vals[m]), B, C, r0, r1);
+    dev::lds_block<VT, BT>(L, rps[m], cis[m], static_cast<const VT*>(vals[m]), B, C, r0, r1, S,
+                           E);
   }
 }
 

@@ -52,7 +52,7 @@ struct Plan {
   char* ws = nullptr;
   size_t ws_bytes = 0;
   WsHeader* hdr = nullptr;        // device
-  int32_t* blocks = nullptr;      // device int32[nblocks+1]
+  int2* blocks = nullptr;         // device [nblocks+1]: (first row, row_ptr[first row])
   int64_t nblocks = 0;
   int32_t* bin_rows = nullptr;    // device int32[n_rows]
   int32_t bin_count[kNumBins] = {0, 0, 0, 0, 0};
@@ -74,7 +74,7 @@ struct Batch {
   const int32_t* const* row_ptrs = nullptr;  // device arrays of device pointers
   const int32_t* const* col_idxs = nullptr;
   const void* const* vals = nullptr;
-  int32_t* tiles = nullptr;   // device int32[3 * ntiles]: matrix, row begin, row end
+  int32_t* tiles = nullptr;   // device int32[6 * ntiles]: matrix, r0, r1, S, E, pad
   int64_t ntiles = 0;
   int32_t* err = nullptr;     // device
   int64_t* tile_offset_host = nullptr;  // host [count+1]

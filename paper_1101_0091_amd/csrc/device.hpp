@@ -118,14 +118,15 @@ __device__ __forceinline__ void block_rows(const BlockLds& L, const int32_t* __r
   }
 }
 
+// S = row_ptr[r0] and E = row_ptr[r1] come from the block table, so the
+// workgroup's first dependent round trip already yields the stream bounds.
 template <typename VT, typename BT>
 __device__ __forceinline__ void lds_block(BlockLds& L, const int32_t* __restrict__ rp,
                                           const int32_t* __restrict__ ci,
                                           const VT* __restrict__ val, const BT* __restrict__ B,
-                                          double* __restrict__ C, int32_t r0, int32_t r1) {
+                                          double* __restrict__ C, int32_t r0, int32_t r1,
+                                          int32_t S, int32_t E) {
   const int tid = threadIdx.x;
-  const int32_t S = rp[r0];
-  const int32_t E = rp[r1];
   const int32_t cend = (E - S > kBlockBudget) ? S + kBlockBudget : E;
   const int32_t nin = cend - S;
   const bool tail = E > cend;

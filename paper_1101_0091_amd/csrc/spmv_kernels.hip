@@ -96,7 +96,7 @@ __global__ __launch_bounds__(kWG) void k_block_row(int32_t nrows, const int32_t*
 
 // ---------------------------------------------------------------- V4
 template <typename VT, typename BT>
-__global__ __launch_bounds__(kWG) void k_lds_block(int64_t nblocks, const int32_t* __restrict__ blocks,
+__global__ __launch_bounds__(kWG) void k_lds_block(int64_t nblocks, const int2* __restrict__ blocks,
                                                    const int32_t* __restrict__ rp,
                                                    const int32_t* __restrict__ ci,
                                                    const VT* __restrict__ val,
@@ -104,9 +104,9 @@ __global__ __launch_bounds__(kWG) void k_lds_block(int64_t nblocks, const int32_
                                                    double* __restrict__ C) {
   __shared__ dev::BlockLds L;
   const int64_t b = dev::xcd_remap(blockIdx.x, nblocks);
-  const int32_t r0 = blocks[b], r1 = blocks[b + 1];
-  if (r0 >= r1) return;
-  dev::lds_block<VT, BT>(L, rp, ci, val, B, C, r0, r1);
+  const int2 m0 = blocks[b], m1 = blocks[b + 1];
+  if (m0.x >= m1.x) return;
+  dev::lds_block<VT, BT>(L, rp, ci, val, B, C, m0.x, m1.x, m0.y, m1.y);
 }
 
 // ---------------------------------------------------------------- SpMM
