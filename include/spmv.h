@@ -195,6 +195,10 @@ int spmv_graph_destroy(spmv_graph_handle g);
 int spmv_selector_load(const float* params, const float* feat_mu, const float* feat_sigma,
                        const float* feat_lo, const float* feat_hi, float margin);
 int spmv_selector_loaded(int* loaded);
+/* Load a packed weights file (host path): 8-byte magic "SPMVSEL1", then
+ * little-endian float32 params[SPMV_MLP_PARAMS], mu[16], sigma[16], lo[16],
+ * hi[16], margin[1]. SPMV_ERR_INVALID_ARG if the file is missing or malformed. */
+int spmv_selector_load_file(const char* path);
 
 /*
  * Selector network kernels (device arrays, float32), used by the trainer.

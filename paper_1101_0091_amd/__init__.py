@@ -36,7 +36,8 @@ EXPORTS = (
     "spmv_get_num_blocks", "spmv_destroy", "spmv_batch_workspace_size", "spmv_batch_create",
     "spmv_batch_apply", "spmv_batch_apply_each", "spmv_batch_get_num_tiles",
     "spmv_batch_destroy", "spmv_graph_begin", "spmv_graph_end", "spmv_graph_launch",
-    "spmv_graph_destroy", "spmv_selector_load", "spmv_selector_loaded", "spmv_mlp_forward",
+    "spmv_graph_destroy", "spmv_selector_load", "spmv_selector_loaded",
+    "spmv_selector_load_file", "spmv_mlp_forward",
     "spmv_mlp_backward", "spmv_mlp_adam", "spmv_stream_triad", "spmv_stream_copy",
     "spmv_status_string", "spmv_last_error", "spmv_version",
 )
@@ -90,6 +91,7 @@ def lib():
             "spmv_graph_destroy": [P],
             "spmv_selector_load": [P, P, P, P, P, f32],
             "spmv_selector_loaded": [P],
+            "spmv_selector_load_file": [ctypes.c_char_p],
             "spmv_mlp_forward": [P, P, i32, P, P, P, P],
             "spmv_mlp_backward": [P, P, P, P, P, P, i32, P, P, P],
             "spmv_mlp_adam": [P, P, P, P, i32, f32, f32, f32, f32, P],
@@ -288,6 +290,22 @@ def spmv_selector_loaded() -> bool:
     v = ctypes.c_int(0)
     _check(lib().spmv_selector_loaded(ctypes.byref(v)))
     return bool(v.value)
+
+
+def spmv_selector_load_file(path: str) -> None:
+    _check(lib().spmv_selector_load_file(os.fsencode(path)))
+
+
+def load_selector(path: str | None = None) -> bool:
+    """Load the packaged (or given) selector weights on the current device.
+    Returns False when no weights file exists (plans then use the LDS-block
+    variant by default, or autotune when asked)."""
+    from .selector import DEFAULT_WEIGHTS
+    path = path or DEFAULT_WEIGHTS
+    if not os.path.exists(path):
+        return False
+    spmv_selector_load_file(path)
+    return True
 
 
 def spmv_mlp_forward(theta, X, nb, Y, Z1, Z2, stream=None) -> None:

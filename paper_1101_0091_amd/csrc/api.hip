@@ -1,6 +1,7 @@
 // C ABI of libspmv (declared in include/spmv.h).
 #include <algorithm>
 #include <cmath>
+#include <cstdio>
 #include <cstring>
 #include <string>
 #include <vector>
@@ -555,6 +556,26 @@ int spmv_selector_load(const float* params, const float* mu, const float* sigma,
   g_sel.margin = margin;
   g_sel.have_norm = true;
   return SPMV_OK;
+}
+
+int spmv_selector_load_file(const char* path) {
+  if (!path) return fail(SPMV_ERR_INVALID_ARG, "path is null");
+  FILE* f = std::fopen(path, "rb");
+  if (!f) return fail(SPMV_ERR_INVALID_ARG, std::string("cannot open ") + path);
+  constexpr size_t kFloats = SPMV_MLP_PARAMS + 4 * SPMV_NUM_FEATURES + 1;
+  char magic[8];
+  std::vector<float> buf(kFloats + 1);
+  const size_t m = std::fread(magic, 1, 8, f);
+  const size_t n = std::fread(buf.data(), sizeof(float), kFloats + 1, f);
+  std::fclose(f);
+  if (m != 8 || std::memcmp(magic, "SPMVSEL1", 8) != 0 || n != kFloats)
+    return fail(SPMV_ERR_INVALID_ARG, std::string("malformed selector file ") + path);
+  const float* p = buf.data();
+  const float* mu = p + SPMV_MLP_PARAMS;
+  const float* sd = mu + SPMV_NUM_FEATURES;
+  const float* lo = sd + SPMV_NUM_FEATURES;
+  const float* hi = lo + SPMV_NUM_FEATURES;
+  return spmv_selector_load(p, mu, sd, lo, hi, hi[SPMV_NUM_FEATURES]);
 }
 
 int spmv_selector_loaded(int* loaded) {

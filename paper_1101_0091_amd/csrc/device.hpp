@@ -87,6 +87,38 @@ __device__ __forceinline__ int64_t xcd_remap(int64_t w, int64_t n) {
 // with a lane group whose width G adapts to the rows per block; phase 3
 // streams the remainder of the last row (a row longer than the budget) with
 // the whole workgroup.
+// Strided partial sum over [j0, E) by the lanes of one workgroup: lane t takes
+// j0 + t, j0 + t + kWG, ... in ascending order. Eight positions per lane are
+// loaded before any is used, so a long row costs about E/(8 kWG) round trips.
+template <typename VT, typename BT>
+__device__ __forceinline__ double stream_row_part(const VT* __restrict__ val,
+                                                  const int32_t* __restrict__ ci,
+                                                  const BT* __restrict__ B, int32_t j0,
+                                                  int32_t E) {
+  constexpr int kU = 8;
+  double part = 0.0;
+  for (int32_t jb = j0 + (int32_t)threadIdx.x; jb < E; jb += kU * kWG) {
+    VT v[kU];
+    int32_t c[kU];
+#pragma unroll
+    for (int u = 0; u < kU; ++u) {
+      const int32_t j = jb + u * kWG;
+      if (j < E) {
+        v[u] = ld_stream(val + j);
+        c[u] = ld_stream(ci + j);
+      }
+    }
+    BT b[kU];
+#pragma unroll
+    for (int u = 0; u < kU; ++u)
+      if (jb + u * kWG < E) b[u] = B[c[u]];
+#pragma unroll
+    for (int u = 0; u < kU; ++u)
+      if (jb + u * kWG < E) part = fma(widen(v[u]), widen(b[u]), part);
+  }
+  return part;
+}
+
 struct BlockLds {
   double prod[kBlockBudget];
   double wsum[kWG / 64];
@@ -175,10 +207,7 @@ __device__ __forceinline__ void lds_block(BlockLds& L, const int32_t* __restrict
 
   // phase 3: remainder of a long last row, streamed by the whole workgroup
   if (tail) {
-    double part = 0.0;
-    for (int32_t j = cend + tid; j < E; j += kWG)
-      part = fma(widen(ld_stream(val + j)), widen(B[ld_stream(ci + j)]), part);
-    part = group_sum<64>(part);
+    const double part = group_sum<64>(stream_row_part<VT, BT>(val, ci, B, cend, E));
     if ((tid & 63) == 0) L.wsum[tid >> 6] = part;
     __syncthreads();
     if (tid == 0)

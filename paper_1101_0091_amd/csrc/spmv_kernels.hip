@@ -84,10 +84,7 @@ __global__ __launch_bounds__(kWG) void k_block_row(int32_t nrows, const int32_t*
   __shared__ double wsum[kWG / 64];
   const int32_t r = list[blockIdx.x];
   const int32_t s = rp[r], e = rp[r + 1];
-  double part = 0.0;
-  for (int32_t j = s + threadIdx.x; j < e; j += kWG)
-    part = fma(widen(ld_stream(val + j)), widen(B[ld_stream(ci + j)]), part);
-  part = group_sum<64>(part);
+  const double part = group_sum<64>(dev::stream_row_part<VT, BT>(val, ci, B, s, e));
   if ((threadIdx.x & 63) == 0) wsum[threadIdx.x >> 6] = part;
   __syncthreads();
   if (threadIdx.x == 0) C[r] = (wsum[0] + wsum[1]) + (wsum[2] + wsum[3]);

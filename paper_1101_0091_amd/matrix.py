@@ -5,7 +5,8 @@ from __future__ import annotations
 
 import numpy as np
 
-from . import (SPMV_F32, SPMV_F64, dtype_code, spmm_apply, spmv_apply, spmv_batch_apply,
+from . import (SPMV_F32, SPMV_F64, SPMV_SELECT_DEFAULT, SPMV_SELECT_MLP, dtype_code,
+               load_selector, spmv_selector_loaded, spmm_apply, spmv_apply, spmv_batch_apply,
                spmv_batch_apply_each, spmv_batch_create, spmv_batch_destroy,
                spmv_batch_get_num_tiles, spmv_batch_workspace_size, spmv_create, spmv_destroy,
                spmv_get_features, spmv_get_num_blocks, spmv_get_variant, spmv_set_variant,
@@ -31,6 +32,10 @@ class CRSMatrix:
         import torch
         self.n_rows, self.n_cols = int(n_rows), int(n_cols)
         vdt = val_dtype or torch.float64
+        mode = int(flags) & 0xFF
+        if mode in (SPMV_SELECT_DEFAULT, SPMV_SELECT_MLP) and not spmv_selector_loaded():
+            with torch.cuda.device(torch.device(device)):
+                load_selector()
         self.row_ptr = _dev(row_ptr, torch.int32, device)
         self.col_idx = _dev(col_idx, torch.int32, device)
         self.val = _dev(val, vdt, device)

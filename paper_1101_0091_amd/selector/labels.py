@@ -1,0 +1,83 @@
+"""Label run for the kernel-variant selector: time every variant on the
+seeded matrix collection (N log-uniform in [1e4, 2e7]; uniform, power-law
+or banded rows) and append one JSON line per matrix. Resumable: matrices
+already in the output file are skipped.
+
+    python -m paper_1101_0091_amd.selector.labels --out FILE [--start 0 --stop 512]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+SEED = 5
+NLO, NHI = 1e4, 2e7
+
+
+def time_variants(M, Bd, C, reps=7, warmup=2):
+    import numpy as np
+    import torch
+
+    import paper_1101_0091_amd as pkg
+    s = torch.cuda.current_stream()
+    out = []
+    for v in range(pkg.SPMV_NUM_VARIANTS):
+        M.variant = v
+        for _ in range(warmup):
+            M.apply(Bd, C)
+        ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+              for _ in range(reps)]
+        for a, b in ev:
+            a.record(s)
+            M.apply(Bd, C)
+            b.record(s)
+        torch.cuda.synchronize()
+        out.append(float(np.median([a.elapsed_time(b) for a, b in ev])) * 1000.0)
+    return out
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--out", required=True)
+    ap.add_argument("--start", type=int, default=0)
+    ap.add_argument("--stop", type=int, default=512)
+    args = ap.parse_args(argv)
+    import torch
+
+    import crsgen
+    import paper_1101_0091_amd as pkg
+    done = set()
+    if os.path.exists(args.out):
+        for line in open(args.out):
+            try:
+                done.add(json.loads(line)["id"])
+            except (ValueError, KeyError):
+                pass
+    dev = torch.device("cuda:0")
+    for i in range(args.start, args.stop):
+        if i in done:
+            continue
+        t0 = time.time()
+        A, prm = crsgen.family_matrix(SEED, i, NLO, NHI)
+        B = crsgen.uniform_vec(A.n_cols, SEED)
+        tg = time.time() - t0
+        M = pkg.CRSMatrix.from_crs(A, flags=pkg.SPMV_FLAG_VARIANT(4), device=dev)
+        Bd = torch.from_numpy(B).to(dev)
+        C = torch.empty(A.n_rows, dtype=torch.float64, device=dev)
+        us = time_variants(M, Bd, C)
+        rec = {"id": i, "n": A.n_rows, "nnz": A.nnz, "family": crsgen.FAMILY_NAMES[prm["family"]],
+               "width": prm["width"], "features": [float(x) for x in M.features],
+               "us": [round(t, 3) for t in us], "gen_s": round(tg, 2)}
+        with open(args.out, "a") as f:
+            f.write(json.dumps(rec) + "\n")
+        print(f"[labels] {i} n={A.n_rows} nnz={A.nnz} {rec['family']} best=V{us.index(min(us))} "
+              f"us={rec['us']} ({time.time() - t0:.1f}s)", flush=True)
+        del M, Bd, C, A
+        torch.cuda.empty_cache()
+
+
+if __name__ == "__main__":
+    sys.exit(main())

@@ -148,3 +148,27 @@ def test_selector_in_create_matches_oracle_forward():
     M2 = pkg.CRSMatrix.from_crs(A, flags=pkg.SPMV_SELECT_MLP, device=DEV)
     t = pkg.spmv_get_autotune_times(M2.handle)
     assert M2.variant == int(np.argmin(t))
+
+
+def test_packaged_selector_choice_matches_oracle():
+    """With the trained weights, plan creation picks argmin of the network
+    output; the oracle network on the oracle features picks the same variant
+    unless its best two outputs are within float32 noise."""
+    import os
+    from paper_1101_0091_amd.selector import DEFAULT_WEIGHTS, unpack_weights
+    if not os.path.exists(DEFAULT_WEIGHTS):
+        pytest.skip("no trained weights")
+    pkg.load_selector(DEFAULT_WEIGHTS)
+    theta, mu, sigma, lo, hi, margin = unpack_weights(DEFAULT_WEIGHTS)
+    agree = 0
+    for idx in range(12):
+        A, _ = crsgen.family_matrix(9, idx, 2e3, 3e5)
+        M = pkg.CRSMatrix.from_crs(A, device=DEV)
+        f = oracle.row_features(A.n_rows, A.row_ptr, A.col_idx)
+        x = ((f.astype(np.float32) - mu) / sigma).astype(np.float64)
+        y = mlp.forward(theta.astype(np.float64), x[None, :])[0][0]
+        srt = np.sort(y)
+        if srt[1] - srt[0] > 1e-3:
+            assert M.variant == int(np.argmin(y)), (idx, M.variant, y)
+            agree += 1
+    assert agree >= 6
