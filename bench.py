@@ -235,7 +235,54 @@ def run_extra(A, B, M, pkg, pm, dev, stream, args):
                         "mixed_gflops": round(pm.gflops(L.nnz, t32, k), 1)}
     ex["spmm_laplace2d_256"] = spmm
     log(f"spmm: {spmm}")
+    ex["batch_4096"] = run_batch(pkg, pm, dev, stream)
     return ex
+
+
+def run_batch(pkg, pm, dev, stream):
+    """Uneven batch: 4096 seeded matrices, N log-uniform in [100, 5000]."""
+    import numpy as np
+    import torch
+
+    import crsgen
+    log("batch: generating 4096 small matrices")
+    mats = [crsgen.family_matrix(6, i, 100, 5000)[0] for i in range(4096)]
+    Bt = pkg.Batch(mats, device=dev)
+    nnz, rows = int(Bt.nnz.sum()), int(Bt.n_rows.sum())
+    comp = sum(pm.compulsory_bytes(m.n_rows, m.n_cols, m.nnz) for m in mats)
+    B_all = torch.from_numpy(crsgen.uniform_vec(int(Bt.n_cols.sum()), 6)).to(dev)
+    C_all = torch.empty(rows, dtype=torch.float64, device=dev)
+    Bd, Cd, bh, ch = Bt.pointers(B_all, C_all)
+    res = {"count": 4096, "rows": rows, "nnz": nnz, "tiles": Bt.ntiles}
+
+    def rec(name, fn, steps=20):
+        per, _ = time_launches(fn, steps, 3, stream)
+        t = float(np.median(per)) / 1000
+        res[name] = {"us": round(t * 1e6, 1), "eff_gbs": round(comp / t / 1e9, 1),
+                     "gflops": round(pm.gflops(nnz, t), 1)}
+
+    for mode, name in ((pkg.SPMV_BATCH_DYNAMIC, "persistent_dynamic"),
+                       (pkg.SPMV_BATCH_STATIC, "persistent_static"),
+                       (pkg.SPMV_BATCH_TILE_GRID, "one_launch_tile_grid")):
+        Bt.set_mode(mode)
+        rec(name, lambda: Bt.apply(Bd, Cd))
+    Bt.set_mode(pkg.SPMV_BATCH_TILE_GRID)
+    rec("separate_launches_4096", lambda: Bt.apply_each(bh, ch), steps=5)
+    s = torch.cuda.Stream()
+    torch.cuda.synchronize()
+    pkg.spmv_graph_begin(s)
+    Bt.apply_each(bh, ch, stream=s)
+    g_each = pkg.spmv_graph_end(s)
+    pkg.spmv_graph_begin(s)
+    Bt.apply(Bd, Cd, stream=s)
+    g_one = pkg.spmv_graph_end(s)
+    torch.cuda.synchronize()
+    rec("graph_of_4096_launches", lambda: pkg.spmv_graph_launch(g_each, stream), steps=5)
+    rec("graph_of_persistent", lambda: pkg.spmv_graph_launch(g_one, stream))
+    pkg.spmv_graph_destroy(g_each)
+    pkg.spmv_graph_destroy(g_one)
+    log(f"batch: {res}")
+    return res
 
 
 def cpu_baseline(A, B):

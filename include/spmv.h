@@ -169,6 +169,18 @@ int spmv_batch_apply(spmv_batch_handle h, const void* const* Bs, double* const* 
 int spmv_batch_apply_each(spmv_batch_handle h, const void* const* Bs_host,
                           double* const* Cs_host, int b_dtype, void* stream);
 int spmv_batch_get_num_tiles(spmv_batch_handle h, int64_t* ntiles);
+/* Launch shape of spmv_batch_apply (one kernel launch in every mode):
+ *  SPMV_BATCH_TILE_GRID (default) one workgroup per tile; the hardware
+ *                       dispatcher balances the uneven tiles
+ *  SPMV_BATCH_DYNAMIC   persistent grid sized to the device; workgroups
+ *                       claim tiles from a counter in the workspace that
+ *                       the last workgroup resets, so applies of one batch
+ *                       must not overlap in time
+ *  SPMV_BATCH_STATIC    persistent grid; each workgroup owns a contiguous
+ *                       range of tiles (no counters)
+ * All three give bitwise-identical results. */
+typedef enum { SPMV_BATCH_DYNAMIC = 0, SPMV_BATCH_STATIC = 1, SPMV_BATCH_TILE_GRID = 2 } spmv_batch_mode;
+int spmv_batch_set_mode(spmv_batch_handle h, int mode);
 int spmv_batch_destroy(spmv_batch_handle h);
 
 /* ------------------------------------------------------------- HIP graphs */

@@ -27,6 +27,7 @@ VARIANTS = ("V0_thread_row", "V1_lanes4", "V2_lanes16", "V3_wave_row", "V4_lds_b
 SPMV_NUM_VARIANTS = 6
 SPMV_SELECT_DEFAULT, SPMV_SELECT_MLP, SPMV_SELECT_AUTOTUNE, SPMV_SELECT_FIXED = 0, 1, 2, 3
 SPMV_FLAG_SKIP_VALIDATE = 0x10000
+SPMV_BATCH_DYNAMIC, SPMV_BATCH_STATIC, SPMV_BATCH_TILE_GRID = 0, 1, 2
 SPMV_NUM_FEATURES = 16
 SPMV_MLP_PARAMS = 5638
 
@@ -34,7 +35,7 @@ EXPORTS = (
     "spmv_workspace_size", "spmv_create", "spmv_apply", "spmm_apply", "spmv_get_variant",
     "spmv_set_variant", "spmv_get_features", "spmv_get_predictions", "spmv_get_autotune_times",
     "spmv_get_num_blocks", "spmv_destroy", "spmv_batch_workspace_size", "spmv_batch_create",
-    "spmv_batch_apply", "spmv_batch_apply_each", "spmv_batch_get_num_tiles",
+    "spmv_batch_apply", "spmv_batch_apply_each", "spmv_batch_get_num_tiles", "spmv_batch_set_mode",
     "spmv_batch_destroy", "spmv_graph_begin", "spmv_graph_end", "spmv_graph_launch",
     "spmv_graph_destroy", "spmv_selector_load", "spmv_selector_loaded",
     "spmv_selector_load_file", "spmv_mlp_forward",
@@ -84,6 +85,7 @@ def lib():
             "spmv_batch_apply": [P, P, P, ctypes.c_int, P],
             "spmv_batch_apply_each": [P, P, P, ctypes.c_int, P],
             "spmv_batch_get_num_tiles": [P, P],
+            "spmv_batch_set_mode": [P, ctypes.c_int],
             "spmv_batch_destroy": [P],
             "spmv_graph_begin": [P],
             "spmv_graph_end": [P, P],
@@ -257,6 +259,10 @@ def spmv_batch_get_num_tiles(h) -> int:
     n = ctypes.c_int64(0)
     _check(lib().spmv_batch_get_num_tiles(h, ctypes.byref(n)))
     return int(n.value)
+
+
+def spmv_batch_set_mode(h, mode: int) -> None:
+    _check(lib().spmv_batch_set_mode(h, int(mode)))
 
 
 def spmv_batch_destroy(h) -> None:

@@ -346,7 +346,7 @@ BatchLayout batch_layout(int32_t count, int64_t max_tiles) {
   BatchLayout L;
   size_t o = 0;
   L.err = o;
-  o += 256;
+  o += 256;  // err[2] at 0, tile counters[2] at 128
   L.tiles = o;
   o += align256(sizeof(int32_t) * 6 * (size_t)std::max<int64_t>(max_tiles, 1));
   L.toff = o;
@@ -411,6 +411,7 @@ int spmv_batch_create(spmv_batch_handle* h, int32_t count, const int64_t* n_rows
   b.tiles = reinterpret_cast<int32_t*>(ws + L.tiles);
   b.ntiles = ntiles;
   b.err = reinterpret_cast<int32_t*>(ws + L.err);
+  b.counters = reinterpret_cast<unsigned int*>(ws + L.err + 128);
   int dev = 0;
   hipGetDevice(&dev);
   b.grid = batch_grid(dev);
@@ -439,6 +440,7 @@ int spmv_batch_create(spmv_batch_handle* h, int32_t count, const int64_t* n_rows
     if (e != hipSuccess) st = hip_fail(e, "batch init");
   }
   if (!st) st = launch_batch_build(b, d_toff, d_nr, d_nc, d_nz, s);
+  if (!st) st = launch_counters_init(b.counters, s);
   int32_t herr[2] = {0, 0};
   if (!st) {
     e = hipMemcpyAsync(herr, b.err, sizeof(herr), hipMemcpyDeviceToHost, s);
@@ -478,6 +480,14 @@ int spmv_batch_apply_each(spmv_batch_handle h, const void* const* Bs_host,
                                 nullptr, Bs_host[m], Cs_host[m], as_stream(stream));
     if (st) return st;
   }
+  return SPMV_OK;
+}
+
+int spmv_batch_set_mode(spmv_batch_handle h, int mode) {
+  if (!h) return fail(SPMV_ERR_INVALID_ARG, "handle is null");
+  if (mode < SPMV_BATCH_DYNAMIC || mode > SPMV_BATCH_TILE_GRID)
+    return fail(SPMV_ERR_INVALID_ARG, "unknown batch mode");
+  h->b.mode = mode;
   return SPMV_OK;
 }
 

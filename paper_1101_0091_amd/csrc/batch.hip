@@ -1,10 +1,11 @@
-// Uneven batch of small CRS matrices in one persistent launch.
+// Uneven batch of small CRS matrices in one launch.
 //
 // At creation every matrix is cut into the same nnz-balanced row blocks as
-// the single-matrix LDS variant, and a (matrix, first row, end row) tile
-// list is written to the workspace. The apply kernel runs a fixed grid of
-// workgroups sized to the device; workgroup w owns one contiguous range of
-// tiles, so no counters or atomics are needed and the launch is graph-safe.
+// the single-matrix LDS variant, and a (matrix, rows, nonzero range) tile
+// list is written to the workspace. The apply is a single kernel over that
+// list: one workgroup per tile by default, or a persistent grid sized to the
+// device that walks the list statically or claims tiles from a
+// self-resetting counter. Every mode is graph-safe (no memset nodes).
 #include "common.hpp"
 #include "device.hpp"
 
@@ -74,7 +75,24 @@ __global__ __launch_bounds__(kWG) void k_batch_tiles(int32_t count,
 }
 
 template <typename VT, typename BT>
-__global__ __launch_bounds__(kWG) void k_batch_apply(
+__device__ __forceinline__ void batch_tile(dev::BlockLds& L, const int32_t* __restrict__ tiles,
+                                           int64_t t, const int32_t* const* __restrict__ rps,
+                                           const int32_t* const* __restrict__ cis,
+                                           const void* const* __restrict__ vals,
+                                           const void* const* __restrict__ Bs,
+                                           double* const* __restrict__ Cs,
+                                           const BT* __restrict__ B1, double* __restrict__ C1) {
+  const int32_t* tl = tiles + 6 * t;
+  const int32_t m = tl[0], r0 = tl[1], r1 = tl[2], S = tl[3], E = tl[4];
+  if (r0 >= r1) return;
+  const BT* B = Bs ? static_cast<const BT*>(Bs[m]) : B1;
+  double* C = Cs ? Cs[m] : C1;
+  dev::lds_block<VT, BT>(L, rps[m], cis[m], static_cast<const VT*>(vals[m]), B, C, r0, r1, S, E);
+}
+
+// Persistent, static: workgroup w owns one contiguous range of tiles.
+template <typename VT, typename BT>
+__global__ __launch_bounds__(kWG) void k_batch_static(
     int64_t t0, int64_t t1, const int32_t* __restrict__ tiles,
     const int32_t* const* __restrict__ rps, const int32_t* const* __restrict__ cis,
     const void* const* __restrict__ vals, const void* const* __restrict__ Bs,
@@ -84,15 +102,73 @@ __global__ __launch_bounds__(kWG) void k_batch_apply(
   const int64_t n = t1 - t0, g = gridDim.x;
   const int64_t lo = t0 + (n * w) / g, hi = t0 + (n * (w + 1)) / g;
   for (int64_t t = lo; t < hi; ++t) {
-    const int32_t* tl = tiles + 6 * t;
-    const int32_t m = tl[0], r0 = tl[1], r1 = tl[2], S = tl[3], E = tl[4];
-    if (r0 >= r1) continue;
-    const BT* B = Bs ? static_cast<const BT*>(Bs[m]) : B1;
-    double* C = Cs ? Cs[m] : C1;
     __syncthreads();  // LDS of the previous tile is no longer read
-    dev::lds_block<VT, BT>(L, rps[m], cis[m], static_cast<const VT*>(vals[m]), B, C, r0, r1, S,
-                           E);
+    batch_tile<VT, BT>(L, tiles, t, rps, cis, vals, Bs, Cs, B1, C1);
   }
+}
+
+// Persistent, dynamic: workgroups claim the next tile from a counter. The
+// last workgroup to finish returns both counters to zero, so consecutive
+// launches (and graph replays) need no clearing step.
+template <typename VT, typename BT>
+__global__ __launch_bounds__(kWG) void k_batch_dynamic(
+    int64_t t0, int64_t t1, const int32_t* __restrict__ tiles,
+    const int32_t* const* __restrict__ rps, const int32_t* const* __restrict__ cis,
+    const void* const* __restrict__ vals, const void* const* __restrict__ Bs,
+    double* const* __restrict__ Cs, const BT* __restrict__ B1, double* __restrict__ C1,
+    unsigned int* __restrict__ counters) {
+  __shared__ dev::BlockLds L;
+  __shared__ int64_t claim;
+  for (;;) {
+    __syncthreads();  // previous tile done with LDS and with `claim`
+    if (threadIdx.x == 0) claim = t0 + (int64_t)atomicAdd(&counters[0], 1u);
+    __syncthreads();
+    const int64_t t = claim;
+    if (t >= t1) break;
+    batch_tile<VT, BT>(L, tiles, t, rps, cis, vals, Bs, Cs, B1, C1);
+  }
+  if (threadIdx.x == 0) {
+    __threadfence();
+    if (atomicAdd(&counters[1], 1u) == gridDim.x - 1) {
+      atomicExch(&counters[0], 0u);
+      atomicExch(&counters[1], 0u);
+    }
+  }
+}
+
+// One workgroup per tile (no persistence; the hardware dispatcher balances).
+template <typename VT, typename BT>
+__global__ __launch_bounds__(kWG) void k_batch_tilegrid(
+    int64_t t0, int64_t t1, const int32_t* __restrict__ tiles,
+    const int32_t* const* __restrict__ rps, const int32_t* const* __restrict__ cis,
+    const void* const* __restrict__ vals, const void* const* __restrict__ Bs,
+    double* const* __restrict__ Cs, const BT* __restrict__ B1, double* __restrict__ C1) {
+  __shared__ dev::BlockLds L;
+  const int64_t t = t0 + dev::xcd_remap(blockIdx.x, t1 - t0);
+  batch_tile<VT, BT>(L, tiles, t, rps, cis, vals, Bs, Cs, B1, C1);
+}
+
+template <typename VT, typename BT>
+int batch_launch(const Batch& b, int64_t t0, int64_t t1, const void* const* Bs,
+                 double* const* Cs, const void* B1v, double* C1, hipStream_t s) {
+  const BT* B1 = static_cast<const BT*>(B1v);
+  const int64_t n = t1 - t0;
+  const int64_t pgrid = std::min<int64_t>(b.grid, n);
+  switch (b.mode) {
+    case SPMV_BATCH_STATIC:
+      k_batch_static<VT, BT><<<(unsigned)pgrid, kWG, 0, s>>>(t0, t1, b.tiles, b.row_ptrs,
+                                                             b.col_idxs, b.vals, Bs, Cs, B1, C1);
+      break;
+    case SPMV_BATCH_TILE_GRID:
+      k_batch_tilegrid<VT, BT><<<(unsigned)n, kWG, 0, s>>>(t0, t1, b.tiles, b.row_ptrs,
+                                                           b.col_idxs, b.vals, Bs, Cs, B1, C1);
+      break;
+    default:
+      k_batch_dynamic<VT, BT><<<(unsigned)pgrid, kWG, 0, s>>>(
+          t0, t1, b.tiles, b.row_ptrs, b.col_idxs, b.vals, Bs, Cs, B1, C1, b.counters);
+  }
+  SPMV_HIP(hipGetLastError());
+  return SPMV_OK;
 }
 
 }  // namespace
@@ -117,15 +193,17 @@ int launch_batch_build(Batch& b, const int64_t* toff, const int64_t* nr, const i
 int launch_batch_apply(const Batch& b, int64_t t0, int64_t t1, const void* const* Bs,
                        double* const* Cs, const void* B1, double* C1, hipStream_t s) {
   if (t1 <= t0) return SPMV_OK;
-  int64_t grid = std::min<int64_t>(b.grid, t1 - t0);
-  if (b.vdt == SPMV_F64)
-    k_batch_apply<double, double><<<(unsigned)grid, kWG, 0, s>>>(
-        t0, t1, b.tiles, b.row_ptrs, b.col_idxs, b.vals, Bs, Cs,
-        static_cast<const double*>(B1), C1);
-  else
-    k_batch_apply<float, float><<<(unsigned)grid, kWG, 0, s>>>(
-        t0, t1, b.tiles, b.row_ptrs, b.col_idxs, b.vals, Bs, Cs, static_cast<const float*>(B1),
-        C1);
+  if (b.vdt == SPMV_F64) return batch_launch<double, double>(b, t0, t1, Bs, Cs, B1, C1, s);
+  return batch_launch<float, float>(b, t0, t1, Bs, Cs, B1, C1, s);
+}
+
+__global__ void k_counters_init(unsigned int* c) {
+  c[0] = 0u;
+  c[1] = 0u;
+}
+
+int launch_counters_init(unsigned int* c, hipStream_t s) {
+  k_counters_init<<<1, 1, 0, s>>>(c);
   SPMV_HIP(hipGetLastError());
   return SPMV_OK;
 }

@@ -77,6 +77,8 @@ struct Batch {
   int32_t* tiles = nullptr;   // device int32[6 * ntiles]: matrix, r0, r1, S, E, pad
   int64_t ntiles = 0;
   int32_t* err = nullptr;     // device
+  unsigned int* counters = nullptr;  // device [2]: next tile, finished workgroups
+  int mode = SPMV_BATCH_TILE_GRID;
   int64_t* tile_offset_host = nullptr;  // host [count+1]
   const int32_t** rp_host = nullptr;    // host copies of the device pointer arrays
   const int32_t** ci_host = nullptr;
@@ -119,6 +121,7 @@ int launch_batch_build(Batch& b, const int64_t* tile_offset_dev, const int64_t* 
 int launch_batch_apply(const Batch& b, int64_t t0, int64_t t1, const void* const* Bs,
                        double* const* Cs, const void* B1, double* C1, hipStream_t s);
 int batch_grid(int device);
+int launch_counters_init(unsigned int* c, hipStream_t s);
 // mlp.hip
 int launch_mlp_forward(const float* theta, const float* X, int nb, float* Y, float* Z1,
                        float* Z2, hipStream_t s);

@@ -7,7 +7,7 @@ import numpy as np
 
 from . import (SPMV_F32, SPMV_F64, SPMV_SELECT_DEFAULT, SPMV_SELECT_MLP, dtype_code,
                load_selector, spmv_selector_loaded, spmm_apply, spmv_apply, spmv_batch_apply,
-               spmv_batch_apply_each, spmv_batch_create, spmv_batch_destroy,
+               spmv_batch_apply_each, spmv_batch_create, spmv_batch_destroy, spmv_batch_set_mode,
                spmv_batch_get_num_tiles, spmv_batch_workspace_size, spmv_create, spmv_destroy,
                spmv_get_features, spmv_get_num_blocks, spmv_get_variant, spmv_set_variant,
                spmv_workspace_size)
@@ -141,6 +141,9 @@ class Batch:
         cs = C_all.data_ptr() + 8 * self.row_off[:-1]
         return (torch.tensor(bs, dtype=torch.int64, device=B_all.device),
                 torch.tensor(cs, dtype=torch.int64, device=B_all.device), bs, cs)
+
+    def set_mode(self, mode: int) -> None:
+        spmv_batch_set_mode(self.handle, mode)
 
     def apply(self, Bs_dev, Cs_dev, b_code=None, stream=None):
         spmv_batch_apply(self.handle, Bs_dev, Cs_dev, self.code if b_code is None else b_code,

@@ -211,6 +211,12 @@ def test_batch_vs_oracle_and_each(dt):
     C_all.fill_(float("nan"))
     Bt.apply_each(bh, ch)
     assert torch.equal(C_all, C1)  # same tiles, same order: bitwise
+    for mode in (pkg.SPMV_BATCH_STATIC, pkg.SPMV_BATCH_TILE_GRID, pkg.SPMV_BATCH_DYNAMIC):
+        Bt.set_mode(mode)
+        for _ in range(3):  # repeated launches: the dynamic counters reset themselves
+            C_all.fill_(float("nan"))
+            Bt.apply(Bd, Cd)
+            assert torch.equal(C_all, C1), mode
 
 
 def test_graph_replay_matches_eager():
