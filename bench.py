@@ -235,8 +235,109 @@ def run_extra(A, B, M, pkg, pm, dev, stream, args):
                         "mixed_gflops": round(pm.gflops(L.nnz, t32, k), 1)}
     ex["spmm_laplace2d_256"] = spmm
     log(f"spmm: {spmm}")
+    ex["split_shard"] = run_split(A, B, pkg, pm, dev, stream)
     ex["batch_4096"] = run_batch(pkg, pm, dev, stream)
+    ex["laplace2d_256"] = run_small(pkg, pm, dev, stream)
+    ex["mesh3d_280_permuted"] = run_mesh(pkg, pm, dev, stream)
     return ex
+
+
+def run_split(A, B, pkg, pm, dev, stream):
+    """The split product of eq. (2) on one shard of the workload at its real
+    shape: rows [3N/8, 4N/8) of 8 row shards, local columns = the same range
+    (the columns that shard would own). Compared with the unsplit product of
+    the same rows; the model's penalty is eq. (2) / eq. (1) at kappa = 0."""
+    import numpy as np
+    import torch
+    n = A.n_rows
+    r0, r1 = 3 * n // 8, 4 * n // 8
+    s0, s1 = int(A.row_ptr[r0]), int(A.row_ptr[r1])
+    rp = (A.row_ptr[r0:r1 + 1] - A.row_ptr[r0]).astype(np.int32)
+    ci, va = A.col_idx[s0:s1], A.val[s0:s1]
+    rows, nnz = r1 - r0, s1 - s0
+    U = pkg.CRSMatrix(rows, n, rp, ci, va, flags=pkg.SPMV_FLAG_VARIANT(4), device=dev)
+    S = pkg.SplitMatrix(rows, n, rp, ci, va, r0, r1, device=dev)
+    Bd = torch.from_numpy(B).to(dev)
+    C = torch.empty(rows, dtype=torch.float64, device=dev)
+    res = {"rows": rows, "nnz": nnz, "nnz_local": S.nnz_local, "nnz_remote": S.nnz_remote}
+    for name, fn in (("unsplit_us", lambda: U.apply(Bd, C)),
+                     ("split_both_us", lambda: S.apply(Bd, C)),
+                     ("split_pass0_us", lambda: S.apply(Bd, C, pass_=0)),
+                     ("split_pass1_us", lambda: S.apply(Bd, C, pass_=1))):
+        per, _ = time_launches(fn, 50, 5, stream)
+        res[name] = round(float(np.median(per)) * 1000, 2)
+    nnzr = nnz / rows
+    res["measured_penalty"] = round(res["split_both_us"] / res["unsplit_us"] - 1, 4)
+    res["eq2_over_eq1_penalty"] = round(pm.split_penalty(nnzr), 4)
+    # GPU byte form: the split adds a second row_ptr (4 B/row) and a C read + write (16 B/row)
+    base = 12 * nnz + 4 * (rows + 1) + 8 * rows + 8 * rows
+    res["gpu_model_penalty"] = round((base + 4 * (rows + 1) + 16 * rows) / base - 1, 4)
+    log(f"split: {res}")
+    del U, S
+    torch.cuda.empty_cache()
+    return res
+
+
+def run_small(pkg, pm, dev, stream):
+    """The 2D Laplacian (256^2): fits in cache, so report warm (back to back)
+    and cold (a 1 GiB buffer written between products evicts it)."""
+    import numpy as np
+    import torch
+
+    import crsgen
+    L = crsgen.laplace2d(256)
+    M = pkg.CRSMatrix.from_crs(L, flags=pkg.SPMV_SELECT_AUTOTUNE, device=dev)
+    Bd = torch.from_numpy(crsgen.uniform_vec(L.n_cols, 1)).to(dev)
+    C = torch.empty(L.n_rows, dtype=torch.float64, device=dev)
+    comp = pm.compulsory_bytes(L.n_rows, L.n_cols, L.nnz)
+    per, _ = time_launches(lambda: pkg.spmv_apply(M.handle, Bd, pkg.SPMV_F64, C), 50, 5, stream)
+    warm = float(np.median(per)) / 1000
+    flush = torch.empty(1 << 27, dtype=torch.float64, device=dev)
+    cold = []
+    for _ in range(20):
+        flush.fill_(1.0)
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record(stream)
+        pkg.spmv_apply(M.handle, Bd, pkg.SPMV_F64, C)
+        b.record(stream)
+        torch.cuda.synchronize()
+        cold.append(a.elapsed_time(b))
+    cold_t = float(np.median(cold)) / 1000
+    res = {"variant": pkg.VARIANTS[M.variant], "warm_us": round(warm * 1e6, 2),
+           "cold_us": round(cold_t * 1e6, 2), "warm_gflops": round(pm.gflops(L.nnz, warm), 1),
+           "cold_gflops": round(pm.gflops(L.nnz, cold_t), 1),
+           "warm_eff_gbs": round(comp / warm / 1e9, 1), "cold_eff_gbs": round(comp / cold_t / 1e9, 1)}
+    log(f"laplace2d_256: {res}")
+    return res
+
+
+def run_mesh(pkg, pm, dev, stream):
+    """The permuted 3D stencil with random extras (N = 21.95M), FP64 and FP32 storage."""
+    import numpy as np
+    import torch
+
+    import crsgen
+    log("generating permuted 3D stencil matrix N=21,952,000")
+    A = crsgen.mesh3d(280, seed=3)[0]
+    B = crsgen.uniform_vec(A.n_cols, 3)
+    res = {"n_rows": A.n_rows, "nnz": A.nnz}
+    C = torch.empty(A.n_rows, dtype=torch.float64, device=dev)
+    for tag, vdt, bdt, code, sv in (("fp64", torch.float64, np.float64, pkg.SPMV_F64, 8),
+                                    ("mixed_fp32_storage", torch.float32, np.float32,
+                                     pkg.SPMV_F32, 4)):
+        M = pkg.CRSMatrix(A.n_rows, A.n_cols, A.row_ptr, A.col_idx, A.val.astype(bdt),
+                          val_dtype=vdt, flags=pkg.SPMV_SELECT_AUTOTUNE, device=dev)
+        Bd = torch.from_numpy(B.astype(bdt)).to(dev)
+        per, _ = time_launches(lambda: pkg.spmv_apply(M.handle, Bd, code, C), 30, 3, stream)
+        t = float(np.median(per)) / 1000
+        eff = pm.effective_gbs(A.n_rows, A.n_cols, A.nnz, t, 1, sv, sv)
+        res[tag] = {"variant": pkg.VARIANTS[M.variant], "kernel_ms": round(t * 1e3, 4),
+                    "gflops": round(pm.gflops(A.nnz, t), 1), "eff_gbs": round(eff, 1),
+                    "pct_of_8tbs": round(100 * eff / HBM_PEAK, 1)}
+        del M, Bd
+        torch.cuda.empty_cache()
+    log(f"mesh: {res}")
+    return res
 
 
 def run_batch(pkg, pm, dev, stream):

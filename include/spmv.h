@@ -48,6 +48,7 @@ extern "C" {
 typedef struct spmv_plan* spmv_handle;        /* one analysed matrix */
 typedef struct spmv_batch* spmv_batch_handle; /* an uneven batch of matrices */
 typedef struct spmv_graph* spmv_graph_handle; /* an instantiated HIP graph */
+typedef struct spmv_split* spmv_split_handle; /* a local/remote split plan */
 
 typedef enum { SPMV_F64 = 0, SPMV_F32 = 1 } spmv_dtype;
 
@@ -143,6 +144,31 @@ int spmv_get_autotune_times(spmv_handle h, double* us);
 /* Number of row blocks of the LDS-block variant (host out). */
 int spmv_get_num_blocks(spmv_handle h, int64_t* nblocks);
 int spmv_destroy(spmv_handle h);
+
+/* ------------------------------------------------------- local/remote split */
+
+/*
+ * The split product of the paper's Sect. 3.1 ("vector mode with naive
+ * overlap"): entries whose column lies in [col_lo, col_hi) are "local", the
+ * others "remote". Pass 0 writes C = A_local*B, pass 1 adds C += A_remote*B,
+ * so C is written twice -- the extra traffic of eq. (2). In a distributed run
+ * pass 0 overlaps the exchange of the remote B entries.
+ * create copies the two parts (original column indices, original order
+ * inside each row) into the caller's workspace; spmv_split_workspace_size
+ * gives the bytes (depends only on n_rows, n_cols, nnz). create validates the
+ * CRS arrays (SPMV_ERR_BAD_CRS) and synchronises `stream`.
+ * apply: pass 0, 1, or -1 for both in order; asynchronous on `stream`.
+ */
+int spmv_split_workspace_size(int64_t n_rows, int64_t n_cols, int64_t nnz, size_t* bytes);
+int spmv_split_create(spmv_split_handle* h, int64_t n_rows, int64_t n_cols, int64_t nnz,
+                      const int32_t* row_ptr, const int32_t* col_idx, const void* val,
+                      int val_dtype, int64_t col_lo, int64_t col_hi, void* workspace,
+                      size_t ws_bytes, void* stream);
+int spmv_split_apply(spmv_split_handle h, int pass, const void* B, int b_dtype, double* C,
+                     void* stream);
+/* Nonzeros in the local and remote parts (host out). */
+int spmv_split_get_nnz(spmv_split_handle h, int64_t* nnz_local, int64_t* nnz_remote);
+int spmv_split_destroy(spmv_split_handle h);
 
 /* ----------------------------------------------------------- uneven batch */
 

@@ -40,7 +40,8 @@ EXPORTS = (
     "spmv_graph_destroy", "spmv_selector_load", "spmv_selector_loaded",
     "spmv_selector_load_file", "spmv_mlp_forward",
     "spmv_mlp_backward", "spmv_mlp_adam", "spmv_stream_triad", "spmv_stream_copy",
-    "spmv_status_string", "spmv_last_error", "spmv_version",
+    "spmv_status_string", "spmv_last_error", "spmv_version", "spmv_split_workspace_size",
+    "spmv_split_create", "spmv_split_apply", "spmv_split_get_nnz", "spmv_split_destroy",
 )
 
 
@@ -99,6 +100,11 @@ def lib():
             "spmv_mlp_adam": [P, P, P, P, i32, f32, f32, f32, f32, P],
             "spmv_stream_triad": [P, P, P, f64, i64, P],
             "spmv_stream_copy": [P, P, i64, P],
+            "spmv_split_workspace_size": [i64, i64, i64, P],
+            "spmv_split_create": [P, i64, i64, i64, P, P, P, ctypes.c_int, i64, i64, P, sz, P],
+            "spmv_split_apply": [P, ctypes.c_int, P, ctypes.c_int, P, P],
+            "spmv_split_get_nnz": [P, P, P],
+            "spmv_split_destroy": [P],
             "spmv_status_string": [ctypes.c_int],
             "spmv_last_error": [],
             "spmv_version": [],
@@ -339,4 +345,33 @@ def spmv_stream_copy(dst, src, n, stream=None) -> None:
     _check(lib().spmv_stream_copy(_ptr(dst), _ptr(src), int(n), _stream(stream)))
 
 
-from .matrix import CRSMatrix, Batch  # noqa: E402,F401
+def spmv_split_workspace_size(n_rows, n_cols, nnz) -> int:
+    out = ctypes.c_size_t(0)
+    _check(lib().spmv_split_workspace_size(n_rows, n_cols, nnz, ctypes.byref(out)))
+    return int(out.value)
+
+
+def spmv_split_create(n_rows, n_cols, nnz, row_ptr, col_idx, val, val_dtype, col_lo, col_hi,
+                      workspace, ws_bytes, stream=None):
+    h = ctypes.c_void_p(0)
+    _check(lib().spmv_split_create(ctypes.byref(h), n_rows, n_cols, nnz, _ptr(row_ptr),
+                                   _ptr(col_idx), _ptr(val), val_dtype, col_lo, col_hi,
+                                   _ptr(workspace), ws_bytes, _stream(stream)))
+    return h
+
+
+def spmv_split_apply(h, pass_, B, b_dtype, C, stream=None) -> None:
+    _check(lib().spmv_split_apply(h, int(pass_), _ptr(B), b_dtype, _ptr(C), _stream(stream)))
+
+
+def spmv_split_get_nnz(h):
+    a, b = ctypes.c_int64(0), ctypes.c_int64(0)
+    _check(lib().spmv_split_get_nnz(h, ctypes.byref(a), ctypes.byref(b)))
+    return int(a.value), int(b.value)
+
+
+def spmv_split_destroy(h) -> None:
+    _check(lib().spmv_split_destroy(h))
+
+
+from .matrix import Batch, CRSMatrix, SplitMatrix  # noqa: E402,F401

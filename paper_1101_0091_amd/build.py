@@ -9,7 +9,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 SO = os.path.join(HERE, "libspmv.so")
-SOURCES = ["api.hip", "analysis.hip", "spmv_kernels.hip", "batch.hip", "mlp.hip", "stream.hip"]
+SOURCES = ["api.hip", "analysis.hip", "spmv_kernels.hip", "batch.hip", "mlp.hip", "stream.hip",
+           "split.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 FLAGS = [

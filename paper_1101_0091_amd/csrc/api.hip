@@ -140,6 +140,9 @@ struct spmv_batch {
 struct spmv_graph {
   hipGraphExec_t exec = nullptr;
 };
+struct spmv_split {
+  Plan loc, rem;
+};
 
 extern "C" {
 
@@ -169,11 +172,12 @@ int spmv_workspace_size(int64_t n_rows, int64_t n_cols, int64_t nnz, uint32_t fl
   return SPMV_OK;
 }
 
-int spmv_create(spmv_handle* h, int64_t n_rows, int64_t n_cols, int64_t nnz,
-                const int32_t* row_ptr, const int32_t* col_idx, const void* val, int val_dtype,
-                void* workspace, size_t ws_bytes, uint32_t flags, void* stream) {
-  if (!h) return fail(SPMV_ERR_INVALID_ARG, "handle pointer is null");
-  *h = nullptr;
+namespace {
+// Analyse a CRS matrix into `p` (the body of spmv_create; also used for the
+// two parts of a split plan).
+int plan_build(Plan& p, int64_t n_rows, int64_t n_cols, int64_t nnz, const int32_t* row_ptr,
+               const int32_t* col_idx, const void* val, int val_dtype, void* workspace,
+               size_t ws_bytes, uint32_t flags, hipStream_t s) {
   int st = check_shape(n_rows, n_cols, nnz);
   if (st) return st;
   if (!dtype_ok(val_dtype)) return fail(SPMV_ERR_INVALID_ARG, "val_dtype must be SPMV_F64 or SPMV_F32");
@@ -192,10 +196,6 @@ int spmv_create(spmv_handle* h, int64_t n_rows, int64_t n_cols, int64_t nnz,
   if (ws_bytes < L.total)
     return fail(SPMV_ERR_WORKSPACE, "workspace too small: need " + std::to_string(L.total) +
                                         " bytes, got " + std::to_string(ws_bytes));
-  hipStream_t s = as_stream(stream);
-  auto* H = new (std::nothrow) spmv_plan;
-  if (!H) return fail(SPMV_ERR_INVALID_ARG, "host allocation failed");
-  Plan& p = H->p;
   p.n_rows = n_rows;
   p.n_cols = n_cols;
   p.nnz = nnz;
@@ -237,10 +237,7 @@ int spmv_create(spmv_handle* h, int64_t n_rows, int64_t n_cols, int64_t nnz,
     if (hh.err & 2) why += " col_idx out of [0,n_cols);";
     st = fail(SPMV_ERR_BAD_CRS, "invalid CRS:" + why);
   }
-  if (st) {
-    delete H;
-    return st;
-  }
+  if (st) return st;
   std::memcpy(p.features, hh.features, sizeof(p.features));
   for (int b = 0; b < kNumBins; ++b) {
     p.bin_count[b] = hh.bin_count[b];
@@ -262,6 +259,19 @@ int spmv_create(spmv_handle* h, int64_t n_rows, int64_t n_cols, int64_t nnz,
   } else {  // default
     p.variant = p.have_pred ? argmin6(p.pred) : SPMV_V4_LDS_BLOCK;
   }
+  return st;
+}
+}  // namespace
+
+int spmv_create(spmv_handle* h, int64_t n_rows, int64_t n_cols, int64_t nnz,
+                const int32_t* row_ptr, const int32_t* col_idx, const void* val, int val_dtype,
+                void* workspace, size_t ws_bytes, uint32_t flags, void* stream) {
+  if (!h) return fail(SPMV_ERR_INVALID_ARG, "handle pointer is null");
+  *h = nullptr;
+  auto* H = new (std::nothrow) spmv_plan;
+  if (!H) return fail(SPMV_ERR_INVALID_ARG, "host allocation failed");
+  const int st = plan_build(H->p, n_rows, n_cols, nnz, row_ptr, col_idx, val, val_dtype,
+                            workspace, ws_bytes, flags, as_stream(stream));
   if (st) {
     delete H;
     return st;
@@ -503,6 +513,150 @@ int spmv_batch_destroy(spmv_batch_handle h) {
   delete[] h->b.rp_host;
   delete[] h->b.ci_host;
   delete[] h->b.val_host;
+  delete h;
+  return SPMV_OK;
+}
+
+// ------------------------------------------------------------------ split
+
+namespace {
+struct SplitLayout {
+  size_t len_loc = 0, len_rem = 0, rp_loc = 0, rp_rem = 0, partials = 0, ci = 0, val = 0,
+         ws_loc = 0, ws_rem = 0, total = 0;
+  size_t plan_bytes = 0;
+};
+SplitLayout split_layout(int64_t n, int64_t n_cols, int64_t nnz) {
+  SplitLayout L;
+  size_t o = 0;
+  auto take = [&](size_t bytes) {
+    const size_t at = o;
+    o += align256(bytes);
+    return at;
+  };
+  const size_t n1 = (size_t)std::max<int64_t>(n, 1);
+  L.len_loc = take(4 * n1);
+  L.len_rem = take(4 * n1);
+  L.rp_loc = take(4 * (n1 + 1));
+  L.rp_rem = take(4 * (n1 + 1));
+  L.partials = take(4 * (size_t)scan_partials_count(n + 1));
+  L.ci = take(4 * (size_t)std::max<int64_t>(nnz, 1));
+  L.val = take(8 * (size_t)std::max<int64_t>(nnz, 1));
+  L.plan_bytes = plan_layout(n, n_cols, nnz, SPMV_FLAG_VARIANT(SPMV_V4_LDS_BLOCK)).total;
+  L.ws_loc = take(L.plan_bytes);
+  L.ws_rem = take(L.plan_bytes);
+  L.total = o;
+  return L;
+}
+}  // namespace
+
+int spmv_split_workspace_size(int64_t n_rows, int64_t n_cols, int64_t nnz, size_t* bytes) {
+  if (!bytes) return fail(SPMV_ERR_INVALID_ARG, "bytes is null");
+  int st = check_shape(n_rows, n_cols, nnz);
+  if (st) return st;
+  *bytes = split_layout(n_rows, n_cols, nnz).total;
+  return SPMV_OK;
+}
+
+int spmv_split_create(spmv_split_handle* h, int64_t n_rows, int64_t n_cols, int64_t nnz,
+                      const int32_t* row_ptr, const int32_t* col_idx, const void* val,
+                      int val_dtype, int64_t col_lo, int64_t col_hi, void* workspace,
+                      size_t ws_bytes, void* stream) {
+  if (!h) return fail(SPMV_ERR_INVALID_ARG, "handle pointer is null");
+  *h = nullptr;
+  int st = check_shape(n_rows, n_cols, nnz);
+  if (st) return st;
+  if (!dtype_ok(val_dtype)) return fail(SPMV_ERR_INVALID_ARG, "bad val_dtype");
+  if (!row_ptr || (nnz > 0 && (!col_idx || !val)))
+    return fail(SPMV_ERR_INVALID_ARG, "null CRS array");
+  if (col_lo < 0 || col_hi < col_lo || col_hi > n_cols)
+    return fail(SPMV_ERR_INVALID_ARG, "need 0 <= col_lo <= col_hi <= n_cols");
+  const SplitLayout L = split_layout(n_rows, n_cols, nnz);
+  if (!workspace || reinterpret_cast<uintptr_t>(workspace) % 256)
+    return fail(SPMV_ERR_WORKSPACE, "workspace null or not 256-byte aligned");
+  if (ws_bytes < L.total)
+    return fail(SPMV_ERR_WORKSPACE, "workspace too small: need " + std::to_string(L.total));
+  hipStream_t s = as_stream(stream);
+  char* ws = static_cast<char*>(workspace);
+  auto* H = new (std::nothrow) spmv_split;
+  if (!H) return fail(SPMV_ERR_INVALID_ARG, "host allocation failed");
+  // validate the input once, through the local plan's header
+  Plan& v = H->loc;
+  v.n_rows = n_rows;
+  v.n_cols = n_cols;
+  v.nnz = nnz;
+  v.row_ptr = row_ptr;
+  v.col_idx = col_idx;
+  v.hdr = reinterpret_cast<WsHeader*>(ws + L.ws_loc);
+  int32_t herr = 0;
+  st = launch_zero_header(v.hdr, s);
+  if (!st) st = launch_validate(v, s);
+  if (!st) {
+    hipError_t e = hipMemcpyAsync(&herr, &v.hdr->err, sizeof(herr), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) st = hip_fail(e, "split validation readback");
+  }
+  if (!st && herr) st = fail(SPMV_ERR_BAD_CRS, "invalid CRS");
+  int32_t* len_loc = reinterpret_cast<int32_t*>(ws + L.len_loc);
+  int32_t* len_rem = reinterpret_cast<int32_t*>(ws + L.len_rem);
+  int32_t* rp_loc = reinterpret_cast<int32_t*>(ws + L.rp_loc);
+  int32_t* rp_rem = reinterpret_cast<int32_t*>(ws + L.rp_rem);
+  int32_t* partials = reinterpret_cast<int32_t*>(ws + L.partials);
+  int32_t tot[2] = {0, 0};
+  if (!st) st = launch_split_count(n_rows, row_ptr, col_idx, col_lo, col_hi, len_loc, len_rem, s);
+  if (!st) st = launch_exclusive_scan(len_loc, rp_loc, n_rows, partials, s);
+  if (!st) st = launch_exclusive_scan(len_rem, rp_rem, n_rows, partials, s);
+  if (!st) {
+    hipError_t e = hipMemcpyAsync(&tot[0], rp_loc + n_rows, 4, hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(&tot[1], rp_rem + n_rows, 4, hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) st = hip_fail(e, "split size readback");
+  }
+  if (!st && (int64_t)tot[0] + tot[1] != nnz) st = fail(SPMV_ERR_BAD_CRS, "split sizes disagree");
+  const int vb = dtype_bytes(val_dtype);
+  int32_t* ci_loc = reinterpret_cast<int32_t*>(ws + L.ci);
+  int32_t* ci_rem = ci_loc + tot[0];
+  char* val_loc = ws + L.val;
+  char* val_rem = val_loc + (size_t)vb * tot[0];
+  if (!st)
+    st = launch_split_fill(n_rows, row_ptr, col_idx, val, val_dtype, col_lo, col_hi, rp_loc,
+                           rp_rem, ci_loc, val_loc, ci_rem, val_rem, s);
+  const uint32_t fl = SPMV_FLAG_VARIANT(SPMV_V4_LDS_BLOCK) | SPMV_FLAG_SKIP_VALIDATE;
+  if (!st)
+    st = plan_build(H->loc, n_rows, n_cols, tot[0], rp_loc, ci_loc, val_loc, val_dtype,
+                    ws + L.ws_loc, L.plan_bytes, fl, s);
+  if (!st)
+    st = plan_build(H->rem, n_rows, n_cols, tot[1], rp_rem, ci_rem, val_rem, val_dtype,
+                    ws + L.ws_rem, L.plan_bytes, fl, s);
+  if (st) {
+    delete H;
+    return st;
+  }
+  *h = H;
+  return SPMV_OK;
+}
+
+int spmv_split_apply(spmv_split_handle h, int pass, const void* B, int b_dtype, double* C,
+                     void* stream) {
+  if (!h) return fail(SPMV_ERR_INVALID_ARG, "handle is null");
+  if (pass < -1 || pass > 1) return fail(SPMV_ERR_INVALID_ARG, "pass must be -1, 0 or 1");
+  if (b_dtype != h->loc.vdt) return fail(SPMV_ERR_UNSUPPORTED, "b_dtype must equal val_dtype");
+  if ((!B && h->loc.n_cols > 0) || (!C && h->loc.n_rows > 0))
+    return fail(SPMV_ERR_INVALID_ARG, "B or C is null");
+  hipStream_t s = as_stream(stream);
+  int st = SPMV_OK;
+  if (pass <= 0) st = launch_spmv(h->loc, SPMV_V4_LDS_BLOCK, B, C, s);
+  if (!st && pass != 0) st = launch_spmv_accumulate(h->rem, B, C, s);
+  return st;
+}
+
+int spmv_split_get_nnz(spmv_split_handle h, int64_t* nnz_local, int64_t* nnz_remote) {
+  if (!h || !nnz_local || !nnz_remote) return fail(SPMV_ERR_INVALID_ARG, "null argument");
+  *nnz_local = h->loc.nnz;
+  *nnz_remote = h->rem.nnz;
+  return SPMV_OK;
+}
+
+int spmv_split_destroy(spmv_split_handle h) {
   delete h;
   return SPMV_OK;
 }

@@ -115,6 +115,18 @@ int launch_spmv(const Plan& p, int variant, const void* B, double* C, hipStream_
 int launch_spmm(const Plan& p, int k, const void* B, int64_t ldb, double* C, int64_t ldc,
                 hipStream_t s);
 int launch_fill(void* dst, int dtype, int64_t n, double value, hipStream_t s);
+// C += A*B with the LDS-block kernel (second pass of a split product)
+int launch_spmv_accumulate(const Plan& p, const void* B, double* C, hipStream_t s);
+// split.hip
+int launch_split_count(int64_t n, const int32_t* rp, const int32_t* ci, int64_t col_lo,
+                       int64_t col_hi, int32_t* len_loc, int32_t* len_rem, hipStream_t s);
+int launch_exclusive_scan(const int32_t* in, int32_t* out, int64_t n, int32_t* partials,
+                          hipStream_t s);
+int scan_partials_count(int64_t n);
+int launch_split_fill(int64_t n, const int32_t* rp, const int32_t* ci, const void* val, int vdt,
+                      int64_t col_lo, int64_t col_hi, const int32_t* rp_loc,
+                      const int32_t* rp_rem, int32_t* ci_loc, void* val_loc, int32_t* ci_rem,
+                      void* val_rem, hipStream_t s);
 // batch.hip
 int launch_batch_build(Batch& b, const int64_t* tile_offset_dev, const int64_t* n_rows_dev,
                        const int64_t* n_cols_dev, const int64_t* nnz_dev, hipStream_t s);

@@ -125,7 +125,8 @@ struct BlockLds {
   double last_part;
 };
 
-template <int G>
+// ACC: add to C instead of overwriting it (second pass of a split product).
+template <int G, bool ACC>
 __device__ __forceinline__ void block_rows(const BlockLds& L, const int32_t* __restrict__ rp,
                                            int32_t r0, int32_t r1, int32_t S, int32_t cend,
                                            bool tail, double* __restrict__ C,
@@ -145,14 +146,14 @@ __device__ __forceinline__ void block_rows(const BlockLds& L, const int32_t* __r
       if (tail && r == r1 - 1)
         *last_part = sum;
       else
-        C[r] = sum;
+        C[r] = ACC ? C[r] + sum : sum;
     }
   }
 }
 
 // S = row_ptr[r0] and E = row_ptr[r1] come from the block table, so the
 // workgroup's first dependent round trip already yields the stream bounds.
-template <typename VT, typename BT>
+template <typename VT, typename BT, bool ACC = false>
 __device__ __forceinline__ void lds_block(BlockLds& L, const int32_t* __restrict__ rp,
                                           const int32_t* __restrict__ ci,
                                           const VT* __restrict__ val, const BT* __restrict__ B,
@@ -191,27 +192,29 @@ __device__ __forceinline__ void lds_block(BlockLds& L, const int32_t* __restrict
   // phase 2: lane groups of width G reduce rows from LDS
   const int32_t nrows = r1 - r0;
   if (nrows * 64 <= kWG)
-    block_rows<64>(L, rp, r0, r1, S, cend, tail, C, &L.last_part);
+    block_rows<64, ACC>(L, rp, r0, r1, S, cend, tail, C, &L.last_part);
   else if (nrows * 32 <= kWG)
-    block_rows<32>(L, rp, r0, r1, S, cend, tail, C, &L.last_part);
+    block_rows<32, ACC>(L, rp, r0, r1, S, cend, tail, C, &L.last_part);
   else if (nrows * 16 <= kWG)
-    block_rows<16>(L, rp, r0, r1, S, cend, tail, C, &L.last_part);
+    block_rows<16, ACC>(L, rp, r0, r1, S, cend, tail, C, &L.last_part);
   else if (nrows * 8 <= kWG)
-    block_rows<8>(L, rp, r0, r1, S, cend, tail, C, &L.last_part);
+    block_rows<8, ACC>(L, rp, r0, r1, S, cend, tail, C, &L.last_part);
   else if (nrows * 4 <= kWG)
-    block_rows<4>(L, rp, r0, r1, S, cend, tail, C, &L.last_part);
+    block_rows<4, ACC>(L, rp, r0, r1, S, cend, tail, C, &L.last_part);
   else if (nrows * 2 <= kWG)
-    block_rows<2>(L, rp, r0, r1, S, cend, tail, C, &L.last_part);
+    block_rows<2, ACC>(L, rp, r0, r1, S, cend, tail, C, &L.last_part);
   else
-    block_rows<1>(L, rp, r0, r1, S, cend, tail, C, &L.last_part);
+    block_rows<1, ACC>(L, rp, r0, r1, S, cend, tail, C, &L.last_part);
 
   // phase 3: remainder of a long last row, streamed by the whole workgroup
   if (tail) {
     const double part = group_sum<64>(stream_row_part<VT, BT>(val, ci, B, cend, E));
     if ((tid & 63) == 0) L.wsum[tid >> 6] = part;
     __syncthreads();
-    if (tid == 0)
-      C[r1 - 1] = L.last_part + ((L.wsum[0] + L.wsum[1]) + (L.wsum[2] + L.wsum[3]));
+    if (tid == 0) {
+      const double s = L.last_part + ((L.wsum[0] + L.wsum[1]) + (L.wsum[2] + L.wsum[3]));
+      C[r1 - 1] = ACC ? C[r1 - 1] + s : s;
+    }
   }
 }
 

@@ -92,7 +92,7 @@ __global__ __launch_bounds__(kWG) void k_block_row(int32_t nrows, const int32_t*
 }
 
 // ---------------------------------------------------------------- V4
-template <typename VT, typename BT>
+template <typename VT, typename BT, bool ACC>
 __global__ __launch_bounds__(kWG) void k_lds_block(int64_t nblocks, const int2* __restrict__ blocks,
                                                    const int32_t* __restrict__ rp,
                                                    const int32_t* __restrict__ ci,
@@ -103,7 +103,7 @@ __global__ __launch_bounds__(kWG) void k_lds_block(int64_t nblocks, const int2* 
   const int64_t b = dev::xcd_remap(blockIdx.x, nblocks);
   const int2 m0 = blocks[b], m1 = blocks[b + 1];
   if (m0.x >= m1.x) return;
-  dev::lds_block<VT, BT>(L, rp, ci, val, B, C, m0.x, m1.x, m0.y, m1.y);
+  dev::lds_block<VT, BT, ACC>(L, rp, ci, val, B, C, m0.x, m1.x, m0.y, m1.y);
 }
 
 // ---------------------------------------------------------------- SpMM
@@ -225,7 +225,7 @@ int spmv_typed(const Plan& p, int variant, const BT* B, double* C, hipStream_t s
       break;
     case SPMV_V4_LDS_BLOCK:
       if (p.nblocks > 0)
-        k_lds_block<VT, BT><<<(unsigned)p.nblocks, kWG, 0, s>>>(p.nblocks, p.blocks, p.row_ptr,
+        k_lds_block<VT, BT, false><<<(unsigned)p.nblocks, kWG, 0, s>>>(p.nblocks, p.blocks, p.row_ptr,
                                                                 p.col_idx, val, B, C);
       break;
     case SPMV_V5_BINNED: {
@@ -284,7 +284,22 @@ int spmm_lpr(const Plan& p, int k, const BT* B, int64_t ldb, double* C, int64_t 
   return SPMV_OK;
 }
 
+template <typename VT, typename BT>
+int spmv_accumulate_typed(const Plan& p, const BT* B, double* C, hipStream_t s) {
+  if (p.nblocks > 0)
+    k_lds_block<VT, BT, true><<<(unsigned)p.nblocks, kWG, 0, s>>>(
+        p.nblocks, p.blocks, p.row_ptr, p.col_idx, static_cast<const VT*>(p.val), B, C);
+  SPMV_HIP(hipGetLastError());
+  return SPMV_OK;
+}
+
 }  // namespace
+
+int launch_spmv_accumulate(const Plan& p, const void* B, double* C, hipStream_t s) {
+  if (p.vdt == SPMV_F64)
+    return spmv_accumulate_typed<double, double>(p, static_cast<const double*>(B), C, s);
+  return spmv_accumulate_typed<float, float>(p, static_cast<const float*>(B), C, s);
+}
 
 int launch_spmv(const Plan& p, int variant, const void* B, double* C, hipStream_t s) {
   if (p.vdt == SPMV_F64)

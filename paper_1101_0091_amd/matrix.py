@@ -10,7 +10,8 @@ from . import (SPMV_F32, SPMV_F64, SPMV_SELECT_DEFAULT, SPMV_SELECT_MLP, dtype_c
                spmv_batch_apply_each, spmv_batch_create, spmv_batch_destroy, spmv_batch_set_mode,
                spmv_batch_get_num_tiles, spmv_batch_workspace_size, spmv_create, spmv_destroy,
                spmv_get_features, spmv_get_num_blocks, spmv_get_variant, spmv_set_variant,
-               spmv_workspace_size)
+               spmv_split_apply, spmv_split_create, spmv_split_destroy, spmv_split_get_nnz,
+               spmv_split_workspace_size, spmv_workspace_size)
 
 
 def _dev(x, dtype, device):
@@ -156,6 +157,45 @@ class Batch:
     def close(self):
         if getattr(self, "handle", None) is not None:
             spmv_batch_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class SplitMatrix:
+    """Local/remote split of a CRS matrix by a column window [col_lo, col_hi)."""
+
+    def __init__(self, n_rows, n_cols, row_ptr, col_idx, val, col_lo, col_hi, val_dtype=None,
+                 device="cuda", stream=None):
+        import torch
+        vdt = val_dtype or torch.float64
+        self.n_rows, self.n_cols = int(n_rows), int(n_cols)
+        self.row_ptr = _dev(row_ptr, torch.int32, device)
+        self.col_idx = _dev(col_idx, torch.int32, device)
+        self.val = _dev(val, vdt, device)
+        self.code = SPMV_F64 if vdt == torch.float64 else SPMV_F32
+        nnz = int(self.col_idx.numel())
+        self.ws_bytes = spmv_split_workspace_size(self.n_rows, self.n_cols, nnz)
+        self.workspace = torch.empty(self.ws_bytes, dtype=torch.uint8, device=device)
+        self.handle = spmv_split_create(self.n_rows, self.n_cols, nnz, self.row_ptr,
+                                        self.col_idx, self.val, self.code, int(col_lo),
+                                        int(col_hi), self.workspace, self.ws_bytes, stream)
+        self.nnz_local, self.nnz_remote = spmv_split_get_nnz(self.handle)
+
+    def apply(self, B, C=None, pass_=-1, stream=None):
+        import torch
+        if C is None:
+            C = torch.empty(self.n_rows, dtype=torch.float64, device=B.device)
+        spmv_split_apply(self.handle, pass_, B, self.code, C, stream)
+        return C
+
+    def close(self):
+        if getattr(self, "handle", None) is not None:
+            spmv_split_destroy(self.handle)
             self.handle = None
 
     def __del__(self):

@@ -272,3 +272,41 @@ def test_single_matrix_graph_replay():
             assert torch.equal(C, eager), v
             M.apply(Bd)
         pkg.spmv_graph_destroy(g)
+
+
+@pytest.mark.parametrize("name", ["hamiltonian_200k", "mesh3d_48_permuted", "laplace2d_256"])
+def test_fp32_storage_error_vs_fp64_oracle(name):
+    """FP32-stored val and B against the FP64-input oracle. Rounding each
+    input to float32 perturbs every product by at most 2^-23 + 2^-48 of its
+    magnitude; the float64 sums add at most gamma_n on each side, so
+    |C32 - C64| <= (2^-23 + 2^-48 + 2 gamma_n (1 + 2^-23)) S_i. Reports the
+    observed worst ratio and the relative 2-norm error."""
+    A, B = case(name)
+    Cref, S = oracle.spmv(A.n_rows, A.row_ptr, A.col_idx, A.val, B)
+    M = pkg.CRSMatrix(A.n_rows, A.n_cols, A.row_ptr, A.col_idx, A.val.astype(np.float32),
+                      val_dtype=torch.float32, device=DEV)
+    C = M.apply(_gpu(B.astype(np.float32))).cpu().numpy()
+    n = np.diff(A.row_ptr).astype(np.float64)
+    u = 2.0 ** -53
+    gam = n * u / (1 - n * u)
+    tol = (2.0 ** -23 + 2.0 ** -48 + 2 * gam * (1 + 2.0 ** -23)) * S
+    d = np.abs(C - Cref)
+    assert np.all(d <= tol)
+    nz = S > 0
+    print(f"{name}: max |dC|/S = {np.max(d[nz] / S[nz]):.3e}, "
+          f"rel 2-norm = {np.linalg.norm(C - Cref) / np.linalg.norm(Cref):.3e}")
+
+
+def test_spmm_fp32_storage_error_per_column():
+    A = crsgen.laplace2d(256)
+    k = 32
+    Bh = crsgen.uniform_vec(A.n_cols * k, 4).reshape(A.n_cols, k)
+    Cref, S = oracle.spmm(A.n_rows, A.row_ptr, A.col_idx, A.val, Bh)
+    M = pkg.CRSMatrix(A.n_rows, A.n_cols, A.row_ptr, A.col_idx, A.val.astype(np.float32),
+                      val_dtype=torch.float32, device=DEV)
+    C = M.spmm(_gpu(Bh.astype(np.float32))).cpu().numpy()
+    n = np.diff(A.row_ptr).astype(np.float64)[:, None]
+    gam = n * 2.0 ** -53 / (1 - n * 2.0 ** -53)
+    assert np.all(np.abs(C - Cref) <= (2.0 ** -23 + 2.0 ** -48 + 2 * gam * (1 + 2.0 ** -23)) * S)
+    col_err = np.linalg.norm(C - Cref, axis=0) / np.linalg.norm(Cref, axis=0)
+    assert np.all(col_err < 1e-6)
