@@ -209,6 +209,33 @@ typedef enum { SPMV_BATCH_DYNAMIC = 0, SPMV_BATCH_STATIC = 1, SPMV_BATCH_TILE_GR
 int spmv_batch_set_mode(spmv_batch_handle h, int mode);
 int spmv_batch_destroy(spmv_batch_handle h);
 
+/* -------------------------------------------------------------- reordering */
+
+/*
+ * Reverse Cuthill-McKee ordering of a square CRS pattern (HOST arrays; no
+ * device work): perm[new] = old, a permutation of 0..n-1. The graph is the
+ * pattern of A + A^T (symmetric_part = 0) or only the entries present in
+ * both A and A^T (symmetric_part = 1: one-sided long-range entries, such as
+ * random extras, are ignored so they cannot collapse the level structure).
+ * Self loops and columns >= n are ignored. Applying it as A' = P A P^T
+ * narrows the band of A, which improves the locality of the B gathers (the
+ * paper's Sect. 1.3.1 use of RCM). O(nnz log d) time, O(nnz) host memory.
+ * SPMV_ERR_BAD_CRS if row_ptr does not start at 0 or decreases.
+ */
+int spmv_rcm_order(int64_t n, const int32_t* row_ptr, const int32_t* col_idx, int symmetric_part,
+                   int32_t* perm);
+
+/*
+ * Symmetric permutation on the HOST: (row_ptr_out, col_idx_out, val_out) =
+ * P A P^T with perm[new] = old; the entries of each new row are sorted by
+ * their new column (stable for duplicates). Output arrays are caller-owned
+ * host arrays of sizes n+1, nnz, nnz. SPMV_ERR_INVALID_ARG if perm is not a
+ * permutation, SPMV_ERR_BAD_CRS if a column is outside [0, n).
+ */
+int spmv_permute_crs(int64_t n, const int32_t* row_ptr, const int32_t* col_idx, const void* val,
+                     int val_dtype, const int32_t* perm, int32_t* row_ptr_out,
+                     int32_t* col_idx_out, void* val_out);
+
 /* ------------------------------------------------------------- HIP graphs */
 
 /* Start capturing the calls issued on `stream` (thread-local capture mode).

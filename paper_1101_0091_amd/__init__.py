@@ -42,6 +42,7 @@ EXPORTS = (
     "spmv_mlp_backward", "spmv_mlp_adam", "spmv_stream_triad", "spmv_stream_copy",
     "spmv_status_string", "spmv_last_error", "spmv_version", "spmv_split_workspace_size",
     "spmv_split_create", "spmv_split_apply", "spmv_split_get_nnz", "spmv_split_destroy",
+    "spmv_rcm_order", "spmv_permute_crs",
 )
 
 
@@ -105,6 +106,8 @@ def lib():
             "spmv_split_apply": [P, ctypes.c_int, P, ctypes.c_int, P, P],
             "spmv_split_get_nnz": [P, P, P],
             "spmv_split_destroy": [P],
+            "spmv_rcm_order": [i64, P, P, ctypes.c_int, P],
+            "spmv_permute_crs": [i64, P, P, P, ctypes.c_int, P, P, P, P],
             "spmv_status_string": [ctypes.c_int],
             "spmv_last_error": [],
             "spmv_version": [],
@@ -372,6 +375,34 @@ def spmv_split_get_nnz(h):
 
 def spmv_split_destroy(h) -> None:
     _check(lib().spmv_split_destroy(h))
+
+
+def spmv_rcm_order(n, row_ptr, col_idx, symmetric_part: bool = False) -> np.ndarray:
+    """Host arrays in, host permutation out (perm[new] = old)."""
+    rp = np.ascontiguousarray(row_ptr, dtype=np.int32)
+    ci = np.ascontiguousarray(col_idx, dtype=np.int32)
+    perm = np.empty(int(n), dtype=np.int32)
+    _check(lib().spmv_rcm_order(int(n), rp.ctypes.data, ci.ctypes.data, int(bool(symmetric_part)),
+                                perm.ctypes.data))
+    return perm
+
+
+def spmv_permute_crs(n, row_ptr, col_idx, val, perm):
+    """Host P A P^T (perm[new] = old); returns (row_ptr, col_idx, val)."""
+    rp = np.ascontiguousarray(row_ptr, dtype=np.int32)
+    ci = np.ascontiguousarray(col_idx, dtype=np.int32)
+    va = np.ascontiguousarray(val)
+    code = SPMV_F64 if va.dtype == np.float64 else SPMV_F32
+    if va.dtype not in (np.float64, np.float32):
+        raise TypeError(va.dtype)
+    pm = np.ascontiguousarray(perm, dtype=np.int32)
+    rpo = np.empty(int(n) + 1, dtype=np.int32)
+    cio = np.empty_like(ci)
+    vao = np.empty_like(va)
+    _check(lib().spmv_permute_crs(int(n), rp.ctypes.data, ci.ctypes.data, va.ctypes.data, code,
+                                  pm.ctypes.data, rpo.ctypes.data, cio.ctypes.data,
+                                  vao.ctypes.data))
+    return rpo, cio, vao
 
 
 from .matrix import Batch, CRSMatrix, SplitMatrix  # noqa: E402,F401

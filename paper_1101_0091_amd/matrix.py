@@ -203,3 +203,4 @@ class SplitMatrix:
             self.close()
         except Exception:
             pass
+
