@@ -243,6 +243,7 @@ def run_extra(A, B, M, pkg, pm, dev, stream, args):
     ex["split_shard"] = run_split(A, B, pkg, pm, dev, stream)
     ex["batch_4096"] = run_batch(pkg, pm, dev, stream)
     ex["laplace2d_256"] = run_small(pkg, pm, dev, stream)
+    ex["solvers_laplace2d_256"] = run_solvers(pkg, dev)
     ex["mesh3d_280_permuted"] = run_mesh(pkg, pm, dev, stream)
     return ex
 
@@ -319,6 +320,57 @@ def run_rcm(pkg, pm, dev, stream):
         out[name] = res
         log(f"rcm {name}: {res}")
     return out
+
+
+def run_solvers(pkg, dev):
+    """CG (graph-replayed iterations) and Lanczos on the 2D Laplacian, FP64 and
+    FP32 storage: iterations, time per iteration, and the true residual
+    recomputed with an FP64 product."""
+    import numpy as np
+    import torch
+
+    import crsgen
+    L = crsgen.laplace2d(256)
+    n = L.n_rows
+    M64 = pkg.CRSMatrix.from_crs(L, flags=pkg.SPMV_FLAG_VARIANT(4), device=dev)
+    M32 = pkg.CRSMatrix(n, n, L.row_ptr, L.col_idx, L.val.astype(np.float32),
+                        val_dtype=torch.float32, flags=pkg.SPMV_FLAG_VARIANT(4), device=dev)
+    xs = torch.from_numpy(crsgen.uniform_vec(n, 8)).to(dev)
+    b = M64.apply(xs)
+    wsb = pkg.spmv_cg_workspace_size(n)
+    ws = torch.empty(wsb, dtype=torch.uint8, device=dev)
+    s = torch.cuda.Stream()
+    res = {}
+    for tag, M, tol in (("cg_fp64", M64, 1e-10), ("cg_fp32_storage", M32, 1e-5)):
+        for graph in (False, True):
+            x = torch.zeros(n, dtype=torch.float64, device=dev)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            it, rr = pkg.spmv_cg_solve(M.handle, b, x, tol, 5000, 50, graph, ws, wsb, s)
+            torch.cuda.synchronize()
+            t = time.perf_counter() - t0
+            r = (b - M64.apply(x)).double()
+            key = f"{tag}{'_graph' if graph else ''}"
+            res[key] = {"iters": it, "recurrence_relres": rr,
+                        "true_relres": float(torch.linalg.vector_norm(r) /
+                                             torch.linalg.vector_norm(b)),
+                        "us_per_iter": round(1e6 * t / max(it, 1), 2)}
+    k = 300
+    lb = pkg.spmv_lanczos_workspace_size(n, k)
+    lws = torch.empty(lb, dtype=torch.uint8, device=dev)
+    v0 = torch.from_numpy(crsgen.uniform_vec(n, 7)).to(dev)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    al, be = pkg.spmv_lanczos(M64.handle, v0, k, lws, lb)
+    t = time.perf_counter() - t0
+    from scipy.linalg import eigvalsh_tridiagonal
+    th = eigvalsh_tridiagonal(al, be[:-1])
+    c = np.cos(np.pi / 257)
+    res["lanczos_fp64"] = {"steps": k, "us_per_step": round(1e6 * t / k, 2),
+                           "max_ritz_err": float(abs(th[-1] - (4 + 4 * c))),
+                           "min_ritz_err": float(abs(th[0] - (4 - 4 * c)))}
+    log(f"solvers: {res}")
+    return res
 
 
 def run_small(pkg, pm, dev, stream):

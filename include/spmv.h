@@ -145,6 +145,39 @@ int spmv_get_autotune_times(spmv_handle h, double* us);
 int spmv_get_num_blocks(spmv_handle h, int64_t* nblocks);
 int spmv_destroy(spmv_handle h);
 
+/* ----------------------------------------------------------------- solvers */
+
+/*
+ * Conjugate gradients for a symmetric positive definite plan (square): solves
+ * A x = b, x holding the initial guess on entry (device float64 arrays of n).
+ * Every vector operation and scalar stays on the device; an iteration is one
+ * product with the plan's variant (an FP32-storage plan gets a float32 copy of
+ * the search direction; the iteration itself is float64), two fixed-order dot
+ * products and three vector updates. use_graph != 0 captures one iteration in
+ * a HIP graph and replays it (needs a non-null stream). The recurrence
+ * residual ||r||/||b|| is read back every check_every iterations (one sync
+ * each); stops when it is <= tol or after maxit iterations. iters, relres:
+ * host out. workspace: spmv_cg_workspace_size(n) bytes, 256-byte aligned.
+ * Results are bitwise reproducible for a given plan, b and x0.
+ */
+int spmv_cg_workspace_size(int64_t n, size_t* bytes);
+int spmv_cg_solve(spmv_handle h, const double* b, double* x, double tol, int32_t maxit,
+                  int32_t check_every, int32_t use_graph, void* workspace, size_t ws_bytes,
+                  int32_t* iters, double* relres, void* stream);
+
+/*
+ * k steps of the Lanczos recurrence (no reorthogonalisation) from the device
+ * start vector v0 (float64[n], not modified, must be nonzero). Host out:
+ * alpha[0..k-1] (diagonal of T_k) and beta[0..k-1] with beta[j] = beta_{j+1}
+ * (beta[0..k-2] are the off-diagonals of T_k; beta[k-1] is the norm of the
+ * last residual vector). The eigenvalues of T_k approximate the extreme
+ * eigenvalues of a symmetric A. A zero beta (invariant subspace) makes the
+ * following values non-finite. workspace: spmv_lanczos_workspace_size bytes.
+ */
+int spmv_lanczos_workspace_size(int64_t n, int32_t k, size_t* bytes);
+int spmv_lanczos(spmv_handle h, const double* v0, int32_t k, double* alpha, double* beta,
+                 void* workspace, size_t ws_bytes, void* stream);
+
 /* ------------------------------------------------------- local/remote split */
 
 /*

@@ -42,7 +42,8 @@ EXPORTS = (
     "spmv_mlp_backward", "spmv_mlp_adam", "spmv_stream_triad", "spmv_stream_copy",
     "spmv_status_string", "spmv_last_error", "spmv_version", "spmv_split_workspace_size",
     "spmv_split_create", "spmv_split_apply", "spmv_split_get_nnz", "spmv_split_destroy",
-    "spmv_rcm_order", "spmv_permute_crs",
+    "spmv_rcm_order", "spmv_permute_crs", "spmv_cg_workspace_size", "spmv_cg_solve",
+    "spmv_lanczos_workspace_size", "spmv_lanczos",
 )
 
 
@@ -107,6 +108,10 @@ def lib():
             "spmv_split_get_nnz": [P, P, P],
             "spmv_split_destroy": [P],
             "spmv_rcm_order": [i64, P, P, ctypes.c_int, P],
+            "spmv_cg_workspace_size": [i64, P],
+            "spmv_cg_solve": [P, P, P, f64, i32, i32, i32, P, sz, P, P, P],
+            "spmv_lanczos_workspace_size": [i64, i32, P],
+            "spmv_lanczos": [P, P, i32, P, P, P, sz, P],
             "spmv_permute_crs": [i64, P, P, P, ctypes.c_int, P, P, P, P],
             "spmv_status_string": [ctypes.c_int],
             "spmv_last_error": [],
@@ -403,6 +408,37 @@ def spmv_permute_crs(n, row_ptr, col_idx, val, perm):
                                   pm.ctypes.data, rpo.ctypes.data, cio.ctypes.data,
                                   vao.ctypes.data))
     return rpo, cio, vao
+
+
+def spmv_cg_workspace_size(n) -> int:
+    out = ctypes.c_size_t(0)
+    _check(lib().spmv_cg_workspace_size(int(n), ctypes.byref(out)))
+    return int(out.value)
+
+
+def spmv_cg_solve(h, b, x, tol, maxit, check_every, use_graph, workspace, ws_bytes,
+                  stream=None):
+    """Returns (iterations, recurrence relative residual)."""
+    it, rr = ctypes.c_int32(0), ctypes.c_double(0.0)
+    _check(lib().spmv_cg_solve(h, _ptr(b), _ptr(x), float(tol), int(maxit), int(check_every),
+                               int(bool(use_graph)), _ptr(workspace), int(ws_bytes),
+                               ctypes.byref(it), ctypes.byref(rr), _stream(stream)))
+    return int(it.value), float(rr.value)
+
+
+def spmv_lanczos_workspace_size(n, k) -> int:
+    out = ctypes.c_size_t(0)
+    _check(lib().spmv_lanczos_workspace_size(int(n), int(k), ctypes.byref(out)))
+    return int(out.value)
+
+
+def spmv_lanczos(h, v0, k, workspace, ws_bytes, stream=None):
+    """Returns host arrays (alpha[k], beta[k]) of the Lanczos recurrence."""
+    al = np.zeros(int(k), dtype=np.float64)
+    be = np.zeros(int(k), dtype=np.float64)
+    _check(lib().spmv_lanczos(h, _ptr(v0), int(k), al.ctypes.data, be.ctypes.data,
+                              _ptr(workspace), int(ws_bytes), _stream(stream)))
+    return al, be
 
 
 from .matrix import Batch, CRSMatrix, SplitMatrix  # noqa: E402,F401

@@ -517,6 +517,53 @@ int spmv_batch_destroy(spmv_batch_handle h) {
   return SPMV_OK;
 }
 
+// ---------------------------------------------------------------- solvers
+
+int spmv_cg_workspace_size(int64_t n, size_t* bytes) {
+  if (!bytes || n < 0) return fail(SPMV_ERR_INVALID_ARG, "bad argument");
+  *bytes = cg_workspace_bytes(n);
+  return SPMV_OK;
+}
+
+int spmv_cg_solve(spmv_handle h, const double* b, double* x, double tol, int32_t maxit,
+                  int32_t check_every, int32_t use_graph, void* workspace, size_t ws_bytes,
+                  int32_t* iters, double* relres, void* stream) {
+  if (!h || !iters || !relres) return fail(SPMV_ERR_INVALID_ARG, "null argument");
+  const Plan& P = h->p;
+  if (P.n_rows != P.n_cols) return fail(SPMV_ERR_INVALID_ARG, "CG needs a square matrix");
+  if (P.n_rows > 0 && (!b || !x)) return fail(SPMV_ERR_INVALID_ARG, "b or x is null");
+  if (!(tol >= 0.0) || maxit < 0) return fail(SPMV_ERR_INVALID_ARG, "tol >= 0 and maxit >= 0");
+  if (!workspace || reinterpret_cast<uintptr_t>(workspace) % 256 ||
+      ws_bytes < cg_workspace_bytes(P.n_rows))
+    return fail(SPMV_ERR_WORKSPACE, "solver workspace missing, misaligned or too small");
+  int it = 0;
+  double rr = 0.0;
+  const int st = run_cg(P, b, x, tol, maxit, check_every, use_graph != 0, workspace, &it, &rr,
+                        as_stream(stream));
+  *iters = it;
+  *relres = rr;
+  return st;
+}
+
+int spmv_lanczos_workspace_size(int64_t n, int32_t k, size_t* bytes) {
+  if (!bytes || n < 0 || k < 1) return fail(SPMV_ERR_INVALID_ARG, "bad argument");
+  *bytes = lanczos_workspace_bytes(n, k);
+  return SPMV_OK;
+}
+
+int spmv_lanczos(spmv_handle h, const double* v0, int32_t k, double* alpha, double* beta,
+                 void* workspace, size_t ws_bytes, void* stream) {
+  if (!h || !v0 || !alpha || !beta) return fail(SPMV_ERR_INVALID_ARG, "null argument");
+  const Plan& P = h->p;
+  if (P.n_rows != P.n_cols || P.n_rows < 1)
+    return fail(SPMV_ERR_INVALID_ARG, "Lanczos needs a non-empty square matrix");
+  if (k < 1) return fail(SPMV_ERR_INVALID_ARG, "k >= 1");
+  if (!workspace || reinterpret_cast<uintptr_t>(workspace) % 256 ||
+      ws_bytes < lanczos_workspace_bytes(P.n_rows, k))
+    return fail(SPMV_ERR_WORKSPACE, "solver workspace missing, misaligned or too small");
+  return run_lanczos(P, v0, k, alpha, beta, workspace, as_stream(stream));
+}
+
 // ------------------------------------------------------------------ split
 
 namespace {

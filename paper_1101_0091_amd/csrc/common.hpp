@@ -144,6 +144,13 @@ int launch_mlp_adam(float* theta, const float* grad, float* m, float* v, int t, 
                     float b1, float b2, float eps, hipStream_t s);
 int selector_upload(const float* params);
 const float* selector_theta_device();  // null if not loaded on the current device
+// solver.hip
+size_t cg_workspace_bytes(int64_t n);
+size_t lanczos_workspace_bytes(int64_t n, int k);
+int run_cg(const Plan& P, const double* b, double* x, double tol, int maxit, int check_every,
+           bool use_graph, void* ws, int* iters, double* relres, hipStream_t s);
+int run_lanczos(const Plan& P, const double* v0, int k, double* alpha, double* beta, void* ws,
+                hipStream_t s);
 // stream.hip
 int launch_triad(double* a, const double* b, const double* c, double s, int64_t n,
                  hipStream_t st);

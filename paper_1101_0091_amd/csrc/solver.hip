@@ -1,0 +1,364 @@
+// Iterative solvers on top of the CRS product: conjugate gradients and
+// Lanczos, the kind of eigen- and linear solvers whose run time the paper's
+// spMVM dominates (Sect. 1). Every vector operation is a kernel here; the
+// scalars (alpha, beta, norms) stay in device memory, so an iteration is a
+// fixed launch sequence that can be captured into a HIP graph. Dot products
+// use a fixed grid and a fixed summation order: results are bitwise
+// reproducible.
+#include <cmath>
+#include <vector>
+
+#include "common.hpp"
+#include "device.hpp"
+
+namespace spmv {
+namespace {
+
+constexpr int kRed = 1024;  // workgroups of every reduction (fixed: deterministic order)
+
+// scalar slots in the solver workspace
+enum : int { S_RR = 0, S_PAP = 1, S_ALPHA = 2, S_BETA = 3, S_BB = 4, S_TMP = 5 };
+
+__device__ __forceinline__ double block_sum(double v, double* sh) {
+  v = dev::group_sum<64>(v);
+  if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = v;
+  __syncthreads();
+  const double s = (sh[0] + sh[1]) + (sh[2] + sh[3]);
+  __syncthreads();
+  return s;
+}
+
+// partials[g] = sum over this workgroup's strided indices of x*y
+__global__ __launch_bounds__(kWG) void k_dot(const double* __restrict__ x,
+                                             const double* __restrict__ y, int64_t n,
+                                             double* __restrict__ partials) {
+  __shared__ double sh[4];
+  double s = 0.0;
+  for (int64_t i = (int64_t)blockIdx.x * kWG + threadIdx.x; i < n; i += (int64_t)kRed * kWG)
+    s = fma(x[i], y[i], s);
+  s = block_sum(s, sh);
+  if (threadIdx.x == 0) partials[blockIdx.x] = s;
+}
+
+// Sum of the kRed partials in fixed order, then a scalar update:
+// op 0: sc[dst] = sum; 1: sc[dst] = sqrt(sum); 2: alpha = rr / sum;
+// 3: beta = sum / rr, rr = sum.
+__global__ __launch_bounds__(kWG) void k_finish(const double* __restrict__ partials,
+                                                double* __restrict__ sc, int op, int dst,
+                                                double* __restrict__ hist) {
+  __shared__ double sh[4];
+  double s = 0.0;
+  for (int g = threadIdx.x; g < kRed; g += kWG) s += partials[g];
+  s = block_sum(s, sh);
+  if (threadIdx.x == 0) {
+    if (op == 0) sc[dst] = s;
+    if (op == 1) sc[dst] = sqrt(s);
+    if (op == 2) sc[S_ALPHA] = sc[S_RR] / s;
+    if (op == 3) {
+      sc[S_BETA] = s / sc[S_RR];
+      sc[S_RR] = s;
+    }
+    if (hist) *hist = op == 1 ? sqrt(s) : s;
+  }
+}
+
+// r = b - Ap ; p = r
+__global__ __launch_bounds__(kWG) void k_cg_init(const double* __restrict__ b,
+                                                 const double* __restrict__ Ap,
+                                                 double* __restrict__ r, double* __restrict__ p,
+                                                 int64_t n) {
+  for (int64_t i = (int64_t)blockIdx.x * kWG + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * kWG) {
+    const double v = b[i] - Ap[i];
+    r[i] = v;
+    p[i] = v;
+  }
+}
+
+// x += alpha p ; r -= alpha Ap ; partials of r.r
+__global__ __launch_bounds__(kWG) void k_cg_xr(double* __restrict__ x, double* __restrict__ r,
+                                               const double* __restrict__ p,
+                                               const double* __restrict__ Ap,
+                                               const double* __restrict__ sc, int64_t n,
+                                               double* __restrict__ partials) {
+  __shared__ double sh[4];
+  const double a = sc[S_ALPHA];
+  double s = 0.0;
+  for (int64_t i = (int64_t)blockIdx.x * kWG + threadIdx.x; i < n; i += (int64_t)kRed * kWG) {
+    x[i] = fma(a, p[i], x[i]);
+    const double ri = fma(-a, Ap[i], r[i]);
+    r[i] = ri;
+    s = fma(ri, ri, s);
+  }
+  s = block_sum(s, sh);
+  if (threadIdx.x == 0) partials[blockIdx.x] = s;
+}
+
+// p = r + beta p
+__global__ __launch_bounds__(kWG) void k_cg_p(double* __restrict__ p, const double* __restrict__ r,
+                                              const double* __restrict__ sc, int64_t n) {
+  const double be = sc[S_BETA];
+  for (int64_t i = (int64_t)blockIdx.x * kWG + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * kWG)
+    p[i] = fma(be, p[i], r[i]);
+}
+
+__global__ __launch_bounds__(kWG) void k_to_f32(float* __restrict__ d, const double* __restrict__ s,
+                                                int64_t n) {
+  for (int64_t i = (int64_t)blockIdx.x * kWG + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * kWG)
+    d[i] = (float)s[i];
+}
+
+// Lanczos: w -= beta_j v_prev (beta from the history array) and partials of w.v
+__global__ __launch_bounds__(kWG) void k_lz_a(double* __restrict__ w,
+                                              const double* __restrict__ v,
+                                              const double* __restrict__ vprev,
+                                              const double* __restrict__ beta_j, int64_t n,
+                                              double* __restrict__ partials) {
+  __shared__ double sh[4];
+  const double be = *beta_j;
+  double s = 0.0;
+  for (int64_t i = (int64_t)blockIdx.x * kWG + threadIdx.x; i < n; i += (int64_t)kRed * kWG) {
+    const double wi = fma(-be, vprev[i], w[i]);
+    w[i] = wi;
+    s = fma(wi, v[i], s);
+  }
+  s = block_sum(s, sh);
+  if (threadIdx.x == 0) partials[blockIdx.x] = s;
+}
+
+// w -= alpha_j v and partials of w.w
+__global__ __launch_bounds__(kWG) void k_lz_b(double* __restrict__ w,
+                                              const double* __restrict__ v,
+                                              const double* __restrict__ alpha_j, int64_t n,
+                                              double* __restrict__ partials) {
+  __shared__ double sh[4];
+  const double al = *alpha_j;
+  double s = 0.0;
+  for (int64_t i = (int64_t)blockIdx.x * kWG + threadIdx.x; i < n; i += (int64_t)kRed * kWG) {
+    const double wi = fma(-al, v[i], w[i]);
+    w[i] = wi;
+    s = fma(wi, wi, s);
+  }
+  s = block_sum(s, sh);
+  if (threadIdx.x == 0) partials[blockIdx.x] = s;
+}
+
+// v_out = w / beta (beta = norm stored at *beta_next)
+__global__ __launch_bounds__(kWG) void k_scale(double* __restrict__ out,
+                                               const double* __restrict__ in,
+                                               const double* __restrict__ denom, int64_t n) {
+  const double d = *denom;
+  for (int64_t i = (int64_t)blockIdx.x * kWG + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * kWG)
+    out[i] = in[i] / d;
+}
+
+unsigned vgrid(int64_t n) {
+  return (unsigned)std::max<int64_t>(1, std::min<int64_t>((n + kWG - 1) / kWG, 8192));
+}
+
+struct SolverWs {
+  double* sc;
+  double* partials;
+  double* r;
+  double* p;
+  double* Ap;
+  float* p32;
+};
+
+size_t solver_ws_bytes(int64_t n, int64_t hist) {
+  const size_t n1 = (size_t)std::max<int64_t>(n, 1);
+  return align256(sizeof(double) * 64) + align256(sizeof(double) * kRed) +
+         3 * align256(sizeof(double) * n1) + align256(sizeof(float) * n1) +
+         align256(sizeof(double) * (size_t)std::max<int64_t>(hist, 1));
+}
+
+SolverWs carve(void* ws, int64_t n) {
+  char* c = static_cast<char*>(ws);
+  const size_t n1 = (size_t)std::max<int64_t>(n, 1);
+  SolverWs w;
+  w.sc = reinterpret_cast<double*>(c);
+  c += align256(sizeof(double) * 64);
+  w.partials = reinterpret_cast<double*>(c);
+  c += align256(sizeof(double) * kRed);
+  w.r = reinterpret_cast<double*>(c);
+  c += align256(sizeof(double) * n1);
+  w.p = reinterpret_cast<double*>(c);
+  c += align256(sizeof(double) * n1);
+  w.Ap = reinterpret_cast<double*>(c);
+  c += align256(sizeof(double) * n1);
+  w.p32 = reinterpret_cast<float*>(c);
+  return w;
+}
+
+double* history(void* ws, int64_t n) {
+  char* c = static_cast<char*>(ws);
+  const size_t n1 = (size_t)std::max<int64_t>(n, 1);
+  return reinterpret_cast<double*>(c + align256(sizeof(double) * 64) +
+                                   align256(sizeof(double) * kRed) +
+                                   3 * align256(sizeof(double) * n1) +
+                                   align256(sizeof(float) * n1));
+}
+
+// y = A x for a plan of either storage type (x float64; cast for FP32 plans)
+int plan_apply(const Plan& p, const double* x, float* x32, double* y, hipStream_t s) {
+  if (p.vdt == SPMV_F64) return launch_spmv(p, p.variant, x, y, s);
+  k_to_f32<<<vgrid(p.n_cols), kWG, 0, s>>>(x32, x, p.n_cols);
+  SPMV_HIP(hipGetLastError());
+  return launch_spmv(p, p.variant, x32, y, s);
+}
+
+int dot(const double* x, const double* y, int64_t n, SolverWs& w, int op, int dst,
+        double* hist, hipStream_t s) {
+  k_dot<<<kRed, kWG, 0, s>>>(x, y, n, w.partials);
+  SPMV_HIP(hipGetLastError());
+  k_finish<<<1, kWG, 0, s>>>(w.partials, w.sc, op, dst, hist);
+  SPMV_HIP(hipGetLastError());
+  return SPMV_OK;
+}
+
+// one CG iteration: Ap = A p; alpha = rr/(p.Ap); x += alpha p; r -= alpha Ap;
+// beta = r.r/rr; rr = r.r; p = r + beta p
+int cg_iteration(const Plan& P, double* x, SolverWs& w, int64_t n, hipStream_t s) {
+  int st = plan_apply(P, w.p, w.p32, w.Ap, s);
+  if (!st) st = dot(w.p, w.Ap, n, w, 2, 0, nullptr, s);
+  if (st) return st;
+  k_cg_xr<<<kRed, kWG, 0, s>>>(x, w.r, w.p, w.Ap, w.sc, n, w.partials);
+  SPMV_HIP(hipGetLastError());
+  k_finish<<<1, kWG, 0, s>>>(w.partials, w.sc, 3, 0, nullptr);
+  SPMV_HIP(hipGetLastError());
+  k_cg_p<<<vgrid(n), kWG, 0, s>>>(w.p, w.r, w.sc, n);
+  SPMV_HIP(hipGetLastError());
+  return SPMV_OK;
+}
+
+}  // namespace
+
+size_t cg_workspace_bytes(int64_t n) { return solver_ws_bytes(n, 1); }
+size_t lanczos_workspace_bytes(int64_t n, int k) {
+  // solver block plus history (alpha[k], beta[k+1]) plus three Lanczos vectors
+  return solver_ws_bytes(n, 2 * (int64_t)k + 2) +
+         3 * align256(sizeof(double) * (size_t)std::max<int64_t>(n, 1));
+}
+
+int run_cg(const Plan& P, const double* b, double* x, double tol, int maxit, int check_every,
+           bool use_graph, void* ws, int* iters, double* relres, hipStream_t s) {
+  const int64_t n = P.n_rows;
+  SolverWs w = carve(ws, n);
+  // ||b||^2 and the initial residual
+  int st = dot(b, b, n, w, 0, S_BB, nullptr, s);
+  if (!st) st = plan_apply(P, x, w.p32, w.Ap, s);
+  if (st) return st;
+  k_cg_init<<<vgrid(n), kWG, 0, s>>>(b, w.Ap, w.r, w.p, n);
+  SPMV_HIP(hipGetLastError());
+  st = dot(w.r, w.r, n, w, 0, S_RR, nullptr, s);
+  if (st) return st;
+  double h[6];
+  SPMV_HIP(hipMemcpyAsync(h, w.sc, sizeof(h), hipMemcpyDeviceToHost, s));
+  SPMV_HIP(hipStreamSynchronize(s));
+  const double bn = h[S_BB] > 0.0 ? std::sqrt(h[S_BB]) : 1.0;
+  double rr = h[S_RR];
+  int it = 0;
+  *relres = std::sqrt(rr) / bn;
+  if (*relres <= tol || maxit <= 0) {
+    *iters = 0;
+    return SPMV_OK;
+  }
+  hipGraphExec_t exec = nullptr;
+  if (use_graph) {
+    if (!s) return fail(SPMV_ERR_INVALID_ARG, "graph mode needs a non-null stream");
+    hipGraph_t g = nullptr;
+    SPMV_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+    st = cg_iteration(P, x, w, n, s);
+    hipError_t e = hipStreamEndCapture(s, &g);
+    if (st) {
+      if (g) hipGraphDestroy(g);
+      return st;
+    }
+    if (e != hipSuccess) return hip_fail(e, "capture of a CG iteration");
+    e = hipGraphInstantiate(&exec, g, nullptr, nullptr, 0);
+    hipGraphDestroy(g);
+    if (e != hipSuccess) return hip_fail(e, "hipGraphInstantiate");
+  }
+  const int every = check_every > 0 ? check_every : 1;
+  while (it < maxit) {
+    if (exec) {
+      hipError_t e = hipGraphLaunch(exec, s);
+      if (e != hipSuccess) {
+        hipGraphExecDestroy(exec);
+        return hip_fail(e, "hipGraphLaunch");
+      }
+    } else {
+      st = cg_iteration(P, x, w, n, s);
+      if (st) return st;
+    }
+    ++it;
+    if (it % every == 0 || it == maxit) {
+      hipError_t e = hipMemcpyAsync(&rr, w.sc + S_RR, sizeof(double), hipMemcpyDeviceToHost, s);
+      if (e == hipSuccess) e = hipStreamSynchronize(s);
+      if (e != hipSuccess) {
+        if (exec) hipGraphExecDestroy(exec);
+        return hip_fail(e, "residual readback");
+      }
+      *relres = std::sqrt(rr) / bn;
+      if (*relres <= tol) break;
+    }
+  }
+  if (exec) hipGraphExecDestroy(exec);
+  *iters = it;
+  return SPMV_OK;
+}
+
+int run_lanczos(const Plan& P, const double* v0, int k, double* alpha, double* beta, void* ws,
+                hipStream_t s) {
+  const int64_t n = P.n_rows;
+  SolverWs w = carve(ws, n);
+  double* hist = history(ws, n);  // alpha[k] then beta[k+1]
+  double* ha = hist;
+  double* hb = hist + k;
+  char* vec = reinterpret_cast<char*>(hist) + align256(sizeof(double) * (2 * (size_t)k + 2));
+  const size_t vb = align256(sizeof(double) * (size_t)std::max<int64_t>(n, 1));
+  double* V[3] = {reinterpret_cast<double*>(vec), reinterpret_cast<double*>(vec + vb),
+                  reinterpret_cast<double*>(vec + 2 * vb)};
+  double* wv = w.Ap;
+  // beta_0 = 0, v_prev = 0, v = v0 / ||v0||
+  int st = dot(v0, v0, n, w, 1, S_TMP, hb, s);
+  if (st) return st;
+  k_scale<<<vgrid(n), kWG, 0, s>>>(V[1], v0, hb, n);
+  SPMV_HIP(hipGetLastError());
+  k_scale<<<vgrid(n), kWG, 0, s>>>(V[0], v0, hb, n);  // any finite vector; scaled by beta_0 = 0
+  SPMV_HIP(hipGetLastError());
+  static const double zero = 0.0;
+  SPMV_HIP(hipMemcpyAsync(hb, &zero, sizeof(double), hipMemcpyHostToDevice, s));
+  int prev = 0, cur = 1, nxt = 2;
+  for (int j = 0; j < k; ++j) {
+    st = plan_apply(P, V[cur], w.p32, wv, s);
+    if (st) return st;
+    k_lz_a<<<kRed, kWG, 0, s>>>(wv, V[cur], V[prev], hb + j, n, w.partials);
+    SPMV_HIP(hipGetLastError());
+    k_finish<<<1, kWG, 0, s>>>(w.partials, w.sc, 0, S_TMP, ha + j);
+    SPMV_HIP(hipGetLastError());
+    k_lz_b<<<kRed, kWG, 0, s>>>(wv, V[cur], ha + j, n, w.partials);
+    SPMV_HIP(hipGetLastError());
+    k_finish<<<1, kWG, 0, s>>>(w.partials, w.sc, 1, S_TMP, hb + j + 1);
+    SPMV_HIP(hipGetLastError());
+    k_scale<<<vgrid(n), kWG, 0, s>>>(V[nxt], wv, hb + j + 1, n);
+    SPMV_HIP(hipGetLastError());
+    const int t = prev;
+    prev = cur;
+    cur = nxt;
+    nxt = t;
+  }
+  std::vector<double> hh(2 * (size_t)k + 1);
+  SPMV_HIP(hipMemcpyAsync(hh.data(), hist, sizeof(double) * hh.size(), hipMemcpyDeviceToHost, s));
+  SPMV_HIP(hipStreamSynchronize(s));
+  for (int j = 0; j < k; ++j) {
+    alpha[j] = hh[j];
+    beta[j] = hh[k + j + 1];
+  }
+  return SPMV_OK;
+}
+
+}  // namespace spmv

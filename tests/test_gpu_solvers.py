@@ -1,0 +1,116 @@
+"""CG and Lanczos on top of the product, checked against closed forms of the
+2D Laplacian: the exact solution of A x = A x*, and the extreme eigenvalues
+4 +- 4 cos(pi/(m+1)). True residuals are recomputed with the CPU oracle."""
+import math
+
+import numpy as np
+import pytest
+
+import crsgen
+import oracle
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+import paper_1101_0091_amd as pkg  # noqa: E402
+
+DEV = "cuda:0"
+
+
+def _cg(M, b, tol, maxit=3000, graph=False, check_every=10):
+    n = b.shape[0]
+    ws_bytes = pkg.spmv_cg_workspace_size(n)
+    ws = torch.empty(ws_bytes, dtype=torch.uint8, device=DEV)
+    bd = torch.from_numpy(b).to(DEV)
+    x = torch.zeros(n, dtype=torch.float64, device=DEV)
+    s = torch.cuda.Stream() if graph else None
+    torch.cuda.synchronize()
+    it, rr = pkg.spmv_cg_solve(M.handle, bd, x, tol, maxit, check_every, graph, ws, ws_bytes,
+                               s)
+    torch.cuda.synchronize()
+    return x.cpu().numpy(), it, rr
+
+
+@pytest.fixture(scope="module")
+def lap128():
+    A = crsgen.laplace2d(128)
+    xs = crsgen.uniform_vec(A.n_rows, 8)
+    b, _ = oracle.spmv(A.n_rows, A.row_ptr, A.col_idx, A.val, xs)
+    return A, xs, b
+
+
+def test_cg_solves_laplacian(lap128):
+    A, xs, b = lap128
+    M = pkg.CRSMatrix.from_crs(A, flags=pkg.SPMV_FLAG_VARIANT(4), device=DEV)
+    x, it, rr = _cg(M, b, 1e-10)
+    assert rr <= 1e-10 and 100 < it < 1000
+    Ax, _ = oracle.spmv(A.n_rows, A.row_ptr, A.col_idx, A.val, x)
+    assert np.linalg.norm(b - Ax) / np.linalg.norm(b) <= 1e-9
+    assert np.linalg.norm(x - xs) / np.linalg.norm(xs) <= 1e-6
+
+
+def test_cg_graph_replay_and_variants_bitwise(lap128):
+    A, xs, b = lap128
+    M = pkg.CRSMatrix.from_crs(A, flags=pkg.SPMV_FLAG_VARIANT(4), device=DEV)
+    x1, it1, r1 = _cg(M, b, 1e-10)
+    x2, it2, r2 = _cg(M, b, 1e-10, graph=True)
+    x3, it3, r3 = _cg(M, b, 1e-10)
+    assert it1 == it2 == it3 and r1 == r2 == r3
+    assert np.array_equal(x1, x2) and np.array_equal(x1, x3)
+    # other variants round the products differently; the solutions agree to
+    # the solver tolerance
+    outs = []
+    for v in (0, 4, 5):
+        M.variant = v
+        outs.append(_cg(M, b, 1e-8)[0])
+    for o in outs[1:]:
+        assert np.linalg.norm(o - outs[0]) <= 1e-6 * np.linalg.norm(outs[0])
+
+
+def test_cg_fp32_storage_effect(lap128):
+    """FP32 storage of the (exactly representable) Laplacian with a float32
+    copy of the search direction: convergence stalls near float32 accuracy."""
+    A, xs, b = lap128
+    M32 = pkg.CRSMatrix(A.n_rows, A.n_cols, A.row_ptr, A.col_idx, A.val.astype(np.float32),
+                        val_dtype=torch.float32, device=DEV)
+    x, it, rr = _cg(M32, b, 1e-5)
+    Ax, _ = oracle.spmv(A.n_rows, A.row_ptr, A.col_idx, A.val, x)
+    true = np.linalg.norm(b - Ax) / np.linalg.norm(b)
+    assert rr <= 1e-5 and true <= 1e-4
+    print(f"fp32-storage CG: {it} iterations to 1e-5, true residual {true:.2e}")
+
+
+def test_cg_rejects_bad_arguments(lap128):
+    A, xs, b = lap128
+    M = pkg.CRSMatrix.from_crs(A, device=DEV)
+    with pytest.raises(pkg.SpmvError):
+        pkg.spmv_cg_solve(M.handle, torch.zeros(A.n_rows, dtype=torch.float64, device=DEV),
+                          torch.zeros(A.n_rows, dtype=torch.float64, device=DEV), 1e-8, 10, 1,
+                          False, torch.empty(256, dtype=torch.uint8, device=DEV), 256)
+    R = crsgen.random_crs(10, 12, seed=1)
+    MR = pkg.CRSMatrix.from_crs(R, device=DEV)
+    n = pkg.spmv_cg_workspace_size(10)
+    with pytest.raises(pkg.SpmvError):
+        pkg.spmv_cg_solve(MR.handle, torch.zeros(10, dtype=torch.float64, device=DEV),
+                          torch.zeros(10, dtype=torch.float64, device=DEV), 1e-8, 10, 1, False,
+                          torch.empty(n, dtype=torch.uint8, device=DEV), n)
+
+
+@pytest.mark.parametrize("dt", ["f64", "f32"])
+def test_lanczos_extreme_eigenvalues(dt):
+    from scipy.linalg import eigvalsh_tridiagonal
+    m, k = 64, 300
+    A = crsgen.laplace2d(m)
+    tdt = torch.float32 if dt == "f32" else torch.float64
+    val = A.val.astype(np.float32) if dt == "f32" else A.val
+    M = pkg.CRSMatrix(A.n_rows, A.n_cols, A.row_ptr, A.col_idx, val, val_dtype=tdt, device=DEV)
+    v0 = torch.from_numpy(crsgen.uniform_vec(A.n_rows, 7)).to(DEV)
+    nb = pkg.spmv_lanczos_workspace_size(A.n_rows, k)
+    ws = torch.empty(nb, dtype=torch.uint8, device=DEV)
+    al, be = pkg.spmv_lanczos(M.handle, v0, k, ws, nb)
+    al2, be2 = pkg.spmv_lanczos(M.handle, v0, k, ws, nb)
+    assert np.array_equal(al, al2) and np.array_equal(be, be2)
+    th = eigvalsh_tridiagonal(al, be[:-1])
+    c = math.cos(math.pi / (m + 1))
+    tol = 1e-10 if dt == "f64" else 1e-5
+    assert abs(th[-1] - (4 + 4 * c)) <= tol
+    assert abs(th[0] - (4 - 4 * c)) <= tol
