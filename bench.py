@@ -142,6 +142,8 @@ def main():
     log(f"fp64: {ms_per_step:.4f} ms/step, kernel {k_ms:.4f} ms, {value:.1f} GFlop/s, "
         f"{achieved:.1f} GB/s")
     traffic = stored_traffic(wname, vname)
+    kappa = (None if traffic is None else
+             round(pm.kappa_from_bytes(traffic, A.n_rows, A.n_cols, nnz), 3))
     out = {
         "metric": METRIC,
         "value": round(value, 2),
@@ -164,7 +166,7 @@ def main():
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK, 4),
                      "traffic": traffic, "kernel": "k_lds_block<double,double>" if
                      vname.startswith("V4") else vname, "kernel_ms": round(k_ms, 5),
-                     "algorithmic_bytes_per_launch": comp},
+                     "algorithmic_bytes_per_launch": comp, "kappa_bytes_per_nnz": kappa},
     }
     extra = {}
     if not args.no_extra:
@@ -173,6 +175,35 @@ def main():
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(A, B)
     print(json.dumps(out), flush=True)
+
+
+def time_create(A, pkg, dev):
+    """Plan creation cost: analysis only (fixed variant), analysis + selector
+    network, analysis + exhaustive autotune (the selector's alternative)."""
+    import torch
+    rp = torch.from_numpy(A.row_ptr).to(dev)
+    ci = torch.from_numpy(A.col_idx).to(dev)
+    va = torch.from_numpy(A.val).to(dev)
+    out = {}
+    for name, flags in (("fixed", pkg.SPMV_FLAG_VARIANT(4)), ("selector", pkg.SPMV_SELECT_DEFAULT),
+                        ("autotune", pkg.SPMV_SELECT_AUTOTUNE)):
+        if name == "selector":
+            pkg.load_selector()
+        nb = pkg.spmv_workspace_size(A.n_rows, A.n_cols, A.nnz, flags)
+        ws = torch.empty(nb, dtype=torch.uint8, device=dev)
+        best = None
+        for _ in range(3):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            h = pkg.spmv_create(A.n_rows, A.n_cols, A.nnz, rp, ci, va, pkg.SPMV_F64, ws, nb, flags)
+            torch.cuda.synchronize()
+            t = time.perf_counter() - t0
+            v = pkg.spmv_get_variant(h)
+            pkg.spmv_destroy(h)
+            best = t if best is None else min(best, t)
+        out[name] = {"ms": round(best * 1e3, 3), "variant": pkg.VARIANTS[v]}
+    log(f"plan creation: {out}")
+    return out
 
 
 def run_extra(A, B, M, pkg, pm, dev, stream, args):
@@ -195,6 +226,7 @@ def run_extra(A, B, M, pkg, pm, dev, stream, args):
     M.variant = v0
     ex["variant_ms"] = var_ms
     log(f"variants: {var_ms}")
+    ex["plan_create_ms"] = time_create(A, pkg, dev)
     # FP32 storage, FP64 accumulation
     M32 = pkg.CRSMatrix(A.n_rows, A.n_cols, A.row_ptr, A.col_idx, A.val.astype(np.float32),
                         val_dtype=torch.float32, flags=pkg.SPMV_SELECT_AUTOTUNE, device=dev)
