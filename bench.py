@@ -22,6 +22,8 @@ sys.path.insert(0, ROOT)
 
 METRIC = "CRS spMVM GFlop/s and effective HBM GB/s (% roofline) at 1 MI355X, FP64 vs mixed"
 HBM_PEAK = 8000.0  # GB/s, MI355X nominal
+KERNEL_NAMES = {"V4_lds_block": "k_lds_block<double,double>", "V6_sell64": "k_sell<double,double>"}
+SELL = 0  # plan flag requesting the V6 chunked copy; set in main()
 
 
 def log(msg):
@@ -30,7 +32,7 @@ def log(msg):
 
 def kernel_source_hash() -> str:
     h = hashlib.sha256()
-    for f in ("device.hpp", "spmv_kernels.hip", "common.hpp"):
+    for f in ("device.hpp", "spmv_kernels.hip", "common.hpp", "sell.hip"):
         h.update(open(os.path.join(ROOT, "paper_1101_0091_amd", "csrc", f), "rb").read())
     return h.hexdigest()[:16]
 
@@ -80,6 +82,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--variant", type=int, default=-1, help="force a variant (default: autotune)")
     ap.add_argument("--workload", default="hamiltonian", choices=["hamiltonian", "mesh"])
+    ap.add_argument("--no-sell", action="store_true",
+                    help="build plans without the V6 chunked copy")
     ap.add_argument("--rcm", action="store_true",
                     help="only measure the RCM-reordered workloads (host reordering ~30 s)")
     ap.add_argument("--calib-copy", action="store_true",
@@ -97,6 +101,8 @@ def main():
     import paper_1101_0091_amd as pkg
     from paper_1101_0091_amd import perfmodel as pm
 
+    global SELL
+    SELL = 0 if args.no_sell else pkg.SPMV_FLAG_SELL
     dev = torch.device("cuda:0")
     stream = torch.cuda.current_stream()
     if args.rcm:
@@ -121,9 +127,11 @@ def main():
         A = crsgen.mesh3d(280, seed=seed)[0]
     B = crsgen.uniform_vec(A.n_cols, seed)
     flags = pkg.SPMV_SELECT_AUTOTUNE if args.variant < 0 else pkg.SPMV_FLAG_VARIANT(args.variant)
+    flags |= SELL
     M = pkg.CRSMatrix.from_crs(A, flags=flags, device=dev)
     vname = pkg.VARIANTS[M.variant]
-    log(f"plan ready: nnz={A.nnz} variant={vname} blocks={M.num_blocks}")
+    log(f"plan ready: nnz={A.nnz} variant={vname} blocks={M.num_blocks} "
+        f"sell_slots={M.sell_slots}")
     Bd = torch.from_numpy(B).to(dev)
     C = torch.empty(A.n_rows, dtype=torch.float64, device=dev)
     h = M.handle
@@ -164,8 +172,8 @@ def main():
                                   / HBM_PEAK, 2),
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK, 4),
-                     "traffic": traffic, "kernel": "k_lds_block<double,double>" if
-                     vname.startswith("V4") else vname, "kernel_ms": round(k_ms, 5),
+                     "traffic": traffic, "kernel": KERNEL_NAMES.get(vname, vname),
+                     "kernel_ms": round(k_ms, 5),
                      "algorithmic_bytes_per_launch": comp, "kappa_bytes_per_nnz": kappa},
     }
     extra = {}
@@ -186,7 +194,9 @@ def time_create(A, pkg, dev):
     va = torch.from_numpy(A.val).to(dev)
     out = {}
     for name, flags in (("fixed", pkg.SPMV_FLAG_VARIANT(4)), ("selector", pkg.SPMV_SELECT_DEFAULT),
-                        ("autotune", pkg.SPMV_SELECT_AUTOTUNE)):
+                        ("autotune", pkg.SPMV_SELECT_AUTOTUNE),
+                        ("fixed_v6_with_copy", pkg.SPMV_FLAG_VARIANT(6) | pkg.SPMV_FLAG_SELL),
+                        ("autotune_with_v6_copy", pkg.SPMV_SELECT_AUTOTUNE | pkg.SPMV_FLAG_SELL)):
         if name == "selector":
             pkg.load_selector()
         nb = pkg.spmv_workspace_size(A.n_rows, A.n_cols, A.nnz, flags)
@@ -219,6 +229,8 @@ def run_extra(A, B, M, pkg, pm, dev, stream, args):
     var_ms = {}
     v0 = M.variant
     for v in range(pkg.SPMV_NUM_VARIANTS):
+        if v == pkg.SPMV_V6_SELL64 and M.sell_slots is None:
+            continue
         M.variant = v
         per, _ = time_launches(lambda: pkg.spmv_apply(M.handle, Bd, pkg.SPMV_F64, C), steps, 3,
                                stream)
@@ -229,7 +241,8 @@ def run_extra(A, B, M, pkg, pm, dev, stream, args):
     ex["plan_create_ms"] = time_create(A, pkg, dev)
     # FP32 storage, FP64 accumulation
     M32 = pkg.CRSMatrix(A.n_rows, A.n_cols, A.row_ptr, A.col_idx, A.val.astype(np.float32),
-                        val_dtype=torch.float32, flags=pkg.SPMV_SELECT_AUTOTUNE, device=dev)
+                        val_dtype=torch.float32, flags=pkg.SPMV_SELECT_AUTOTUNE | SELL,
+                        device=dev)
     B32 = torch.from_numpy(B.astype(np.float32)).to(dev)
     per, _ = time_launches(lambda: pkg.spmv_apply(M32.handle, B32, pkg.SPMV_F32, C), steps, 5,
                            stream)
@@ -338,7 +351,7 @@ def run_rcm(pkg, pm, dev, stream):
         C = torch.empty(A.n_rows, dtype=torch.float64, device=dev)
         for tag, (r, c, v, b) in (("as_given", (A.row_ptr, A.col_idx, A.val, B)),
                                   ("rcm", (rp, ci, va, B[perm]))):
-            M = pkg.CRSMatrix(A.n_rows, A.n_cols, r, c, v, flags=pkg.SPMV_SELECT_AUTOTUNE,
+            M = pkg.CRSMatrix(A.n_rows, A.n_cols, r, c, v, flags=pkg.SPMV_SELECT_AUTOTUNE | SELL,
                               device=dev)
             Bd = torch.from_numpy(np.ascontiguousarray(b)).to(dev)
             per, _ = time_launches(lambda: pkg.spmv_apply(M.handle, Bd, pkg.SPMV_F64, C), 30, 3,
@@ -413,7 +426,7 @@ def run_small(pkg, pm, dev, stream):
 
     import crsgen
     L = crsgen.laplace2d(256)
-    M = pkg.CRSMatrix.from_crs(L, flags=pkg.SPMV_SELECT_AUTOTUNE, device=dev)
+    M = pkg.CRSMatrix.from_crs(L, flags=pkg.SPMV_SELECT_AUTOTUNE | SELL, device=dev)
     Bd = torch.from_numpy(crsgen.uniform_vec(L.n_cols, 1)).to(dev)
     C = torch.empty(L.n_rows, dtype=torch.float64, device=dev)
     comp = pm.compulsory_bytes(L.n_rows, L.n_cols, L.nnz)
@@ -453,7 +466,7 @@ def run_mesh(pkg, pm, dev, stream):
                                     ("mixed_fp32_storage", torch.float32, np.float32,
                                      pkg.SPMV_F32, 4)):
         M = pkg.CRSMatrix(A.n_rows, A.n_cols, A.row_ptr, A.col_idx, A.val.astype(bdt),
-                          val_dtype=vdt, flags=pkg.SPMV_SELECT_AUTOTUNE, device=dev)
+                          val_dtype=vdt, flags=pkg.SPMV_SELECT_AUTOTUNE | SELL, device=dev)
         Bd = torch.from_numpy(B.astype(bdt)).to(dev)
         per, _ = time_launches(lambda: pkg.spmv_apply(M.handle, Bd, code, C), 30, 3, stream)
         t = float(np.median(per)) / 1000

@@ -70,8 +70,13 @@ typedef enum {
   SPMV_V3_WAVE_ROW = 3,   /* one 64-lane wavefront per row */
   SPMV_V4_LDS_BLOCK = 4,  /* nnz-balanced row blocks staged through LDS */
   SPMV_V5_BINNED = 5,     /* row-length bins, one launch per non-empty bin */
-  SPMV_NUM_VARIANTS = 6
+  SPMV_V6_SELL64 = 6,     /* chunked copy: 64 rows per chunk stored column by column
+                             (sliced ELLPACK, built at create; needs SPMV_FLAG_SELL) */
+  SPMV_NUM_VARIANTS = 7
 } spmv_variant;
+
+/* The MLP selector ranks V0..V5; V6 is chosen by autotune or by name. */
+#define SPMV_NUM_SELECTOR_OUTPUTS 6
 
 /* spmv_create flags. The low byte selects how the variant is chosen. */
 #define SPMV_SELECT_DEFAULT 0x0u  /* MLP selector if loaded, else V4 */
@@ -80,6 +85,13 @@ typedef enum {
 #define SPMV_SELECT_FIXED 0x3u    /* use the variant in bits 8..11 */
 #define SPMV_FLAG_VARIANT(v) (SPMV_SELECT_FIXED | ((uint32_t)(v) << 8))
 #define SPMV_FLAG_SKIP_VALIDATE 0x10000u /* trust the CRS arrays (no device check) */
+/* Reserve workspace for the V6 copy and build it at create. The copy holds
+ * 64 * (sum over chunks of the longest row in the chunk) slots of 4-byte
+ * column index + value; the reserve is 1.5 nnz + 4096 slots (rounded up to
+ * 64) at 12 bytes each whatever val_dtype is. A pattern whose padded size
+ * exceeds it still gets a plan, without V6 (spmv_get_sell_slots reports
+ * SPMV_ERR_STATE); asking for V6 by name then fails with UNSUPPORTED. */
+#define SPMV_FLAG_SELL 0x20000u
 
 #define SPMV_NUM_FEATURES 16
 #define SPMV_MLP_PARAMS 5638 /* 16->64->64->6: W1 b1 W2 b2 W3 b3, [out,in] row-major */
@@ -89,8 +101,10 @@ typedef enum {
 /*
  * Bytes of device workspace spmv_create needs for this shape (host call, no
  * device work). The workspace holds the row-block table, the row-length bin
- * lists, the analysis counters and the selector scratch. It depends only on
- * (n_rows, nnz) and is stable across calls. `bytes` is a host pointer.
+ * lists, the analysis counters, the selector scratch and, with
+ * SPMV_FLAG_SELL, the reserve of the V6 copy. It depends only on
+ * (n_rows, n_cols, nnz, flags) and is stable across calls. `bytes` is a host
+ * pointer.
  */
 int spmv_workspace_size(int64_t n_rows, int64_t n_cols, int64_t nnz, uint32_t flags,
                         size_t* bytes);
@@ -103,7 +117,7 @@ int spmv_workspace_size(int64_t n_rows, int64_t n_cols, int64_t nnz, uint32_t fl
  *  row_ptr  int32[n_rows+1], col_idx int32[nnz], val float64 or float32 [nnz]
  *  val_dtype SPMV_F64 or SPMV_F32
  *  workspace device, >= spmv_workspace_size() bytes, 256-byte aligned
- *  flags    SPMV_SELECT_* | SPMV_FLAG_SKIP_VALIDATE
+ *  flags    SPMV_SELECT_* | SPMV_FLAG_SKIP_VALIDATE | SPMV_FLAG_SELL
  *  stream   the stream for the analysis kernels
  * Unless SPMV_FLAG_SKIP_VALIDATE is set, the CRS arrays are checked on the
  * device (row_ptr[0]=0, nondecreasing, row_ptr[n_rows]=nnz, 0<=col<n_cols)
@@ -131,16 +145,21 @@ int spmm_apply(spmv_handle h, int32_t k, const void* B, int64_t ldb, int b_dtype
 
 /* Variant in use (host out). */
 int spmv_get_variant(spmv_handle h, int* variant);
-/* Switch the variant of an existing plan (all variants' tables are built at create). */
+/* Switch the variant of an existing plan (every table is built at create);
+ * SPMV_ERR_STATE for V6 on a plan without the V6 copy. */
 int spmv_set_variant(spmv_handle h, int variant);
 /* The 16 row-statistics features computed at create (host out, float64[16]). */
 int spmv_get_features(spmv_handle h, double* features);
-/* The selector's 6 predicted relative log2 times from create (host out, float[6]);
- * SPMV_ERR_STATE if no selector was run. */
+/* The selector's predicted relative log2 times of V0..V5 from create (host
+ * out, float[SPMV_NUM_SELECTOR_OUTPUTS]); SPMV_ERR_STATE if no selector ran. */
 int spmv_get_predictions(spmv_handle h, float* pred);
 /* Per-variant median times in microseconds measured by SPMV_SELECT_AUTOTUNE
- * (host out, double[6]); SPMV_ERR_STATE if autotune did not run. */
+ * (host out, double[SPMV_NUM_VARIANTS]; +infinity for a variant the plan does
+ * not have); SPMV_ERR_STATE if autotune did not run. */
 int spmv_get_autotune_times(spmv_handle h, double* us);
+/* Slots of the V6 copy (host out): 64 * sum of chunk widths, >= nnz; the
+ * padding is slots - nnz. SPMV_ERR_STATE if the plan has no V6 copy. */
+int spmv_get_sell_slots(spmv_handle h, int64_t* slots);
 /* Number of row blocks of the LDS-block variant (host out). */
 int spmv_get_num_blocks(spmv_handle h, int64_t* nblocks);
 int spmv_destroy(spmv_handle h);

@@ -23,10 +23,13 @@ SPMV_OK = 0
 SPMV_ERR_INVALID_ARG, SPMV_ERR_BAD_CRS, SPMV_ERR_UNSUPPORTED = -1, -2, -3
 SPMV_ERR_WORKSPACE, SPMV_ERR_HIP, SPMV_ERR_STATE = -4, -5, -6
 VARIANTS = ("V0_thread_row", "V1_lanes4", "V2_lanes16", "V3_wave_row", "V4_lds_block",
-            "V5_binned")
-SPMV_NUM_VARIANTS = 6
+            "V5_binned", "V6_sell64")
+SPMV_NUM_VARIANTS = 7
+SPMV_V6_SELL64 = 6
+SPMV_NUM_SELECTOR_OUTPUTS = 6
 SPMV_SELECT_DEFAULT, SPMV_SELECT_MLP, SPMV_SELECT_AUTOTUNE, SPMV_SELECT_FIXED = 0, 1, 2, 3
 SPMV_FLAG_SKIP_VALIDATE = 0x10000
+SPMV_FLAG_SELL = 0x20000
 SPMV_BATCH_DYNAMIC, SPMV_BATCH_STATIC, SPMV_BATCH_TILE_GRID = 0, 1, 2
 SPMV_NUM_FEATURES = 16
 SPMV_MLP_PARAMS = 5638
@@ -34,7 +37,7 @@ SPMV_MLP_PARAMS = 5638
 EXPORTS = (
     "spmv_workspace_size", "spmv_create", "spmv_apply", "spmm_apply", "spmv_get_variant",
     "spmv_set_variant", "spmv_get_features", "spmv_get_predictions", "spmv_get_autotune_times",
-    "spmv_get_num_blocks", "spmv_destroy", "spmv_batch_workspace_size", "spmv_batch_create",
+    "spmv_get_num_blocks", "spmv_get_sell_slots", "spmv_destroy", "spmv_batch_workspace_size", "spmv_batch_create",
     "spmv_batch_apply", "spmv_batch_apply_each", "spmv_batch_get_num_tiles", "spmv_batch_set_mode",
     "spmv_batch_destroy", "spmv_graph_begin", "spmv_graph_end", "spmv_graph_launch",
     "spmv_graph_destroy", "spmv_selector_load", "spmv_selector_loaded",
@@ -82,6 +85,7 @@ def lib():
             "spmv_get_predictions": [P, P],
             "spmv_get_autotune_times": [P, P],
             "spmv_get_num_blocks": [P, P],
+            "spmv_get_sell_slots": [P, P],
             "spmv_destroy": [P],
             "spmv_batch_workspace_size": [i32, i64, i64, P],
             "spmv_batch_create": [P, i32, P, P, P, P, P, P, ctypes.c_int, P, sz, P],
@@ -217,13 +221,13 @@ def spmv_get_features(h) -> np.ndarray:
 
 
 def spmv_get_predictions(h) -> np.ndarray:
-    p = np.zeros(6, dtype=np.float32)
+    p = np.zeros(SPMV_NUM_SELECTOR_OUTPUTS, dtype=np.float32)
     _check(lib().spmv_get_predictions(h, p.ctypes.data))
     return p
 
 
 def spmv_get_autotune_times(h) -> np.ndarray:
-    t = np.zeros(6, dtype=np.float64)
+    t = np.zeros(SPMV_NUM_VARIANTS, dtype=np.float64)
     _check(lib().spmv_get_autotune_times(h, t.ctypes.data))
     return t
 
@@ -231,6 +235,12 @@ def spmv_get_autotune_times(h) -> np.ndarray:
 def spmv_get_num_blocks(h) -> int:
     n = ctypes.c_int64(0)
     _check(lib().spmv_get_num_blocks(h, ctypes.byref(n)))
+    return int(n.value)
+
+
+def spmv_get_sell_slots(h) -> int:
+    n = ctypes.c_int64(0)
+    _check(lib().spmv_get_sell_slots(h, ctypes.byref(n)))
     return int(n.value)
 
 

@@ -29,7 +29,9 @@ int dtype_bytes(int dt) { return dt == SPMV_F64 ? 8 : 4; }
 bool dtype_ok(int dt) { return dt == SPMV_F64 || dt == SPMV_F32; }
 
 struct PlanLayout {
-  size_t header = 0, blocks = 0, bins = 0, at_B = 0, at_C = 0, total = 0;
+  size_t header = 0, blocks = 0, bins = 0, at_B = 0, at_C = 0;
+  size_t sell_width = 0, sell_off = 0, sell_partials = 0, sell_ci = 0, sell_val = 0;
+  size_t total = 0;
 };
 
 PlanLayout plan_layout(int64_t n_rows, int64_t n_cols, int64_t nnz, uint32_t flags) {
@@ -48,6 +50,19 @@ PlanLayout plan_layout(int64_t n_rows, int64_t n_cols, int64_t nnz, uint32_t fla
     o += align256(8 * (size_t)std::max<int64_t>(n_cols, 1));
     L.at_C = o;
     o += align256(8 * (size_t)std::max<int64_t>(n_rows, 1));
+  }
+  if (flags & SPMV_FLAG_SELL) {
+    const int64_t nch = sell_chunks(n_rows), cap = sell_capacity(nnz);
+    L.sell_width = o;
+    o += align256(4 * (size_t)std::max<int64_t>(nch, 1));
+    L.sell_off = o;
+    o += align256(4 * (size_t)(nch + 1));
+    L.sell_partials = o;
+    o += align256(4 * (size_t)scan_partials_count(nch));
+    L.sell_ci = o;
+    o += align256(4 * (size_t)cap);
+    L.sell_val = o;
+    o += align256(8 * (size_t)cap);
   }
   L.total = o;
   return L;
@@ -70,6 +85,10 @@ int autotune(Plan& p, hipStream_t s) {
   SPMV_HIP(hipEventCreate(&e1));
   constexpr int kReps = 5;
   for (int v = 0; v < SPMV_NUM_VARIANTS; ++v) {
+    if (v == SPMV_V6_SELL64 && !p.sell_ok) {
+      p.at_us[v] = INFINITY;
+      continue;
+    }
     st = launch_spmv(p, v, p.at_B, p.at_C, s);
     if (st) break;
     float ms[kReps];
@@ -94,7 +113,7 @@ int autotune(Plan& p, hipStream_t s) {
 
 bool selector_confident(const Plan& p) {
   float best = p.pred[0], second = INFINITY;
-  for (int v = 1; v < SPMV_NUM_VARIANTS; ++v) {
+  for (int v = 1; v < SPMV_NUM_SELECTOR_OUTPUTS; ++v) {
     if (p.pred[v] < best) {
       second = best;
       best = p.pred[v];
@@ -110,7 +129,7 @@ bool selector_confident(const Plan& p) {
 
 int argmin6(const float* x) {
   int b = 0;
-  for (int v = 1; v < SPMV_NUM_VARIANTS; ++v)
+  for (int v = 1; v < SPMV_NUM_SELECTOR_OUTPUTS; ++v)
     if (x[v] < x[b]) b = v;
   return b;
 }
@@ -188,7 +207,10 @@ int plan_build(Plan& p, int64_t n_rows, int64_t n_cols, int64_t nnz, const int32
   if (mode > SPMV_SELECT_FIXED) return fail(SPMV_ERR_INVALID_ARG, "unknown selection mode");
   if (mode == SPMV_SELECT_FIXED && fixed >= SPMV_NUM_VARIANTS)
     return fail(SPMV_ERR_INVALID_ARG, "variant out of range");
-  if (flags & ~(0xFFFu | SPMV_FLAG_SKIP_VALIDATE)) return fail(SPMV_ERR_INVALID_ARG, "unknown flag bits");
+  if (flags & ~(0xFFFu | SPMV_FLAG_SKIP_VALIDATE | SPMV_FLAG_SELL))
+    return fail(SPMV_ERR_INVALID_ARG, "unknown flag bits");
+  if (mode == SPMV_SELECT_FIXED && fixed == SPMV_V6_SELL64 && !(flags & SPMV_FLAG_SELL))
+    return fail(SPMV_ERR_INVALID_ARG, "variant V6 needs SPMV_FLAG_SELL");
   const PlanLayout L = plan_layout(n_rows, n_cols, nnz, flags);
   if (!workspace) return fail(SPMV_ERR_WORKSPACE, "workspace is null");
   if (reinterpret_cast<uintptr_t>(workspace) % 256)
@@ -213,6 +235,16 @@ int plan_build(Plan& p, int64_t n_rows, int64_t n_cols, int64_t nnz, const int32
     p.at_B = p.ws + L.at_B;
     p.at_C = reinterpret_cast<double*>(p.ws + L.at_C);
   }
+  if (flags & SPMV_FLAG_SELL) {
+    p.sell_reserved = true;
+    p.sell_nch = sell_chunks(n_rows);
+    p.sell_cap = sell_capacity(nnz);
+    p.sell_width = reinterpret_cast<int32_t*>(p.ws + L.sell_width);
+    p.sell_off = reinterpret_cast<int32_t*>(p.ws + L.sell_off);
+    p.sell_partials = reinterpret_cast<int32_t*>(p.ws + L.sell_partials);
+    p.sell_ci = reinterpret_cast<int32_t*>(p.ws + L.sell_ci);
+    p.sell_val = p.ws + L.sell_val;
+  }
   hipGetDevice(&p.device);
 
   const float* theta = selector_theta_device();
@@ -224,6 +256,7 @@ int plan_build(Plan& p, int64_t n_rows, int64_t n_cols, int64_t nnz, const int32
   if (!st) st = launch_analysis(p, run_mlp ? g_sel.mu : nullptr, run_mlp ? g_sel.sigma : nullptr, s);
   if (!st && run_mlp)
     st = launch_mlp_forward(theta, p.hdr->x_std, 1, p.hdr->pred, p.hdr->z1, p.hdr->z2, s);
+  if (!st && p.sell_reserved) st = launch_sell_build(p, s);
   if (!st) {
     hipError_t e = hipMemcpyAsync(&hh, p.hdr, sizeof(WsHeader), hipMemcpyDeviceToHost, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
@@ -246,6 +279,14 @@ int plan_build(Plan& p, int64_t n_rows, int64_t n_cols, int64_t nnz, const int32
   if (run_mlp) {
     std::memcpy(p.pred, hh.pred, sizeof(p.pred));
     p.have_pred = true;
+  }
+  if (p.sell_reserved) {
+    // the fill kernel reports the padded width sum even when it does not fit
+    p.sell_slots = p.sell_nch > 0 ? 64 * hh.sell_total : 0;
+    p.sell_ok = p.sell_slots >= 0 && p.sell_slots <= p.sell_cap;
+    if (!p.sell_ok && mode == SPMV_SELECT_FIXED && fixed == SPMV_V6_SELL64)
+      return fail(SPMV_ERR_UNSUPPORTED, "V6 copy needs " + std::to_string(p.sell_slots) +
+                                            " slots, reserve is " + std::to_string(p.sell_cap));
   }
   if (mode == SPMV_SELECT_FIXED) {
     p.variant = fixed;
@@ -311,6 +352,8 @@ int spmv_get_variant(spmv_handle h, int* variant) {
 int spmv_set_variant(spmv_handle h, int variant) {
   if (!h) return fail(SPMV_ERR_INVALID_ARG, "handle is null");
   if (variant < 0 || variant >= SPMV_NUM_VARIANTS) return fail(SPMV_ERR_INVALID_ARG, "variant out of range");
+  if (variant == SPMV_V6_SELL64 && !h->p.sell_ok)
+    return fail(SPMV_ERR_STATE, "this plan has no V6 copy");
   h->p.variant = variant;
   return SPMV_OK;
 }
@@ -332,6 +375,13 @@ int spmv_get_autotune_times(spmv_handle h, double* us) {
   if (!h || !us) return fail(SPMV_ERR_INVALID_ARG, "null argument");
   if (!h->p.have_autotune) return fail(SPMV_ERR_STATE, "autotune did not run for this plan");
   std::memcpy(us, h->p.at_us, sizeof(h->p.at_us));
+  return SPMV_OK;
+}
+
+int spmv_get_sell_slots(spmv_handle h, int64_t* slots) {
+  if (!h || !slots) return fail(SPMV_ERR_INVALID_ARG, "null argument");
+  if (!h->p.sell_ok) return fail(SPMV_ERR_STATE, "this plan has no V6 copy");
+  *slots = h->p.sell_slots;
   return SPMV_OK;
 }
 

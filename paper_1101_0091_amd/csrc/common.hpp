@@ -32,6 +32,7 @@ struct alignas(256) WsHeader {
   int32_t bin_count[8];
   int32_t bin_offset[8];
   int32_t bin_cursor[8];
+  int64_t sell_total;  // padded width sum of the V6 copy, in units of 64 slots
 };
 constexpr size_t kHeaderBytes = (sizeof(WsHeader) + 255) / 256 * 256;
 
@@ -61,11 +62,22 @@ struct Plan {
   double* at_C = nullptr;
   int variant = SPMV_V4_LDS_BLOCK;
   double features[SPMV_NUM_FEATURES] = {};
-  float pred[6] = {};
+  float pred[SPMV_NUM_SELECTOR_OUTPUTS] = {};
   bool have_pred = false;
-  double at_us[6] = {};
+  double at_us[SPMV_NUM_VARIANTS] = {};
   bool have_autotune = false;
   int device = 0;
+  // V6 chunked copy (present only with SPMV_FLAG_SELL)
+  int64_t sell_nch = 0;           // chunks of 64 rows
+  int64_t sell_cap = 0;           // reserved slots
+  int64_t sell_slots = 0;         // slots in use (64 * sum of chunk widths)
+  int32_t* sell_width = nullptr;  // device int32[nch]
+  int32_t* sell_off = nullptr;    // device int32[nch + 1], in units of 64 slots
+  int32_t* sell_partials = nullptr;
+  int32_t* sell_ci = nullptr;     // device int32[cap]
+  void* sell_val = nullptr;       // device val_dtype[cap]
+  bool sell_reserved = false;
+  bool sell_ok = false;
 };
 
 struct Batch {
@@ -151,6 +163,11 @@ int run_cg(const Plan& P, const double* b, double* x, double tol, int maxit, int
            bool use_graph, void* ws, int* iters, double* relres, hipStream_t s);
 int run_lanczos(const Plan& P, const double* v0, int k, double* alpha, double* beta, void* ws,
                 hipStream_t s);
+// sell.hip
+int64_t sell_chunks(int64_t n_rows);
+int64_t sell_capacity(int64_t nnz);
+int launch_sell_build(Plan& p, hipStream_t s);
+int launch_sell(const Plan& p, const void* B, double* C, hipStream_t s);
 // stream.hip
 int launch_triad(double* a, const double* b, const double* c, double s, int64_t n,
                  hipStream_t st);

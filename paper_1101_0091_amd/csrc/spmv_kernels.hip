@@ -249,6 +249,8 @@ int spmv_typed(const Plan& p, int variant, const BT* B, double* C, hipStream_t s
                                                            p.col_idx, val, B, C);
       break;
     }
+    case SPMV_V6_SELL64:
+      return launch_sell(p, B, C, s);
     default:
       return fail(SPMV_ERR_INVALID_ARG, "unknown variant");
   }

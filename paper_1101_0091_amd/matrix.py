@@ -5,7 +5,8 @@ from __future__ import annotations
 
 import numpy as np
 
-from . import (SPMV_F32, SPMV_F64, SPMV_SELECT_DEFAULT, SPMV_SELECT_MLP, dtype_code,
+from . import (SPMV_ERR_STATE, SPMV_F32, SPMV_F64, SPMV_SELECT_DEFAULT, SPMV_SELECT_MLP,
+               SpmvError, dtype_code, spmv_get_sell_slots,
                load_selector, spmv_selector_loaded, spmm_apply, spmv_apply, spmv_batch_apply,
                spmv_batch_apply_each, spmv_batch_create, spmv_batch_destroy, spmv_batch_set_mode,
                spmv_batch_get_num_tiles, spmv_batch_workspace_size, spmv_create, spmv_destroy,
@@ -71,6 +72,16 @@ class CRSMatrix:
     @property
     def num_blocks(self) -> int:
         return spmv_get_num_blocks(self.handle)
+
+    @property
+    def sell_slots(self):
+        """Slots of the V6 copy, or None if the plan has none."""
+        try:
+            return spmv_get_sell_slots(self.handle)
+        except SpmvError as e:
+            if e.status == SPMV_ERR_STATE:
+                return None
+            raise
 
     def apply(self, B, C=None, stream=None):
         import torch

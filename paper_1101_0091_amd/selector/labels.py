@@ -24,7 +24,7 @@ def time_variants(M, Bd, C, reps=7, warmup=2):
     import paper_1101_0091_amd as pkg
     s = torch.cuda.current_stream()
     out = []
-    for v in range(pkg.SPMV_NUM_VARIANTS):
+    for v in range(pkg.SPMV_NUM_SELECTOR_OUTPUTS):
         M.variant = v
         for _ in range(warmup):
             M.apply(Bd, C)

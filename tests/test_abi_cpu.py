@@ -38,6 +38,10 @@ def test_workspace_size_is_stable_and_checked():
     assert a == pkg.spmv_workspace_size(6_000_000, 6_000_000, 87_000_000)
     assert pkg.spmv_workspace_size(6_000_000, 6_000_000, 87_000_000, pkg.SPMV_SELECT_AUTOTUNE) > a
     assert pkg.spmv_workspace_size(0, 0, 0) > 0
+    # the V6 reserve: 1.5 nnz + 4096 slots (rounded up to 64) of 4 + 8 bytes
+    s = pkg.spmv_workspace_size(6_000_000, 6_000_000, 87_000_000, pkg.SPMV_FLAG_SELL)
+    cap = (87_000_000 + 43_500_000 + 4096 + 63) // 64 * 64
+    assert 12 * cap <= s - a <= 12 * cap + 4 * 6_000_000 // 64 * 3 + 4096
     with pytest.raises(pkg.SpmvError) as e:
         pkg.spmv_workspace_size(-1, 5, 5)
     assert e.value.status == pkg.SPMV_ERR_INVALID_ARG
@@ -63,7 +67,10 @@ def _create(**kw):
     (dict(row_ptr=None), pkg.SPMV_ERR_INVALID_ARG),
     (dict(col_idx=None), pkg.SPMV_ERR_INVALID_ARG),
     (dict(flags=9), pkg.SPMV_ERR_INVALID_ARG),
-    (dict(flags=pkg.SPMV_FLAG_VARIANT(6)), pkg.SPMV_ERR_INVALID_ARG),
+    (dict(flags=pkg.SPMV_FLAG_VARIANT(7)), pkg.SPMV_ERR_INVALID_ARG),
+    (dict(flags=pkg.SPMV_FLAG_VARIANT(6)), pkg.SPMV_ERR_INVALID_ARG),  # V6 without its flag
+    (dict(flags=pkg.SPMV_FLAG_VARIANT(6) | pkg.SPMV_FLAG_SELL, ws_bytes=1 << 12),
+     pkg.SPMV_ERR_WORKSPACE),
     (dict(flags=1 << 20), pkg.SPMV_ERR_INVALID_ARG),
     (dict(workspace=None), pkg.SPMV_ERR_WORKSPACE),
     (dict(workspace=0x10010), pkg.SPMV_ERR_WORKSPACE),

@@ -18,6 +18,26 @@ DEV = "cuda:0"
 NV = pkg.SPMV_NUM_VARIANTS
 
 
+SELL = pkg.SPMV_FLAG_SELL
+
+
+def variants(M):
+    """Every variant the plan has (V6 only where its chunked copy was built)."""
+    return [v for v in range(NV) if v != pkg.SPMV_V6_SELL64 or M.sell_slots is not None]
+
+
+def sell_expected(A):
+    """Slots of the V6 copy (64 x sum over 64-row chunks of the longest row)
+    and whether they fit the reserve of 1.5 nnz + 4096 slots."""
+    lens = np.diff(A.row_ptr.astype(np.int64))
+    nch = (A.n_rows + 63) // 64
+    padded = np.zeros(nch * 64, np.int64)
+    padded[:A.n_rows] = lens
+    slots = 64 * int(padded.reshape(nch, 64).max(axis=1).sum()) if nch else 0
+    cap = (A.nnz + A.nnz // 2 + 4096 + 63) // 64 * 64
+    return slots, slots <= cap
+
+
 def _gpu(x, dtype=None):
     t = torch.from_numpy(np.ascontiguousarray(x))
     return t.to(DEV) if dtype is None else t.to(DEV, dtype)
@@ -44,9 +64,9 @@ def test_all_variants_vs_oracle(name, dt):
         val_h, B_h, tdt = A.val, B, torch.float64
     Cref, S = oracle.spmv(A.n_rows, A.row_ptr, A.col_idx, val_h, B_h)
     M = pkg.CRSMatrix(A.n_rows, A.n_cols, A.row_ptr, A.col_idx, val_h, val_dtype=tdt,
-                      flags=pkg.SPMV_FLAG_VARIANT(4), device=DEV)
+                      flags=pkg.SPMV_FLAG_VARIANT(4) | SELL, device=DEV)
     Bd = _gpu(B_h)
-    for v in range(NV):
+    for v in variants(M):
         M.variant = v
         C = torch.full((A.n_rows,), float("nan"), dtype=torch.float64, device=DEV)
         M.apply(Bd, C)
@@ -62,9 +82,9 @@ def test_integer_inputs_bit_exact(dt):
     Cref, _ = oracle.spmv(A.n_rows, A.row_ptr, A.col_idx, A.val, B)
     tdt = torch.float32 if dt == "f32" else torch.float64
     M = pkg.CRSMatrix(A.n_rows, A.n_cols, A.row_ptr, A.col_idx, A.val, val_dtype=tdt,
-                      flags=pkg.SPMV_FLAG_VARIANT(0), device=DEV)
+                      flags=pkg.SPMV_FLAG_VARIANT(0) | SELL, device=DEV)
     Bd = _gpu(B, tdt)
-    for v in range(NV):
+    for v in variants(M):
         M.variant = v
         assert np.array_equal(M.apply(Bd).cpu().numpy(), Cref), v
 
@@ -73,8 +93,9 @@ def test_diagonal_bit_exact():
     n = 100_000
     rng = np.random.default_rng(5)
     d, B = rng.standard_normal(n), rng.standard_normal(n)
-    M = pkg.CRSMatrix(n, n, np.arange(n + 1), np.arange(n), d, device=DEV)
-    for v in range(NV):
+    M = pkg.CRSMatrix(n, n, np.arange(n + 1), np.arange(n), d, flags=SELL, device=DEV)
+    assert M.sell_slots == (n + 63) // 64 * 64
+    for v in variants(M):
         M.variant = v
         assert np.array_equal(M.apply(_gpu(B)).cpu().numpy(), d * B), v
 
@@ -83,7 +104,7 @@ def test_deterministic_repeats():
     A, B = case("powerlaw_60k")
     M = pkg.CRSMatrix.from_crs(A, device=DEV)
     Bd = _gpu(B)
-    for v in range(NV):
+    for v in variants(M):
         M.variant = v
         first = M.apply(Bd).clone()
         for _ in range(20):
@@ -117,14 +138,19 @@ def test_spmm_vs_oracle(k, dt):
 
 
 def test_full_size_hamiltonian_and_mesh():
-    """Workloads at full size (N = 6.0M and 21.95M), every row checked."""
+    """Workloads at full size (N = 6.0M and 21.95M), every row checked, with
+    the plans the benchmark builds (V6 copy requested; it fits the
+    Hamiltonian-like matrix and not the mesh, whose chunks are 3.7x padded)."""
     for name, A in (("hamiltonian_6M", crsgen.hamiltonian(6_000_000, seed=2)),
                     ("mesh3d_280", crsgen.mesh3d(280, seed=3)[0])):
         B = crsgen.uniform_vec(A.n_cols, 2 if name.startswith("ham") else 3)
         Cref, S = oracle.spmv(A.n_rows, A.row_ptr, A.col_idx, A.val, B)
-        M = pkg.CRSMatrix.from_crs(A, device=DEV)
+        M = pkg.CRSMatrix.from_crs(A, flags=SELL, device=DEV)
+        slots, fits = sell_expected(A)
+        assert fits == name.startswith("ham")
+        assert M.sell_slots == (slots if fits else None)
         Bd = _gpu(B)
-        for v in (4, 5, 1, 0):
+        for v in (6, 4, 5, 1, 0) if fits else (4, 5, 1, 0):
             M.variant = v
             ok, worst = oracle.bound_ok(M.apply(Bd).cpu().numpy(), Cref, A.row_ptr, S)
             assert ok, (name, v, worst)
@@ -132,9 +158,12 @@ def test_full_size_hamiltonian_and_mesh():
         v32, b32 = A.val.astype(np.float32), B.astype(np.float32)
         C32ref, S32 = oracle.spmv(A.n_rows, A.row_ptr, A.col_idx, v32, b32)
         M32 = pkg.CRSMatrix(A.n_rows, A.n_cols, A.row_ptr, A.col_idx, v32,
-                            val_dtype=torch.float32, device=DEV)
-        ok, worst = oracle.bound_ok(M32.apply(_gpu(b32)).cpu().numpy(), C32ref, A.row_ptr, S32)
-        assert ok, (name, "f32", worst)
+                            val_dtype=torch.float32, flags=SELL, device=DEV)
+        for v in (6, 4) if fits else (4,):
+            M32.variant = v
+            ok, worst = oracle.bound_ok(M32.apply(_gpu(b32)).cpu().numpy(), C32ref, A.row_ptr,
+                                        S32)
+            assert ok, (name, "f32", v, worst)
         del M, M32
         torch.cuda.empty_cache()
 
@@ -170,13 +199,62 @@ def test_bad_crs_rejected(name):
     torch.cuda.synchronize()
 
 
-def test_autotune_selects_fastest():
+@pytest.mark.parametrize("sell", [False, True])
+def test_autotune_selects_fastest(sell):
     A, B = case("hamiltonian_200k")
-    M = pkg.CRSMatrix.from_crs(A, flags=pkg.SPMV_SELECT_AUTOTUNE, device=DEV)
+    M = pkg.CRSMatrix.from_crs(A, flags=pkg.SPMV_SELECT_AUTOTUNE | (SELL if sell else 0),
+                               device=DEV)
     t = pkg.spmv_get_autotune_times(M.handle)
-    assert np.all(t > 0) and M.variant == int(np.argmin(t))
+    assert t.shape == (NV,) and np.all(t > 0) and M.variant == int(np.argmin(t))
+    assert np.isfinite(t[pkg.SPMV_V6_SELL64]) == sell
     Cref, S = oracle.spmv(A.n_rows, A.row_ptr, A.col_idx, A.val, B)
     assert oracle.bound_ok(M.apply(_gpu(B)).cpu().numpy(), Cref, A.row_ptr, S)[0]
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_sell_copy_size_and_availability(name):
+    """The V6 copy has exactly 64 x (sum of chunk widths) slots and exists iff
+    that fits the reserve; without it V6 cannot be selected."""
+    A, B = case(name)
+    slots, fits = sell_expected(A)
+    M = pkg.CRSMatrix.from_crs(A, flags=pkg.SPMV_FLAG_VARIANT(4) | SELL, device=DEV)
+    assert M.sell_slots == (slots if fits else None)
+    if fits:
+        M6 = pkg.CRSMatrix.from_crs(A, flags=pkg.SPMV_FLAG_VARIANT(6) | SELL, device=DEV)
+        assert M6.variant == 6
+        Cref, S = oracle.spmv(A.n_rows, A.row_ptr, A.col_idx, A.val, B)
+        assert oracle.bound_ok(M6.apply(_gpu(B)).cpu().numpy(), Cref, A.row_ptr, S)[0]
+    else:
+        with pytest.raises(pkg.SpmvError) as e:
+            M.variant = 6
+        assert e.value.status == pkg.SPMV_ERR_STATE and M.variant == 4
+        with pytest.raises(pkg.SpmvError) as e:
+            pkg.CRSMatrix.from_crs(A, flags=pkg.SPMV_FLAG_VARIANT(6) | SELL, device=DEV)
+        assert e.value.status == pkg.SPMV_ERR_UNSUPPORTED
+    # a plan built without the flag never has the copy
+    M0 = pkg.CRSMatrix.from_crs(A, flags=pkg.SPMV_FLAG_VARIANT(4), device=DEV)
+    assert M0.sell_slots is None
+
+
+def test_sell_padding_and_nonfinite_B():
+    """Padded slots never read B: an infinite or NaN B entry reaches only the
+    rows that reference it, as in the CRS definition."""
+    rng = np.random.default_rng(11)
+    n = 1000
+    lens = rng.integers(0, 9, size=n)
+    rp = np.concatenate([[0], np.cumsum(lens)]).astype(np.int32)
+    ci = np.concatenate([np.sort(rng.choice(n - 1, size=l, replace=False)) + 1 for l in lens]
+                        ).astype(np.int32)  # column 0 never referenced
+    va = rng.standard_normal(ci.shape[0])
+    A = crsgen.CRS(n, n, rp, ci, va)
+    B = crsgen.uniform_vec(n, 3)
+    B[0] = np.inf
+    Cref, S = oracle.spmv(n, rp, ci, va, B)
+    assert np.all(np.isfinite(Cref))
+    M = pkg.CRSMatrix.from_crs(A, flags=pkg.SPMV_FLAG_VARIANT(6) | SELL, device=DEV)
+    assert M.sell_slots > A.nnz
+    C = M.apply(_gpu(B)).cpu().numpy()
+    assert np.all(np.isfinite(C)) and oracle.bound_ok(C, Cref, rp, S)[0]
 
 
 # ------------------------------------------------------------------ batch
@@ -251,12 +329,13 @@ def test_graph_replay_matches_eager():
         pkg.spmv_graph_destroy(g2)
 
 
-def test_single_matrix_graph_replay():
-    A, B = case("mesh3d_48_permuted")
-    M = pkg.CRSMatrix.from_crs(A, device=DEV)
+@pytest.mark.parametrize("name", ["mesh3d_48_permuted", "hamiltonian_200k"])
+def test_single_matrix_graph_replay(name):
+    A, B = case(name)
+    M = pkg.CRSMatrix.from_crs(A, flags=SELL, device=DEV)
     Bd = _gpu(B)
     C = torch.zeros(A.n_rows, dtype=torch.float64, device=DEV)
-    for v in range(NV):
+    for v in variants(M):
         M.variant = v
         eager = M.apply(Bd).clone()
         s = torch.cuda.Stream()
