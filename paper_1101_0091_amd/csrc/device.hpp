@@ -125,6 +125,30 @@ struct BlockLds {
   double last_part;
 };
 
+// Sum of L.prod[k] for k = k0, k0 + STEP, ... < z with four independent
+// accumulators (LDS reads overlap instead of forming one latency chain),
+// combined in a fixed order.
+template <int STEP>
+__device__ __forceinline__ double lds_strided_sum(const BlockLds& L, int32_t k0, int32_t z) {
+  double p0 = 0.0, p1 = 0.0, p2 = 0.0, p3 = 0.0;
+  int32_t k = k0;
+  for (; k + 3 * STEP < z; k += 4 * STEP) {
+    p0 += L.prod[k];
+    p1 += L.prod[k + STEP];
+    p2 += L.prod[k + 2 * STEP];
+    p3 += L.prod[k + 3 * STEP];
+  }
+  for (; k < z; k += STEP) p0 += L.prod[k];
+  return (p0 + p1) + (p2 + p3);
+}
+
+// Phase 2 of the row block: rows [r0, r1) reduced from LDS. Groups of G
+// lanes take one row each; every lane of a wavefront runs the same number of
+// rounds, so the cross-lane steps see all lanes active. A row with more than
+// 32 G products in the chunk would make its G lanes the wavefront's
+// straggler (power-law rows next to hundreds of short ones); such rows are
+// collected with a ballot and summed one after another by the whole
+// wavefront. The tail row's in-chunk sum goes to *last_part.
 // ACC: add to C instead of overwriting it (second pass of a split product).
 template <int G, bool ACC>
 __device__ __forceinline__ void block_rows(const BlockLds& L, const int32_t* __restrict__ rp,
@@ -132,21 +156,38 @@ __device__ __forceinline__ void block_rows(const BlockLds& L, const int32_t* __r
                                            bool tail, double* __restrict__ C,
                                            double* last_part) {
   const int tid = threadIdx.x;
+  const int wl = tid & 63;
   const int lane = tid & (G - 1);
-  const int group = tid / G;
   constexpr int ngroups = kWG / G;
-  for (int32_t r = r0 + group; r < r1; r += ngroups) {
-    const int32_t a = rp[r] - S;
-    int32_t z = rp[r + 1];
-    z = (z < cend ? z : cend) - S;
-    double part = 0.0;
-    for (int32_t k = a + lane; k < z; k += G) part += L.prod[k];
+  constexpr int32_t kLong = 32 * G;
+  for (int32_t rw = r0 + (tid & ~63) / G; rw < r1; rw += ngroups) {
+    const int32_t r = rw + wl / G;
+    const bool valid = r < r1;
+    int32_t a = 0, z = 0;
+    if (valid) {
+      a = rp[r] - S;
+      const int32_t e = rp[r + 1];
+      z = (e < cend ? e : cend) - S;
+    }
+    const bool lng = valid && z - a > kLong;
+    const double part = (valid && !lng) ? lds_strided_sum<G>(L, a + lane, z) : 0.0;
     const double sum = group_sum<G>(part);
-    if (lane == 0) {
+    if (valid && !lng && lane == 0) {
       if (tail && r == r1 - 1)
         *last_part = sum;
       else
         C[r] = ACC ? C[r] + sum : sum;
+    }
+    for (uint64_t m = __ballot(lng && lane == 0); m; m &= m - 1) {
+      const int src = __ffsll((unsigned long long)m) - 1;
+      const int32_t ra = __shfl(a, src), rz = __shfl(z, src), rr = __shfl(r, src);
+      const double s = group_sum<64>(lds_strided_sum<64>(L, ra + wl, rz));
+      if (wl == 0) {
+        if (tail && rr == r1 - 1)
+          *last_part = s;
+        else
+          C[rr] = ACC ? C[rr] + s : s;
+      }
     }
   }
 }
