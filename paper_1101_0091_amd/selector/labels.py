@@ -17,14 +17,14 @@ SEED = 5
 NLO, NHI = 1e4, 2e7
 
 
-def time_variants(M, Bd, C, reps=7, warmup=2):
+def time_variants(M, Bd, C, reps=7, warmup=2, variants=None):
     import numpy as np
     import torch
 
     import paper_1101_0091_amd as pkg
     s = torch.cuda.current_stream()
     out = []
-    for v in range(pkg.SPMV_NUM_SELECTOR_OUTPUTS):
+    for v in (range(pkg.SPMV_NUM_SELECTOR_OUTPUTS) if variants is None else variants):
         M.variant = v
         for _ in range(warmup):
             M.apply(Bd, C)
@@ -64,13 +64,20 @@ def main(argv=None):
         A, prm = crsgen.family_matrix(SEED, i, NLO, NHI)
         B = crsgen.uniform_vec(A.n_cols, SEED)
         tg = time.time() - t0
-        M = pkg.CRSMatrix.from_crs(A, flags=pkg.SPMV_FLAG_VARIANT(4), device=dev)
+        M = pkg.CRSMatrix.from_crs(A, flags=pkg.SPMV_FLAG_VARIANT(4) | pkg.SPMV_FLAG_SELL,
+                                   device=dev)
         Bd = torch.from_numpy(B).to(dev)
         C = torch.empty(A.n_rows, dtype=torch.float64, device=dev)
         us = time_variants(M, Bd, C)
+        # V6 (chunked copy) is outside the selector's outputs; its time is kept
+        # for reference where the copy fits its reserve
+        us6 = (time_variants(M, Bd, C, variants=(pkg.SPMV_V6_SELL64,))[0]
+               if M.sell_slots is not None else None)
         rec = {"id": i, "n": A.n_rows, "nnz": A.nnz, "family": crsgen.FAMILY_NAMES[prm["family"]],
                "width": prm["width"], "features": [float(x) for x in M.features],
-               "us": [round(t, 3) for t in us], "gen_s": round(tg, 2)}
+               "us": [round(t, 3) for t in us], "gen_s": round(tg, 2),
+               "us_v6": None if us6 is None else round(us6, 3),
+               "sell_slots": M.sell_slots}
         with open(args.out, "a") as f:
             f.write(json.dumps(rec) + "\n")
         print(f"[labels] {i} n={A.n_rows} nnz={A.nnz} {rec['family']} best=V{us.index(min(us))} "
