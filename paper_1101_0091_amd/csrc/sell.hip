@@ -1,12 +1,15 @@
 // Variant V6: the CRS product of Sect. 1.2 computed from a chunked copy of
 // the matrix. Rows are cut into chunks of 64 consecutive rows (one chunk per
-// wavefront, no reordering); a chunk is stored column by column with the
-// width of its longest row, so slot (j, lane) of chunk k holds the j-th
-// nonzero of row 64 k + lane. Shorter rows are padded with col = -1, val = 0.
-// This is a sliced ELLPACK layout with slice height 64 (the SELL-C-sigma
-// family with C = 64, sigma = 1). Every load of val and col_idx is then one
-// contiguous 512- or 256-byte access per wavefront, no LDS or barrier is
-// needed, and each row is still summed in CRS order by one lane.
+// wavefront, no reordering); chunk k has the width w of its longest row and
+// 64 w slots; slot (j, lane) holds the j-th nonzero of row 64 k + lane.
+// Shorter rows are padded with col = -1, val = 0. This is a sliced ELLPACK
+// layout with slice height 64 (the SELL-C-sigma family with C = 64,
+// sigma = 1). Inside a chunk the slots are stored in lane-interleaved pairs:
+// with P = floor(w / 2), slots 2p and 2p + 1 of lane l sit at 2 (64 p + l) and
+// 2 (64 p + l) + 1, and for odd w the last slot of lane l at 128 P + l. Each
+// lane then loads two slots of its row per instruction, and every load is one
+// contiguous 1 KB (val, float64) or 512-byte access per wavefront; no LDS or
+// barrier is needed, and each row is still summed in CRS order by one lane.
 //
 // The copy is built on the device at plan creation in three passes: chunk
 // widths, an exclusive scan of the widths, and the fill. Its capacity is
@@ -19,7 +22,20 @@ namespace spmv {
 namespace {
 
 constexpr int kChunk = 64;  // rows per chunk = lanes per wavefront
-constexpr int kSellU = 16;  // slots of one row loaded before the first is used
+constexpr int kSellUP = 8;  // slot pairs of one row loaded before the first is used
+
+typedef double f64x2 __attribute__((ext_vector_type(2)));
+typedef float f32x2 __attribute__((ext_vector_type(2)));
+typedef int32_t i32x2 __attribute__((ext_vector_type(2)));
+template <typename VT> struct Pair;
+template <> struct Pair<double> { using type = f64x2; };
+template <> struct Pair<float> { using type = f32x2; };
+
+// Offset of slot j of `lane` inside a chunk of width w (see the layout above).
+__device__ __forceinline__ int64_t slot_offset(int64_t j, int lane, int64_t w) {
+  const int64_t P = w >> 1;
+  return j < 2 * P ? 2 * ((j >> 1) * kChunk + lane) + (j & 1) : 2 * P * kChunk + lane;
+}
 
 // Clamped row range: an invalid pattern (reported by validation, which runs
 // earlier in the same stream) never makes these kernels read out of bounds.
@@ -69,58 +85,73 @@ __global__ __launch_bounds__(kWG) void k_sell_fill(
   const int lane = threadIdx.x % kChunk;
   int64_t s, e;
   row_range(chunk * kChunk + lane, n, nnz, rp, s, e);
-  const int64_t len = e - s;
-  int32_t* dc = sci + a * kChunk + lane;
-  VT* dv = sval + a * kChunk + lane;
-  for (int64_t j = 0; j < b - a; ++j) {
+  const int64_t len = e - s, w = b - a;
+  int32_t* dc = sci + a * kChunk;
+  VT* dv = sval + a * kChunk;
+  for (int64_t j = 0; j < w; ++j) {
+    const int64_t o = slot_offset(j, lane, w);
     if (j < len) {
-      dc[j * kChunk] = ci[s + j];
-      dv[j * kChunk] = val[s + j];
+      dc[o] = ci[s + j];
+      dv[o] = val[s + j];
     } else {
-      dc[j * kChunk] = -1;
-      dv[j * kChunk] = (VT)0;
+      dc[o] = -1;
+      dv[o] = (VT)0;
     }
   }
 }
 
 // C = A*B from the chunked copy: lane l of the wavefront of chunk k owns row
-// 64 k + l and sums its slots in order. The width is uniform over the
-// wavefront, so the loop and its masked last round are uniform branches.
+// 64 k + l and sums its slots in order, kSellUP pairs per round, the odd last
+// slot after the rounds. The width is uniform over the wavefront, so the loop
+// and its masked last round are uniform branches.
 template <typename VT, typename BT>
 __global__ __launch_bounds__(kWG) void k_sell(int64_t nch, int64_t n,
                                               const int32_t* __restrict__ off,
                                               const int32_t* __restrict__ sci,
                                               const VT* __restrict__ sval,
                                               const BT* __restrict__ B, double* __restrict__ C) {
+  using V2 = typename Pair<VT>::type;
   const int64_t chunk = ((int64_t)blockIdx.x * kWG + threadIdx.x) / kChunk;
   if (chunk >= nch) return;
   const int lane = threadIdx.x % kChunk;
   const int64_t a = off[chunk];
   const int32_t w = (int32_t)(off[chunk + 1] - a);
-  const VT* vp = sval + a * kChunk + lane;
-  const int32_t* cp = sci + a * kChunk + lane;
+  const int32_t P = w >> 1;
+  const V2* vp = reinterpret_cast<const V2*>(sval + a * kChunk) + lane;
+  const i32x2* cp = reinterpret_cast<const i32x2*>(sci + a * kChunk) + lane;
   double acc = 0.0;
-  for (int32_t j = 0; j < w; j += kSellU) {
-    VT v[kSellU];
-    int32_t c[kSellU];
-    double x[kSellU];
+  // padded and masked slots contribute fma(0, 0, acc) = acc exactly: acc
+  // starts at +0, and a round-to-nearest sum with a +0 operand is never -0,
+  // so acc is never -0
+  for (int32_t p = 0; p < P; p += kSellUP) {
+    V2 v[kSellUP];
+    i32x2 c[kSellUP];
+    double x0[kSellUP], x1[kSellUP];
 #pragma unroll
-    for (int u = 0; u < kSellU; ++u) {
-      if (j + u < w) {
-        v[u] = dev::ld_stream(vp + (int64_t)(j + u) * kChunk);
-        c[u] = dev::ld_stream(cp + (int64_t)(j + u) * kChunk);
+    for (int u = 0; u < kSellUP; ++u) {
+      if (p + u < P) {
+        v[u] = dev::ld_stream(vp + (int64_t)(p + u) * kChunk);
+        c[u] = dev::ld_stream(cp + (int64_t)(p + u) * kChunk);
       } else {
-        v[u] = (VT)0;
-        c[u] = -1;
+        v[u] = V2{(VT)0, (VT)0};
+        c[u] = i32x2{-1, -1};
       }
     }
 #pragma unroll
-    for (int u = 0; u < kSellU; ++u) x[u] = c[u] >= 0 ? (double)B[c[u]] : 0.0;
-    // padded and masked slots contribute fma(0, 0, acc) = acc exactly: acc
-    // starts at +0, and a round-to-nearest sum with a +0 operand is never -0,
-    // so acc is never -0
+    for (int u = 0; u < kSellUP; ++u) {
+      x0[u] = c[u].x >= 0 ? (double)B[c[u].x] : 0.0;
+      x1[u] = c[u].y >= 0 ? (double)B[c[u].y] : 0.0;
+    }
 #pragma unroll
-    for (int u = 0; u < kSellU; ++u) acc = fma(dev::widen(v[u]), x[u], acc);
+    for (int u = 0; u < kSellUP; ++u) {
+      acc = fma(dev::widen(v[u].x), x0[u], acc);
+      acc = fma(dev::widen(v[u].y), x1[u], acc);
+    }
+  }
+  if (w & 1) {
+    const int64_t o = a * kChunk + 2 * (int64_t)P * kChunk + lane;
+    const int32_t c = dev::ld_stream(sci + o);
+    if (c >= 0) acc = fma(dev::widen(dev::ld_stream(sval + o)), (double)B[c], acc);
   }
   const int64_t row = chunk * kChunk + lane;
   if (row < n) C[row] = acc;
