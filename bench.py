@@ -30,9 +30,15 @@ def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
-def kernel_source_hash() -> str:
+# sources that define each variant's product kernel (a stored counter record
+# is valid only while these files are unchanged)
+KERNEL_SOURCES = {"V6_sell64": ("sell.hip", "device.hpp", "common.hpp")}
+DEFAULT_SOURCES = ("spmv_kernels.hip", "device.hpp", "common.hpp")
+
+
+def kernel_source_hash(variant_name: str) -> str:
     h = hashlib.sha256()
-    for f in ("device.hpp", "spmv_kernels.hip", "common.hpp", "sell.hip"):
+    for f in KERNEL_SOURCES.get(variant_name, DEFAULT_SOURCES):
         h.update(open(os.path.join(ROOT, "paper_1101_0091_amd", "csrc", f), "rb").read())
     return h.hexdigest()[:16]
 
@@ -46,7 +52,7 @@ def stored_traffic(workload: str, variant_name: str):
     try:
         d = json.load(open(path))
         e = d.get(f"{workload}/{variant_name}")
-        if e and e.get("kernel_source_hash") == kernel_source_hash():
+        if e and e.get("kernel_source_hash") == kernel_source_hash(variant_name):
             return e["hbm_bytes_per_launch"]
     except (ValueError, KeyError):
         pass

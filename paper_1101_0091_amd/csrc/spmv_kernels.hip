@@ -4,6 +4,8 @@
 // loop) with float64 accumulation; they differ only in how rows and nonzeros
 // are mapped onto lanes. Each output element is reduced by one lane group in
 // an order fixed by the matrix structure, so results are reproducible.
+#include <type_traits>
+
 #include "common.hpp"
 #include "device.hpp"
 
@@ -108,7 +110,12 @@ __global__ __launch_bounds__(kWG) void k_lds_block(int64_t nblocks, const int2* 
 
 // ---------------------------------------------------------------- SpMM
 // LPR lanes per row; lane l owns columns [c0, c0+CPL) with c0 = l*CPL + t*LPR*CPL.
-// Each gathered B row segment is a contiguous CPL-wide vector load.
+// Each gathered B row segment is loaded as 16-byte vectors (CPL = 4 in
+// float64 is two of them). A row is processed kSpmmU entries per round: all
+// val/col loads of the round first, then all B segments, then the FMAs, so a
+// short row costs three dependent round trips instead of one per entry pair.
+constexpr int kSpmmU = 8;
+
 template <typename T, int N>
 struct Vec;
 template <>
@@ -121,19 +128,35 @@ template <>
 struct Vec<float, 4> { using type = float4; };
 
 template <typename BT, int CPL>
-__device__ __forceinline__ void load_vec(const BT* p, double (&out)[CPL]) {
-  using V = typename Vec<BT, CPL>::type;
-  V x = *reinterpret_cast<const V*>(p);
-  if constexpr (CPL == 1) {
-    out[0] = (double)x;
-  } else if constexpr (CPL == 2) {
-    out[0] = (double)x.x; out[1] = (double)x.y;
+__device__ __forceinline__ void load_vec(const BT* p, double* out) {
+  if constexpr (std::is_same<BT, double>::value && CPL == 4) {
+    load_vec<double, 2>(p, out);
+    load_vec<double, 2>(p + 2, out + 2);
   } else {
-    out[0] = (double)x.x; out[1] = (double)x.y; out[2] = (double)x.z; out[3] = (double)x.w;
+    using V = typename Vec<BT, CPL>::type;
+    V x = *reinterpret_cast<const V*>(p);
+    if constexpr (CPL == 1) {
+      out[0] = (double)x;
+    } else if constexpr (CPL == 2) {
+      out[0] = (double)x.x; out[1] = (double)x.y;
+    } else {
+      out[0] = (double)x.x; out[1] = (double)x.y; out[2] = (double)x.z; out[3] = (double)x.w;
+    }
   }
 }
 
-template <typename VT, typename BT, int LPR, int CPL>
+template <int CPL>
+__device__ __forceinline__ void store_vec(double* p, const double* x) {
+  if constexpr (CPL == 1) {
+    p[0] = x[0];
+  } else {
+#pragma unroll
+    for (int t = 0; t < CPL; t += 2) *reinterpret_cast<double2*>(p + t) = double2{x[t], x[t + 1]};
+  }
+}
+
+// VST: C rows are 16-byte aligned (vector stores of full column groups).
+template <typename VT, typename BT, int LPR, int CPL, bool VST>
 __global__ __launch_bounds__(kWG) void k_spmm(int32_t nrows, int32_t k,
                                               const int32_t* __restrict__ rp,
                                               const int32_t* __restrict__ ci,
@@ -148,44 +171,53 @@ __global__ __launch_bounds__(kWG) void k_spmm(int32_t nrows, int32_t k,
     double acc[CPL];
 #pragma unroll
     for (int t = 0; t < CPL; ++t) acc[t] = 0.0;
-    const bool full = c0 + CPL <= k;
-    int32_t j = s;
-    for (; j + 2 <= e; j += 2) {
-      const double v0 = widen(val[j]), v1 = widen(val[j + 1]);
-      const int64_t o0 = (int64_t)ci[j] * ldb + c0, o1 = (int64_t)ci[j + 1] * ldb + c0;
-      double b0[CPL], b1[CPL];
-      if (full) {
-        load_vec<BT, CPL>(B + o0, b0);
-        load_vec<BT, CPL>(B + o1, b1);
-      } else {
-#pragma unroll
-        for (int t = 0; t < CPL; ++t) {
-          b0[t] = c0 + t < k ? (double)B[o0 + t] : 0.0;
-          b1[t] = c0 + t < k ? (double)B[o1 + t] : 0.0;
-        }
-      }
-#pragma unroll
-      for (int t = 0; t < CPL; ++t) acc[t] = fma(v0, b0[t], acc[t]);
-#pragma unroll
-      for (int t = 0; t < CPL; ++t) acc[t] = fma(v1, b1[t], acc[t]);
-    }
-    if (j < e) {
-      const double v0 = widen(val[j]);
-      const int64_t o0 = (int64_t)ci[j] * ldb + c0;
-      double b0[CPL];
-      if (full) {
-        load_vec<BT, CPL>(B + o0, b0);
-      } else {
-#pragma unroll
-        for (int t = 0; t < CPL; ++t) b0[t] = c0 + t < k ? (double)B[o0 + t] : 0.0;
-      }
-#pragma unroll
-      for (int t = 0; t < CPL; ++t) acc[t] = fma(v0, b0[t], acc[t]);
-    }
     double* out = C + row * ldc + c0;
+    if (c0 + CPL <= k) {
+      // full column group: vector loads of B, masked entries read nothing
+      for (int32_t j = s; j < e; j += kSpmmU) {
+        double v[kSpmmU];
+        int32_t c[kSpmmU];
 #pragma unroll
-    for (int t = 0; t < CPL; ++t)
-      if (c0 + t < k) out[t] = acc[t];
+        for (int u = 0; u < kSpmmU; ++u) {
+          const bool in = j + u < e;
+          v[u] = in ? widen(val[j + u]) : 0.0;
+          c[u] = in ? ci[j + u] : -1;
+        }
+        double b[kSpmmU][CPL];
+#pragma unroll
+        for (int u = 0; u < kSpmmU; ++u) {
+          if (c[u] >= 0) {
+            load_vec<BT, CPL>(B + (int64_t)c[u] * ldb + c0, b[u]);
+          } else {
+#pragma unroll
+            for (int t = 0; t < CPL; ++t) b[u][t] = 0.0;
+          }
+        }
+        // masked entries add fma(0, 0, acc) = acc exactly (acc is never -0)
+#pragma unroll
+        for (int u = 0; u < kSpmmU; ++u)
+#pragma unroll
+          for (int t = 0; t < CPL; ++t) acc[t] = fma(v[u], b[u][t], acc[t]);
+      }
+      if (VST) {
+        store_vec<CPL>(out, acc);
+      } else {
+#pragma unroll
+        for (int t = 0; t < CPL; ++t) out[t] = acc[t];
+      }
+    } else {
+      // last, partial column group (k not a multiple of CPL): scalar loads
+      for (int32_t j = s; j < e; ++j) {
+        const double v = widen(val[j]);
+        const int64_t o = (int64_t)ci[j] * ldb + c0;
+#pragma unroll
+        for (int t = 0; t < CPL; ++t)
+          if (c0 + t < k) acc[t] = fma(v, (double)B[o + t], acc[t]);
+      }
+#pragma unroll
+      for (int t = 0; t < CPL; ++t)
+        if (c0 + t < k) out[t] = acc[t];
+    }
   }
 }
 
@@ -258,7 +290,7 @@ int spmv_typed(const Plan& p, int variant, const BT* B, double* C, hipStream_t s
   return SPMV_OK;
 }
 
-template <typename VT, typename BT, int CPL>
+template <typename VT, typename BT, int CPL, bool VST>
 int spmm_lpr(const Plan& p, int k, const BT* B, int64_t ldb, double* C, int64_t ldc,
              hipStream_t s) {
   const VT* val = static_cast<const VT*>(p.val);
@@ -266,11 +298,10 @@ int spmm_lpr(const Plan& p, int k, const BT* B, int64_t ldb, double* C, int64_t 
   int need = (k + CPL - 1) / CPL;
   int lpr = 1;
   while (lpr < need && lpr < 64) lpr *= 2;
-#define SPMM_CASE(L)                                                                       \
-  case L:                                                                                  \
-    k_spmm<VT, BT, L, CPL><<<grid_for((int64_t)n * L), kWG, 0, s>>>(n, k, p.row_ptr,       \
-                                                                   p.col_idx, val, B, ldb, \
-                                                                   C, ldc);                \
+#define SPMM_CASE(L)                                                                        \
+  case L:                                                                                   \
+    k_spmm<VT, BT, L, CPL, VST><<<grid_for((int64_t)n * L), kWG, 0, s>>>(                   \
+        n, k, p.row_ptr, p.col_idx, val, B, ldb, C, ldc);                                   \
     break;
   switch (lpr) {
     SPMM_CASE(1)
@@ -284,6 +315,14 @@ int spmm_lpr(const Plan& p, int k, const BT* B, int64_t ldb, double* C, int64_t 
 #undef SPMM_CASE
   SPMV_HIP(hipGetLastError());
   return SPMV_OK;
+}
+
+template <typename VT, typename BT, int CPL>
+int spmm_store(const Plan& p, int k, const BT* B, int64_t ldb, double* C, int64_t ldc,
+               hipStream_t s) {
+  const bool vst = CPL > 1 && reinterpret_cast<uintptr_t>(C) % 16 == 0 && ldc % 2 == 0;
+  return vst ? spmm_lpr<VT, BT, CPL, (CPL > 1)>(p, k, B, ldb, C, ldc, s)
+             : spmm_lpr<VT, BT, CPL, false>(p, k, B, ldb, C, ldc, s);
 }
 
 template <typename VT, typename BT>
@@ -315,14 +354,16 @@ int launch_spmm(const Plan& p, int k, const void* B, int64_t ldb, double* C, int
   const uintptr_t a = reinterpret_cast<uintptr_t>(B);
   if (p.vdt == SPMV_F64) {
     const double* b = static_cast<const double*>(B);
+    if (k >= 4 && a % 16 == 0 && ldb % 2 == 0)
+      return spmm_store<double, double, 4>(p, k, b, ldb, C, ldc, s);
     if (k >= 2 && a % 16 == 0 && ldb % 2 == 0)
-      return spmm_lpr<double, double, 2>(p, k, b, ldb, C, ldc, s);
-    return spmm_lpr<double, double, 1>(p, k, b, ldb, C, ldc, s);
+      return spmm_store<double, double, 2>(p, k, b, ldb, C, ldc, s);
+    return spmm_store<double, double, 1>(p, k, b, ldb, C, ldc, s);
   }
   const float* b = static_cast<const float*>(B);
   if (k >= 4 && a % 16 == 0 && ldb % 4 == 0)
-    return spmm_lpr<float, float, 4>(p, k, b, ldb, C, ldc, s);
-  return spmm_lpr<float, float, 1>(p, k, b, ldb, C, ldc, s);
+    return spmm_store<float, float, 4>(p, k, b, ldb, C, ldc, s);
+  return spmm_store<float, float, 1>(p, k, b, ldb, C, ldc, s);
 }
 
 int launch_fill(void* dst, int dtype, int64_t n, double value, hipStream_t s) {

@@ -12,3 +12,14 @@ def test_more_than_one_gpu_is_refused():
     assert r.returncode == 2
     assert "one GPU" in r.stderr
     assert r.stdout == ""
+
+
+def test_kernel_source_hash_is_per_variant():
+    """A stored counter record names the sources of its own kernel only, so an
+    edit to another variant's file does not invalidate it."""
+    import bench
+    h6 = bench.kernel_source_hash("V6_sell64")
+    h4 = bench.kernel_source_hash("V4_lds_block")
+    assert len(h6) == 16 and h6 == bench.kernel_source_hash("V6_sell64")
+    assert h6 != h4 and h4 == bench.kernel_source_hash("V0_thread_row")
+    assert "spmv_kernels.hip" not in bench.KERNEL_SOURCES["V6_sell64"]
