@@ -389,3 +389,45 @@ def test_spmm_fp32_storage_error_per_column():
     assert np.all(np.abs(C - Cref) <= (2.0 ** -23 + 2.0 ** -48 + 2 * gam * (1 + 2.0 ** -23)) * S)
     col_err = np.linalg.norm(C - Cref, axis=0) / np.linalg.norm(Cref, axis=0)
     assert np.all(col_err < 1e-6)
+
+
+def _banded_ragged(n, half, seed, jitter):
+    """Rows i with columns [i-half, i+half] clipped, a seeded number (0..jitter)
+    of them dropped per row, so chunk widths are odd and even and rows inside
+    a chunk differ in length."""
+    rng = np.random.default_rng(seed)
+    rows, cols = [], []
+    for i in range(n):
+        c = np.arange(max(0, i - half), min(n, i + half + 1))
+        drop = rng.integers(0, jitter + 1)
+        if drop:
+            c = np.delete(c, rng.choice(len(c), size=min(drop, len(c)), replace=False))
+        rows.append(np.full(len(c), i))
+        cols.append(c)
+    lens = np.array([len(c) for c in cols])
+    rp = np.concatenate([[0], np.cumsum(lens)]).astype(np.int32)
+    ci = np.concatenate(cols).astype(np.int32)
+    return crsgen.CRS(n, n, rp, ci, rng.standard_normal(ci.shape[0]))
+
+
+@pytest.mark.parametrize("dt", ["f64", "f32"])
+@pytest.mark.parametrize("n,half,jitter", [(10_007, 20, 3), (4_099, 7, 1), (130, 1, 1),
+                                           (65, 40, 0), (64, 0, 0)])
+def test_sell_layout_rounds_and_ragged_tail(n, half, jitter, dt):
+    """V6 over chunk widths that need several 8-pair rounds, odd last slots,
+    rows of different lengths inside a chunk and a ragged last chunk."""
+    A = _banded_ragged(n, half, seed=n, jitter=jitter)
+    B = crsgen.uniform_vec(n, 9)
+    if dt == "f32":
+        val, Bh, tdt = A.val.astype(np.float32), B.astype(np.float32), torch.float32
+    else:
+        val, Bh, tdt = A.val, B, torch.float64
+    Cref, S = oracle.spmv(n, A.row_ptr, A.col_idx, val, Bh)
+    M = pkg.CRSMatrix(n, n, A.row_ptr, A.col_idx, val, val_dtype=tdt,
+                      flags=pkg.SPMV_FLAG_VARIANT(6) | SELL, device=DEV)
+    slots, fits = sell_expected(A)
+    assert fits and M.sell_slots == slots
+    C = torch.full((n,), float("nan"), dtype=torch.float64, device=DEV)
+    M.apply(_gpu(Bh), C)
+    ok, worst = oracle.bound_ok(C.cpu().numpy(), Cref, A.row_ptr, S)
+    assert ok, worst
