@@ -153,9 +153,11 @@ int spmv_get_features(spmv_handle h, double* features);
 /* The selector's predicted relative log2 times of V0..V5 from create (host
  * out, float[SPMV_NUM_SELECTOR_OUTPUTS]); SPMV_ERR_STATE if no selector ran. */
 int spmv_get_predictions(spmv_handle h, float* pred);
-/* Per-variant median times in microseconds measured by SPMV_SELECT_AUTOTUNE
- * (host out, double[SPMV_NUM_VARIANTS]; +infinity for a variant the plan does
- * not have); SPMV_ERR_STATE if autotune did not run. */
+/* Per-variant times in microseconds measured by SPMV_SELECT_AUTOTUNE (host
+ * out, double[SPMV_NUM_VARIANTS]): the median of five timed launches for a
+ * variant within 1.5x of the best time seen before it, else its single timed
+ * launch; +infinity for a variant the plan does not have. SPMV_ERR_STATE if
+ * autotune did not run. */
 int spmv_get_autotune_times(spmv_handle h, double* us);
 /* Slots of the V6 copy (host out): 64 * sum of chunk widths, >= nnz; the
  * padding is slots - nnz. SPMV_ERR_STATE if the plan has no V6 copy. */

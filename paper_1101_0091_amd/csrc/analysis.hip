@@ -2,6 +2,7 @@
 // (the selector's 16 features), row-length bins, and the nnz-balanced row
 // blocks. Done once per pattern and reused by every product, as the paper
 // does for its communication bookkeeping (Sect. 3.1).
+#include <algorithm>
 #include <cmath>
 
 #include "common.hpp"
@@ -52,59 +53,81 @@ __device__ __forceinline__ T wave_sum(T x) {
   return x;
 }
 
-// Row statistics. Every row range is clamped to [0, nnz] so that an invalid
-// pattern (reported by k_validate in the same pass) never reads out of bounds.
+// Partial-counter slots of one statistics workgroup.
+enum : int {
+  P_SUMSQ = 0, P_LMAX = 1, P_LMIN = 2, P_BIN0 = 3,  // feature bins P_BIN0..P_BIN0+5
+  P_LONGNNZ = 9, P_DISTLOG = 10, P_NEAR = 11, P_NNZ = 12, P_VB0 = 13  // variant bins ..+4
+};
+static_assert(P_VB0 + kNumBins == kPartSlots, "partial slots");
+
+// Workgroup w of a g-workgroup pass owns rows [w*R, min(n, (w+1)*R)), R = ceil(n/g).
+__device__ __forceinline__ void row_range_of(int64_t n, int64_t w, int64_t g, int64_t& r0,
+                                             int64_t& r1) {
+  const int64_t R = (n + g - 1) / g;
+  r0 = w * R < n ? w * R : n;
+  r1 = r0 + R < n ? r0 + R : n;
+}
+
+// Row statistics. Each workgroup reduces its rows in registers and LDS and
+// writes one record of partial counters (no atomics; k_finalize combines the
+// records in a fixed order). Every row range is clamped to [0, nnz] so that
+// an invalid pattern (reported by k_validate in the same pass) never reads
+// out of bounds.
 __global__ __launch_bounds__(kWG) void k_stats(int64_t n, int64_t nnz,
                                                const int32_t* __restrict__ rp,
-                                               const int32_t* __restrict__ ci, WsHeader* h) {
-  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-  unsigned long long sumsq = 0, bins[6] = {0, 0, 0, 0, 0, 0}, longnnz = 0, distlog = 0,
-                     near = 0, total = 0;
-  unsigned long long lmax = 0, lmin = ~0ull;
-  unsigned long long vb[kNumBins] = {0, 0, 0, 0, 0};
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
+                                               const int32_t* __restrict__ ci,
+                                               unsigned long long* __restrict__ part) {
+  __shared__ unsigned long long red[kWG / 64][kPartSlots];
+  unsigned long long v[kPartSlots];
+  for (int q = 0; q < kPartSlots; ++q) v[q] = 0;
+  v[P_LMIN] = ~0ull;
+  int64_t r0, r1;
+  row_range_of(n, blockIdx.x, gridDim.x, r0, r1);
+  for (int64_t i = r0 + threadIdx.x; i < r1; i += kWG) {
     int64_t s = rp[i], e = rp[i + 1];
     s = s < 0 ? 0 : s > nnz ? nnz : s;
     e = e < s ? s : e > nnz ? nnz : e;
     const int64_t l = e - s;
     const unsigned long long ul = (unsigned long long)l;
-    total += ul;
-    sumsq += ul * ul;
-    lmax = ul > lmax ? ul : lmax;
-    lmin = ul < lmin ? ul : lmin;
-    bins[feature_bin(l)] += 1;
-    vb[variant_bin(l)] += 1;
-    if (l > 64) longnnz += ul;
+    v[P_NNZ] += ul;
+    v[P_SUMSQ] += ul * ul;
+    v[P_LMAX] = ul > v[P_LMAX] ? ul : v[P_LMAX];
+    v[P_LMIN] = ul < v[P_LMIN] ? ul : v[P_LMIN];
+    v[P_BIN0 + feature_bin(l)] += 1;
+    v[P_VB0 + variant_bin(l)] += 1;
+    if (l > 64) v[P_LONGNNZ] += ul;
+    unsigned long long dl = 0, nr = 0;
     for (int64_t j = s; j < e; ++j) {
       int64_t d = (int64_t)ci[j] - i;
       d = d < 0 ? -d : d;
-      distlog += (unsigned long long)(63 - __clzll((unsigned long long)d + 1));
-      near += d <= 64;
+      dl += (unsigned long long)(63 - __clzll((unsigned long long)d + 1));
+      nr += d <= 64;
+    }
+    v[P_DISTLOG] += dl;
+    v[P_NEAR] += nr;
+  }
+  for (int q = 0; q < kPartSlots; ++q) {
+    if (q == P_LMAX || q == P_LMIN) {
+      for (int o = 32; o >= 1; o >>= 1) {
+        const unsigned long long x = __shfl_xor(v[q], o);
+        v[q] = q == P_LMAX ? (x > v[q] ? x : v[q]) : (x < v[q] ? x : v[q]);
+      }
+    } else {
+      v[q] = wave_sum(v[q]);
     }
   }
-  // one atomic per wave per counter
-  sumsq = wave_sum(sumsq);
-  longnnz = wave_sum(longnnz);
-  distlog = wave_sum(distlog);
-  near = wave_sum(near);
-  total = wave_sum(total);
-  for (int b = 0; b < 6; ++b) bins[b] = wave_sum(bins[b]);
-  for (int b = 0; b < kNumBins; ++b) vb[b] = wave_sum(vb[b]);
-  for (int o = 32; o >= 1; o >>= 1) {
-    unsigned long long a = __shfl_xor(lmax, o), c = __shfl_xor(lmin, o);
-    lmax = a > lmax ? a : lmax;
-    lmin = c < lmin ? c : lmin;
-  }
-  if ((threadIdx.x & 63) == 0) {
-    atomicAdd(&h->cnt[C_SUMSQ], sumsq);
-    atomicAdd(&h->cnt[C_LONGNNZ], longnnz);
-    atomicAdd(&h->cnt[C_DISTLOG], distlog);
-    atomicAdd(&h->cnt[C_NEAR], near);
-    atomicAdd(&h->cnt[C_NNZ], total);
-    for (int b = 0; b < 6; ++b) atomicAdd(&h->cnt[C_BIN0 + b], bins[b]);
-    atomicMax(&h->cnt[C_LMAX], lmax);
-    atomicMin(&h->cnt[C_LMIN], lmin);
-    for (int b = 0; b < kNumBins; ++b) atomicAdd(&h->bin_count[b], (int32_t)vb[b]);
+  const int wv = threadIdx.x / 64;
+  if (threadIdx.x % 64 == 0)
+    for (int q = 0; q < kPartSlots; ++q) red[wv][q] = v[q];
+  __syncthreads();
+  if (threadIdx.x < kPartSlots) {
+    const int q = threadIdx.x;
+    unsigned long long a = red[0][q];
+    for (int w = 1; w < kWG / 64; ++w) {
+      const unsigned long long x = red[w][q];
+      a = q == P_LMAX ? (x > a ? x : a) : q == P_LMIN ? (x < a ? x : a) : a + x;
+    }
+    part[(int64_t)blockIdx.x * kPartSlots + q] = a;
   }
 }
 
@@ -113,10 +136,39 @@ struct Standardize {
   float sigma[SPMV_NUM_FEATURES];
 };
 
-// Features from the integer counters (the divisions in float64), the
-// standardised selector input, and the bin offsets for the row lists.
-__global__ void k_finalize(int64_t n, WsHeader* h, Standardize st) {
-  if (threadIdx.x != 0) return;
+// Combines the g partial records in workgroup order into the header counters,
+// then computes the features (divisions in float64), the standardised
+// selector input, the bin offsets, and for every statistics workgroup its
+// first slot inside each bin (an exclusive scan over workgroups).
+__global__ __launch_bounds__(64) void k_finalize(int64_t n, int g,
+                                                 const unsigned long long* __restrict__ part,
+                                                 int32_t* __restrict__ bin_base, WsHeader* h,
+                                                 Standardize st) {
+  const int t = threadIdx.x;
+  if (t < kPartSlots) {
+    unsigned long long a = t == P_LMIN ? ~0ull : 0ull;
+    for (int w = 0; w < g; ++w) {
+      const unsigned long long x = part[(int64_t)w * kPartSlots + t];
+      a = t == P_LMAX ? (x > a ? x : a) : t == P_LMIN ? (x < a ? x : a) : a + x;
+    }
+    if (t < P_VB0) {
+      const int c = t == P_SUMSQ ? C_SUMSQ : t == P_LMAX ? C_LMAX : t == P_LMIN ? C_LMIN
+                  : t < P_LONGNNZ ? C_BIN0 + (t - P_BIN0) : t == P_LONGNNZ ? C_LONGNNZ
+                  : t == P_DISTLOG ? C_DISTLOG : t == P_NEAR ? C_NEAR : C_NNZ;
+      h->cnt[c] = a;
+    } else {
+      h->bin_count[t - P_VB0] = (int32_t)a;
+    }
+  }
+  __syncthreads();
+  if (t < kNumBins) {
+    int32_t acc = 0;
+    for (int w = 0; w < g; ++w) {
+      bin_base[(int64_t)w * kNumBins + t] = acc;
+      acc += (int32_t)part[(int64_t)w * kPartSlots + P_VB0 + t];
+    }
+  }
+  if (t != 0) return;
   double f[SPMV_NUM_FEATURES];
   for (int q = 0; q < SPMV_NUM_FEATURES; ++q) f[q] = 0.0;
   if (n > 0) {
@@ -144,37 +196,58 @@ __global__ void k_finalize(int64_t n, WsHeader* h, Standardize st) {
   int32_t acc = 0;
   for (int b = 0; b < kNumBins; ++b) {
     h->bin_offset[b] = acc;
-    h->bin_cursor[b] = 0;
     acc += h->bin_count[b];
   }
 }
 
-// Row lists per bin. Wave-aggregated atomics keep lane order inside a wave.
+// Row lists per bin, each sorted by row: workgroup w walks its rows (the same
+// ranges as k_stats) 256 at a time; a row's slot is the bin offset + the
+// workgroup's base in that bin + the rows of that bin already placed by the
+// workgroup + those of lower lanes in this round (ballot prefix counts).
 __global__ __launch_bounds__(kWG) void k_scatter_bins(int64_t n, int64_t nnz,
                                                       const int32_t* __restrict__ rp,
-                                                      WsHeader* h, int32_t* __restrict__ rows) {
-  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-  const int64_t base = (int64_t)blockIdx.x * blockDim.x;
-  // every lane of a wave runs the same number of iterations (stride is a multiple of 64)
-  for (int64_t i0 = base; i0 < n; i0 += stride) {
-    const int64_t i = i0 + threadIdx.x;
+                                                      const WsHeader* __restrict__ h,
+                                                      const int32_t* __restrict__ bin_base,
+                                                      int32_t* __restrict__ rows) {
+  __shared__ int32_t wave_cnt[kWG / 64][kNumBins];
+  __shared__ int32_t placed[kNumBins];
+  int64_t r0, r1;
+  row_range_of(n, blockIdx.x, gridDim.x, r0, r1);
+  const int wv = threadIdx.x / 64;
+  if (threadIdx.x < kNumBins) placed[threadIdx.x] = 0;
+  int32_t base[kNumBins];
+  for (int b = 0; b < kNumBins; ++b)
+    base[b] = h->bin_offset[b] + bin_base[(int64_t)blockIdx.x * kNumBins + b];
+  const uint64_t lt = __lanemask_lt();
+  // every lane of the workgroup runs the same rounds
+  for (int64_t c = r0; c < r1; c += kWG) {
+    const int64_t i = c + threadIdx.x;
     int mybin = -1;
-    if (i < n) {
+    if (i < r1) {
       int64_t s = rp[i], e = rp[i + 1];
       s = s < 0 ? 0 : s > nnz ? nnz : s;
       e = e < s ? s : e > nnz ? nnz : e;
       mybin = variant_bin(e - s);
     }
-    const uint64_t lt = __lanemask_lt();
+    int32_t lane_pos = 0;
     for (int b = 0; b < kNumBins; ++b) {
       const uint64_t m = __ballot(mybin == b);
-      if (m == 0) continue;
-      const int leader = __ffsll((unsigned long long)m) - 1;
-      int32_t pos = 0;
-      if ((int)__lane_id() == leader) pos = atomicAdd(&h->bin_cursor[b], __popcll(m));
-      pos = __shfl(pos, leader);
-      if (mybin == b) rows[h->bin_offset[b] + pos + __popcll(m & lt)] = (int32_t)i;
+      if (mybin == b) lane_pos = __popcll(m & lt);
+      if (threadIdx.x % 64 == 0) wave_cnt[wv][b] = __popcll(m);
     }
+    __syncthreads();
+    if (mybin >= 0) {
+      int32_t before = placed[mybin];
+      for (int w = 0; w < wv; ++w) before += wave_cnt[w][mybin];
+      rows[base[mybin] + before + lane_pos] = (int32_t)i;
+    }
+    __syncthreads();
+    if (threadIdx.x < kNumBins) {
+      int32_t add = 0;
+      for (int w = 0; w < kWG / 64; ++w) add += wave_cnt[w][threadIdx.x];
+      placed[threadIdx.x] += add;
+    }
+    __syncthreads();
   }
 }
 
@@ -224,16 +297,18 @@ int launch_analysis(Plan& p, const float* mu, const float* sigma, hipStream_t s)
     st.mu[q] = mu ? mu[q] : 0.0f;
     st.sigma[q] = sigma ? sigma[q] : 1.0f;
   }
+  // one statistics workgroup per 256 rows, at most kStatsGrid
+  const int g = (int)std::max<int64_t>(1, std::min<int64_t>(kStatsGrid, (p.n_rows + kWG - 1) / kWG));
   if (p.n_rows > 0) {
-    k_stats<<<grid_cap(p.n_rows, 8192), kWG, 0, s>>>(p.n_rows, p.nnz, p.row_ptr, p.col_idx,
-                                                     p.hdr);
+    k_stats<<<g, kWG, 0, s>>>(p.n_rows, p.nnz, p.row_ptr, p.col_idx, p.stats_part);
     SPMV_HIP(hipGetLastError());
   }
-  k_finalize<<<1, 64, 0, s>>>(p.n_rows, p.hdr, st);
+  k_finalize<<<1, 64, 0, s>>>(p.n_rows, p.n_rows > 0 ? g : 0, p.stats_part, p.bin_base, p.hdr,
+                              st);
   SPMV_HIP(hipGetLastError());
   if (p.n_rows > 0) {
-    k_scatter_bins<<<grid_cap(p.n_rows, 8192), kWG, 0, s>>>(p.n_rows, p.nnz, p.row_ptr, p.hdr,
-                                                            p.bin_rows);
+    k_scatter_bins<<<g, kWG, 0, s>>>(p.n_rows, p.nnz, p.row_ptr, p.hdr, p.bin_base,
+                                     p.bin_rows);
     SPMV_HIP(hipGetLastError());
     k_blocks<<<grid_cap(p.nblocks + 1, 1u << 30), kWG, 0, s>>>(p.n_rows, p.nblocks, p.row_ptr,
                                                                p.blocks);

@@ -29,7 +29,7 @@ int dtype_bytes(int dt) { return dt == SPMV_F64 ? 8 : 4; }
 bool dtype_ok(int dt) { return dt == SPMV_F64 || dt == SPMV_F32; }
 
 struct PlanLayout {
-  size_t header = 0, blocks = 0, bins = 0, at_B = 0, at_C = 0;
+  size_t header = 0, blocks = 0, bins = 0, stats = 0, bin_base = 0, at_B = 0, at_C = 0;
   size_t sell_width = 0, sell_off = 0, sell_partials = 0, sell_ci = 0, sell_val = 0;
   size_t total = 0;
 };
@@ -44,6 +44,10 @@ PlanLayout plan_layout(int64_t n_rows, int64_t n_cols, int64_t nnz, uint32_t fla
   o += align256(sizeof(int2) * (size_t)(nb + 1));
   L.bins = o;
   o += align256(sizeof(int32_t) * (size_t)std::max<int64_t>(n_rows, 1));
+  L.stats = o;
+  o += align256(8 * (size_t)kStatsGrid * kPartSlots);
+  L.bin_base = o;
+  o += align256(4 * (size_t)kStatsGrid * kNumBins);
   const uint32_t mode = flags & 0xFFu;
   if (mode == SPMV_SELECT_MLP || mode == SPMV_SELECT_AUTOTUNE) {
     L.at_B = o;
@@ -75,6 +79,9 @@ int check_shape(int64_t n_rows, int64_t n_cols, int64_t nnz) {
   return SPMV_OK;
 }
 
+// Times every variant the plan has on a B of ones: one warm-up and one timed
+// launch each; a variant within 1.5x of the best time so far gets four more
+// and is scored by the median of its five. The fastest is kept.
 int autotune(Plan& p, hipStream_t s) {
   if (!p.at_B || !p.at_C)
     return fail(SPMV_ERR_WORKSPACE, "autotune needs the workspace size of an autotune/MLP plan");
@@ -84,7 +91,16 @@ int autotune(Plan& p, hipStream_t s) {
   SPMV_HIP(hipEventCreate(&e0));
   SPMV_HIP(hipEventCreate(&e1));
   constexpr int kReps = 5;
-  for (int v = 0; v < SPMV_NUM_VARIANTS; ++v) {
+  float best = INFINITY;
+  auto timed = [&](int v, float* ms) {
+    hipEventRecord(e0, s);
+    int r = launch_spmv(p, v, p.at_B, p.at_C, s);
+    hipEventRecord(e1, s);
+    if (!r && hipEventSynchronize(e1) != hipSuccess) r = fail(SPMV_ERR_HIP, "event sync");
+    if (!r) hipEventElapsedTime(ms, e0, e1);
+    return r;
+  };
+  for (int v = 0; v < SPMV_NUM_VARIANTS && !st; ++v) {
     if (v == SPMV_V6_SELL64 && !p.sell_ok) {
       p.at_us[v] = INFINITY;
       continue;
@@ -92,16 +108,17 @@ int autotune(Plan& p, hipStream_t s) {
     st = launch_spmv(p, v, p.at_B, p.at_C, s);
     if (st) break;
     float ms[kReps];
-    for (int r = 0; r < kReps && !st; ++r) {
-      hipEventRecord(e0, s);
-      st = launch_spmv(p, v, p.at_B, p.at_C, s);
-      hipEventRecord(e1, s);
-      if (hipEventSynchronize(e1) != hipSuccess) st = fail(SPMV_ERR_HIP, "event sync");
-      hipEventElapsedTime(&ms[r], e0, e1);
-    }
+    st = timed(v, &ms[0]);
     if (st) break;
-    std::sort(ms, ms + kReps);
-    p.at_us[v] = 1000.0 * ms[kReps / 2];
+    int reps = 1;
+    if (ms[0] <= 1.5f * best) {
+      for (; reps < kReps && !st; ++reps) st = timed(v, &ms[reps]);
+      if (st) break;
+    }
+    std::sort(ms, ms + reps);
+    const float med = ms[reps / 2];
+    p.at_us[v] = 1000.0 * med;
+    best = std::min(best, med);
   }
   hipEventDestroy(e0);
   hipEventDestroy(e1);
@@ -231,6 +248,8 @@ int plan_build(Plan& p, int64_t n_rows, int64_t n_cols, int64_t nnz, const int32
   p.blocks = reinterpret_cast<int2*>(p.ws + L.blocks);
   p.nblocks = lds_block_count(n_rows, nnz);
   p.bin_rows = reinterpret_cast<int32_t*>(p.ws + L.bins);
+  p.stats_part = reinterpret_cast<unsigned long long*>(p.ws + L.stats);
+  p.bin_base = reinterpret_cast<int32_t*>(p.ws + L.bin_base);
   if (L.at_B) {
     p.at_B = p.ws + L.at_B;
     p.at_C = reinterpret_cast<double*>(p.ws + L.at_C);

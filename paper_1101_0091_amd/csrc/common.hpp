@@ -19,6 +19,8 @@ constexpr int kBlockBudget = 2048;  // rows + in-chunk nonzeros of one LDS row b
 constexpr int kNumXCD = 8;        // MI355X: 8 accelerator complex dies, one L2 each
 constexpr int kNumBins = 5;       // row-length bins of the binned variant
 constexpr int kCounters = 32;     // u64 analysis counters in the workspace header
+constexpr int kStatsGrid = 1024;  // most workgroups of the row-statistics pass
+constexpr int kPartSlots = 18;    // u64 partial counters per statistics workgroup
 
 // Workspace header (first kHeaderBytes of every plan workspace).
 struct alignas(256) WsHeader {
@@ -31,7 +33,6 @@ struct alignas(256) WsHeader {
   float z1[64], z2[64];                // selector forward scratch
   int32_t bin_count[8];
   int32_t bin_offset[8];
-  int32_t bin_cursor[8];
   int64_t sell_total;  // padded width sum of the V6 copy, in units of 64 slots
 };
 constexpr size_t kHeaderBytes = (sizeof(WsHeader) + 255) / 256 * 256;
@@ -56,6 +57,8 @@ struct Plan {
   int2* blocks = nullptr;         // device [nblocks+1]: (first row, row_ptr[first row])
   int64_t nblocks = 0;
   int32_t* bin_rows = nullptr;    // device int32[n_rows]
+  unsigned long long* stats_part = nullptr;  // device [kStatsGrid][kPartSlots]
+  int32_t* bin_base = nullptr;    // device [kStatsGrid][kNumBins]: a workgroup's first slot per bin
   int32_t bin_count[kNumBins] = {0, 0, 0, 0, 0};
   int32_t bin_offset[kNumBins] = {0, 0, 0, 0, 0};
   void* at_B = nullptr;           // autotune scratch (device) or null

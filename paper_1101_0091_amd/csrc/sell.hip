@@ -88,14 +88,24 @@ __global__ __launch_bounds__(kWG) void k_sell_fill(
   const int64_t len = e - s, w = b - a;
   int32_t* dc = sci + a * kChunk;
   VT* dv = sval + a * kChunk;
-  for (int64_t j = 0; j < w; ++j) {
-    const int64_t o = slot_offset(j, lane, w);
-    if (j < len) {
-      dc[o] = ci[s + j];
-      dv[o] = val[s + j];
-    } else {
-      dc[o] = -1;
-      dv[o] = (VT)0;
+  constexpr int kU = 8;  // entries of the row loaded before any is stored
+  for (int64_t j0 = 0; j0 < w; j0 += kU) {
+    int32_t c[kU];
+    VT v[kU];
+#pragma unroll
+    for (int u = 0; u < kU; ++u) {
+      const int64_t j = j0 + u;
+      c[u] = j < len ? ci[s + j] : -1;
+      v[u] = j < len ? val[s + j] : (VT)0;
+    }
+#pragma unroll
+    for (int u = 0; u < kU; ++u) {
+      const int64_t j = j0 + u;
+      if (j < w) {
+        const int64_t o = slot_offset(j, lane, w);
+        dc[o] = c[u];
+        dv[o] = v[u];
+      }
     }
   }
 }

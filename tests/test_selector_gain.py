@@ -63,5 +63,7 @@ def test_selection_cost_vs_autotune():
     """Choosing by the network costs one tiny forward pass; the autotuner
     runs every variant several times (its cost in multiples of one product)."""
     F, T, tr, te, P, _ = _heldout_predictions()
-    autotune_cost = (T[te].sum(axis=1) * 6) / T[te].min(axis=1)  # 1 warm-up + 5 timed per variant
-    assert geomean(autotune_cost) > 30
+    from paper_1101_0091_amd.selector import autotune_cost as cost_of
+    autotune_cost = np.array([cost_of(t) for t in T[te]])
+    assert np.all(autotune_cost >= 12.0)  # at least warm-up + timed launch of each of 6
+    assert geomean(autotune_cost) > 20
