@@ -427,7 +427,7 @@ BatchLayout batch_layout(int32_t count, int64_t max_tiles) {
   L.err = o;
   o += 256;  // err[2] at 0, tile counters[2] at 128
   L.tiles = o;
-  o += align256(sizeof(int32_t) * 6 * (size_t)std::max<int64_t>(max_tiles, 1));
+  o += align256(sizeof(int32_t) * kTileInts * (size_t)std::max<int64_t>(max_tiles, 1));
   L.toff = o;
   o += align256(sizeof(int64_t) * (size_t)(count + 1));
   L.nr = o;

@@ -64,13 +64,63 @@ __global__ __launch_bounds__(kWG) void k_batch_tiles(int32_t count,
   for (int64_t b = threadIdx.x; b < nb; b += kWG) {
     const int32_t r0 = first_row_at(rp, n, b * kBlockBudget);
     const int32_t r1 = (b + 1 == nb) ? (int32_t)n : first_row_at(rp, n, (b + 1) * kBlockBudget);
-    int32_t* t = tiles + 6 * (toff[m] + b);
+    int32_t* t = tiles + kTileInts * (toff[m] + b);
     t[0] = m;
     t[1] = r0;
     t[2] = r1;
     t[3] = rp[r0];
     t[4] = rp[r1];
     t[5] = 0;
+    t[6] = -1;
+    t[7] = 0;
+  }
+}
+
+// Column bounds of every tile's chunk [S, min(E, S + budget)) (one workgroup
+// per tile), so the apply can stage B[cmin..cmax] in LDS when it fits. S and
+// E are clamped to [0, nnz] so an invalid pattern (reported by validation in
+// the same pass) reads nothing out of bounds.
+__global__ __launch_bounds__(kWG) void k_batch_spans(int64_t ntiles,
+                                                     const int64_t* __restrict__ nz,
+                                                     const int32_t* const* __restrict__ cis,
+                                                     int32_t* __restrict__ tiles) {
+  __shared__ int32_t lo[kWG / 64], hi[kWG / 64];
+  const int64_t t = blockIdx.x;
+  if (t >= ntiles) return;
+  int32_t* tl = tiles + kTileInts * t;
+  const int32_t m = tl[0];
+  const int64_t nnz = nz[m];
+  int64_t S = tl[3], E = tl[4];
+  S = S < 0 ? 0 : S > nnz ? nnz : S;
+  E = E < S ? S : E > nnz ? nnz : E;
+  if (E - S > kBlockBudget) E = S + kBlockBudget;
+  const int32_t* ci = cis[m];
+  int32_t a = INT32_MAX, z = INT32_MIN;
+  for (int64_t j = S + threadIdx.x; j < E; j += kWG) {
+    const int32_t c = ci[j];
+    a = c < a ? c : a;
+    z = c > z ? c : z;
+  }
+  for (int o = 32; o >= 1; o >>= 1) {
+    const int32_t x = __shfl_xor(a, o), y = __shfl_xor(z, o);
+    a = x < a ? x : a;
+    z = y > z ? y : z;
+  }
+  if (threadIdx.x % 64 == 0) {
+    lo[threadIdx.x / 64] = a;
+    hi[threadIdx.x / 64] = z;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int w = 1; w < kWG / 64; ++w) {
+      a = lo[w] < a ? lo[w] : a;
+      z = hi[w] > z ? hi[w] : z;
+    }
+    a = lo[0] < a ? lo[0] : a;
+    z = hi[0] > z ? hi[0] : z;
+    // an empty chunk keeps cmin > cmax (nothing staged)
+    tl[5] = a <= z ? a : 0;
+    tl[6] = a <= z ? z : -1;
   }
 }
 
@@ -82,12 +132,14 @@ __device__ __forceinline__ void batch_tile(dev::BlockLds& L, const int32_t* __re
                                            const void* const* __restrict__ Bs,
                                            double* const* __restrict__ Cs,
                                            const BT* __restrict__ B1, double* __restrict__ C1) {
-  const int32_t* tl = tiles + 6 * t;
-  const int32_t m = tl[0], r0 = tl[1], r1 = tl[2], S = tl[3], E = tl[4];
+  const int32_t* tl = tiles + kTileInts * t;
+  const int32_t m = tl[0], r0 = tl[1], r1 = tl[2], S = tl[3], E = tl[4], cmin = tl[5],
+                cmax = tl[6];
   if (r0 >= r1) return;
   const BT* B = Bs ? static_cast<const BT*>(Bs[m]) : B1;
   double* C = Cs ? Cs[m] : C1;
-  dev::lds_block<VT, BT, false>(L, rps[m], cis[m], static_cast<const VT*>(vals[m]), B, C, r0, r1, S, E);
+  dev::lds_block<VT, BT, false>(L, rps[m], cis[m], static_cast<const VT*>(vals[m]), B, C, r0, r1,
+                                S, E, cmin, cmax);
 }
 
 // Persistent, static: workgroup w owns one contiguous range of tiles.
@@ -187,6 +239,10 @@ int launch_batch_build(Batch& b, const int64_t* toff, const int64_t* nr, const i
   SPMV_HIP(hipGetLastError());
   k_batch_tiles<<<b.count, kWG, 0, s>>>(b.count, nr, toff, b.row_ptrs, b.tiles);
   SPMV_HIP(hipGetLastError());
+  if (b.ntiles > 0) {
+    k_batch_spans<<<(unsigned)b.ntiles, kWG, 0, s>>>(b.ntiles, nz, b.col_idxs, b.tiles);
+    SPMV_HIP(hipGetLastError());
+  }
   return SPMV_OK;
 }
 

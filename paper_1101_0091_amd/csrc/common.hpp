@@ -18,6 +18,7 @@ constexpr int kWG = 256;          // threads per workgroup for the streaming ker
 constexpr int kBlockBudget = 2048;  // rows + in-chunk nonzeros of one LDS row block
 constexpr int kNumXCD = 8;        // MI355X: 8 accelerator complex dies, one L2 each
 constexpr int kNumBins = 5;       // row-length bins of the binned variant
+constexpr int kTileInts = 8;      // batch tile record: matrix, r0, r1, S, E, cmin, cmax, pad
 constexpr int kCounters = 32;     // u64 analysis counters in the workspace header
 constexpr int kStatsGrid = 1024;  // most workgroups of the row-statistics pass
 constexpr int kPartSlots = 18;    // u64 partial counters per statistics workgroup
@@ -89,7 +90,7 @@ struct Batch {
   const int32_t* const* row_ptrs = nullptr;  // device arrays of device pointers
   const int32_t* const* col_idxs = nullptr;
   const void* const* vals = nullptr;
-  int32_t* tiles = nullptr;   // device int32[6 * ntiles]: matrix, r0, r1, S, E, pad
+  int32_t* tiles = nullptr;   // device int32[kTileInts * ntiles]
   int64_t ntiles = 0;
   int32_t* err = nullptr;     // device
   unsigned int* counters = nullptr;  // device [2]: next tile, finished workgroups

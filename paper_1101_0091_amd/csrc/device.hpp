@@ -194,16 +194,23 @@ __device__ __forceinline__ void block_rows(const BlockLds& L, const int32_t* __r
 
 // S = row_ptr[r0] and E = row_ptr[r1] come from the block table, so the
 // workgroup's first dependent round trip already yields the stream bounds.
+// [cmin, cmax] bounds the columns of the chunk [S, min(E, S + budget)); when
+// the span fits the LDS array (and cmin <= cmax), B[cmin..cmax] is first
+// copied into it with coalesced loads and the gathers read LDS; the products
+// then overwrite it. Callers without the bounds pass cmin > cmax.
 template <typename VT, typename BT, bool ACC = false>
 __device__ __forceinline__ void lds_block(BlockLds& L, const int32_t* __restrict__ rp,
                                           const int32_t* __restrict__ ci,
                                           const VT* __restrict__ val, const BT* __restrict__ B,
                                           double* __restrict__ C, int32_t r0, int32_t r1,
-                                          int32_t S, int32_t E) {
+                                          int32_t S, int32_t E, int32_t cmin = 0,
+                                          int32_t cmax = -1) {
   const int tid = threadIdx.x;
   const int32_t cend = (E - S > kBlockBudget) ? S + kBlockBudget : E;
   const int32_t nin = cend - S;
   const bool tail = E > cend;
+  const int32_t span = cmax - cmin + 1;
+  const bool staged = cmin <= cmax && span <= kBlockBudget;
 
   // phase 1: products of the chunk into LDS; all loads issued before use
   constexpr int kPer = kBlockBudget / kWG;
@@ -217,16 +224,27 @@ __device__ __forceinline__ void lds_block(BlockLds& L, const int32_t* __restrict
       c[u] = ld_stream(ci + S + k);
     }
   }
-  BT b[kPer];
+  double b[kPer];
+  if (staged) {
+    for (int32_t k = tid; k < span; k += kWG) L.prod[k] = widen(B[cmin + k]);
+    __syncthreads();
 #pragma unroll
-  for (int u = 0; u < kPer; ++u) {
-    const int k = tid + u * kWG;
-    if (k < nin) b[u] = B[c[u]];
+    for (int u = 0; u < kPer; ++u) {
+      const int k = tid + u * kWG;
+      if (k < nin) b[u] = L.prod[c[u] - cmin];
+    }
+    __syncthreads();  // every staged entry read before the products overwrite them
+  } else {
+#pragma unroll
+    for (int u = 0; u < kPer; ++u) {
+      const int k = tid + u * kWG;
+      if (k < nin) b[u] = widen(B[c[u]]);
+    }
   }
 #pragma unroll
   for (int u = 0; u < kPer; ++u) {
     const int k = tid + u * kWG;
-    if (k < nin) L.prod[k] = widen(v[u]) * widen(b[u]);
+    if (k < nin) L.prod[k] = widen(v[u]) * b[u];
   }
   __syncthreads();
 
