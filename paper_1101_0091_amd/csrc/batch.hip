@@ -124,6 +124,9 @@ __global__ __launch_bounds__(kWG) void k_batch_spans(int64_t ntiles,
   }
 }
 
+// B is staged in the LDS product array itself (2048 doubles): a 4096-entry
+// staging area measured faster on uniform-random tiles but, at twice the LDS,
+// cost more on banded ones through lost occupancy.
 template <typename VT, typename BT>
 __device__ __forceinline__ void batch_tile(dev::BlockLds& L, const int32_t* __restrict__ tiles,
                                            int64_t t, const int32_t* const* __restrict__ rps,
@@ -139,7 +142,7 @@ __device__ __forceinline__ void batch_tile(dev::BlockLds& L, const int32_t* __re
   const BT* B = Bs ? static_cast<const BT*>(Bs[m]) : B1;
   double* C = Cs ? Cs[m] : C1;
   dev::lds_block<VT, BT, false>(L, rps[m], cis[m], static_cast<const VT*>(vals[m]), B, C, r0, r1,
-                                S, E, cmin, cmax);
+                                S, E, cmin, cmax, L.prod, kBlockBudget);
 }
 
 // Persistent, static: workgroup w owns one contiguous range of tiles.

@@ -195,22 +195,24 @@ __device__ __forceinline__ void block_rows(const BlockLds& L, const int32_t* __r
 // S = row_ptr[r0] and E = row_ptr[r1] come from the block table, so the
 // workgroup's first dependent round trip already yields the stream bounds.
 // [cmin, cmax] bounds the columns of the chunk [S, min(E, S + budget)); when
-// the span fits the LDS array (and cmin <= cmax), B[cmin..cmax] is first
-// copied into it with coalesced loads and the gathers read LDS; the products
-// then overwrite it. Callers without the bounds pass cmin > cmax.
+// the span fits the staging array `stage` (stage_cap doubles of LDS that may
+// overlap L, and cmin <= cmax), B[cmin..cmax] is first copied into it with
+// coalesced loads and the gathers read LDS; the products then overwrite it.
+// Callers without the bounds pass cmin > cmax.
 template <typename VT, typename BT, bool ACC = false>
 __device__ __forceinline__ void lds_block(BlockLds& L, const int32_t* __restrict__ rp,
                                           const int32_t* __restrict__ ci,
                                           const VT* __restrict__ val, const BT* __restrict__ B,
                                           double* __restrict__ C, int32_t r0, int32_t r1,
                                           int32_t S, int32_t E, int32_t cmin = 0,
-                                          int32_t cmax = -1) {
+                                          int32_t cmax = -1, double* stage = nullptr,
+                                          int32_t stage_cap = 0) {
   const int tid = threadIdx.x;
   const int32_t cend = (E - S > kBlockBudget) ? S + kBlockBudget : E;
   const int32_t nin = cend - S;
   const bool tail = E > cend;
   const int32_t span = cmax - cmin + 1;
-  const bool staged = cmin <= cmax && span <= kBlockBudget;
+  const bool staged = stage && cmin <= cmax && span <= stage_cap;
 
   // phase 1: products of the chunk into LDS; all loads issued before use
   constexpr int kPer = kBlockBudget / kWG;
@@ -226,12 +228,12 @@ __device__ __forceinline__ void lds_block(BlockLds& L, const int32_t* __restrict
   }
   double b[kPer];
   if (staged) {
-    for (int32_t k = tid; k < span; k += kWG) L.prod[k] = widen(B[cmin + k]);
+    for (int32_t k = tid; k < span; k += kWG) stage[k] = widen(B[cmin + k]);
     __syncthreads();
 #pragma unroll
     for (int u = 0; u < kPer; ++u) {
       const int k = tid + u * kWG;
-      if (k < nin) b[u] = L.prod[c[u] - cmin];
+      if (k < nin) b[u] = stage[c[u] - cmin];
     }
     __syncthreads();  // every staged entry read before the products overwrite them
   } else {
