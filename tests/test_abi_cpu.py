@@ -94,6 +94,12 @@ def test_null_handle_calls():
     assert L.spmv_mlp_adam(None, None, None, None, 1, 0.1, 0.9, 0.999, 1e-8, None) == \
         pkg.SPMV_ERR_INVALID_ARG
     assert L.spmv_stream_triad(None, None, None, 1.0, -1, None) == pkg.SPMV_ERR_INVALID_ARG
+    slots = ctypes.c_int64(-7)
+    assert L.spmv_get_sell_slots(None, ctypes.byref(slots)) == pkg.SPMV_ERR_INVALID_ARG
+    assert slots.value == -7  # untouched on error
+    assert L.spmv_set_variant(None, pkg.SPMV_V6_SELL64) == pkg.SPMV_ERR_INVALID_ARG
+    times = (ctypes.c_double * pkg.SPMV_NUM_VARIANTS)()
+    assert L.spmv_get_autotune_times(None, times) == pkg.SPMV_ERR_INVALID_ARG
 
 
 def test_batch_create_rejects_on_host():
