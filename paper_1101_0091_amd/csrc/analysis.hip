@@ -275,6 +275,48 @@ __global__ void k_blocks(int64_t n, int64_t nblocks, const int32_t* __restrict__
   blocks[b] = make_int2((int32_t)lo, rp[lo]);
 }
 
+// Column bounds of every row block's chunk [S, min(E, S + budget)) (one
+// workgroup per block), so the product can stage B[cmin..cmax] in LDS when it
+// fits. S and E are clamped to [0, nnz] so an invalid pattern (reported by
+// validation in the same pass) reads nothing out of bounds.
+__global__ __launch_bounds__(kWG) void k_block_spans(int64_t nblocks, int64_t nnz,
+                                                     const int2* __restrict__ blocks,
+                                                     const int32_t* __restrict__ ci,
+                                                     int2* __restrict__ spans, WsHeader* h) {
+  __shared__ int32_t lo[kWG / 64], hi[kWG / 64];
+  const int64_t b = blockIdx.x;
+  if (b >= nblocks) return;
+  int64_t S = blocks[b].y, E = blocks[b + 1].y;
+  S = S < 0 ? 0 : S > nnz ? nnz : S;
+  E = E < S ? S : E > nnz ? nnz : E;
+  if (E - S > kBlockBudget) E = S + kBlockBudget;
+  int32_t a = INT32_MAX, z = INT32_MIN;
+  for (int64_t j = S + threadIdx.x; j < E; j += kWG) {
+    const int32_t c = ci[j];
+    a = c < a ? c : a;
+    z = c > z ? c : z;
+  }
+  for (int o = 32; o >= 1; o >>= 1) {
+    const int32_t x = __shfl_xor(a, o), y = __shfl_xor(z, o);
+    a = x < a ? x : a;
+    z = y > z ? y : z;
+  }
+  if (threadIdx.x % 64 == 0) {
+    lo[threadIdx.x / 64] = a;
+    hi[threadIdx.x / 64] = z;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int w = 1; w < kWG / 64; ++w) {
+      a = lo[w] < a ? lo[w] : a;
+      z = hi[w] > z ? hi[w] : z;
+    }
+    // an empty chunk gets cmin > cmax (nothing staged)
+    spans[b] = a <= z ? make_int2(a, z) : make_int2(0, -1);
+    if (a <= z && (int64_t)z - a < kBlockBudget) atomicAdd(&h->staged_blocks, 1);
+  }
+}
+
 inline unsigned grid_cap(int64_t threads, unsigned cap) {
   int64_t g = (threads + kWG - 1) / kWG;
   if (g < 1) g = 1;
@@ -313,6 +355,11 @@ int launch_analysis(Plan& p, const float* mu, const float* sigma, hipStream_t s)
     k_blocks<<<grid_cap(p.nblocks + 1, 1u << 30), kWG, 0, s>>>(p.n_rows, p.nblocks, p.row_ptr,
                                                                p.blocks);
     SPMV_HIP(hipGetLastError());
+    if (p.nblocks > 0) {
+      k_block_spans<<<(unsigned)p.nblocks, kWG, 0, s>>>(p.nblocks, p.nnz, p.blocks, p.col_idx,
+                                                        p.spans, p.hdr);
+      SPMV_HIP(hipGetLastError());
+    }
   }
   return SPMV_OK;
 }

@@ -29,7 +29,7 @@ int dtype_bytes(int dt) { return dt == SPMV_F64 ? 8 : 4; }
 bool dtype_ok(int dt) { return dt == SPMV_F64 || dt == SPMV_F32; }
 
 struct PlanLayout {
-  size_t header = 0, blocks = 0, bins = 0, stats = 0, bin_base = 0, at_B = 0, at_C = 0;
+  size_t header = 0, blocks = 0, spans = 0, bins = 0, stats = 0, bin_base = 0, at_B = 0, at_C = 0;
   size_t sell_width = 0, sell_off = 0, sell_partials = 0, sell_ci = 0, sell_val = 0;
   size_t total = 0;
 };
@@ -42,6 +42,8 @@ PlanLayout plan_layout(int64_t n_rows, int64_t n_cols, int64_t nnz, uint32_t fla
   o += kHeaderBytes;
   L.blocks = o;
   o += align256(sizeof(int2) * (size_t)(nb + 1));
+  L.spans = o;
+  o += align256(sizeof(int2) * (size_t)std::max<int64_t>(nb, 1));
   L.bins = o;
   o += align256(sizeof(int32_t) * (size_t)std::max<int64_t>(n_rows, 1));
   L.stats = o;
@@ -246,6 +248,7 @@ int plan_build(Plan& p, int64_t n_rows, int64_t n_cols, int64_t nnz, const int32
   p.ws_bytes = ws_bytes;
   p.hdr = reinterpret_cast<WsHeader*>(p.ws + L.header);
   p.blocks = reinterpret_cast<int2*>(p.ws + L.blocks);
+  p.spans = reinterpret_cast<int2*>(p.ws + L.spans);
   p.nblocks = lds_block_count(n_rows, nnz);
   p.bin_rows = reinterpret_cast<int32_t*>(p.ws + L.bins);
   p.stats_part = reinterpret_cast<unsigned long long*>(p.ws + L.stats);
@@ -291,6 +294,7 @@ int plan_build(Plan& p, int64_t n_rows, int64_t n_cols, int64_t nnz, const int32
   }
   if (st) return st;
   std::memcpy(p.features, hh.features, sizeof(p.features));
+  p.staged_blocks = hh.staged_blocks;
   for (int b = 0; b < kNumBins; ++b) {
     p.bin_count[b] = hh.bin_count[b];
     p.bin_offset[b] = hh.bin_offset[b];

@@ -141,8 +141,8 @@ __device__ __forceinline__ void batch_tile(dev::BlockLds& L, const int32_t* __re
   if (r0 >= r1) return;
   const BT* B = Bs ? static_cast<const BT*>(Bs[m]) : B1;
   double* C = Cs ? Cs[m] : C1;
-  dev::lds_block<VT, BT, false>(L, rps[m], cis[m], static_cast<const VT*>(vals[m]), B, C, r0, r1,
-                                S, E, cmin, cmax, L.prod, kBlockBudget);
+  dev::lds_block<VT, BT, false, true>(L, rps[m], cis[m], static_cast<const VT*>(vals[m]), B, C,
+                                      r0, r1, S, E, cmin, cmax, L.prod, kBlockBudget);
 }
 
 // Persistent, static: workgroup w owns one contiguous range of tiles.

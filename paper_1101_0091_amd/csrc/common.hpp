@@ -35,6 +35,7 @@ struct alignas(256) WsHeader {
   int32_t bin_count[8];
   int32_t bin_offset[8];
   int64_t sell_total;  // padded width sum of the V6 copy, in units of 64 slots
+  int32_t staged_blocks;  // row blocks whose chunk's columns fit the LDS staging array
 };
 constexpr size_t kHeaderBytes = (sizeof(WsHeader) + 255) / 256 * 256;
 
@@ -56,6 +57,8 @@ struct Plan {
   size_t ws_bytes = 0;
   WsHeader* hdr = nullptr;        // device
   int2* blocks = nullptr;         // device [nblocks+1]: (first row, row_ptr[first row])
+  int2* spans = nullptr;          // device [nblocks]: (smallest, largest) column of the block's chunk
+  int64_t staged_blocks = 0;      // blocks with a span that fits the LDS staging array
   int64_t nblocks = 0;
   int32_t* bin_rows = nullptr;    // device int32[n_rows]
   unsigned long long* stats_part = nullptr;  // device [kStatsGrid][kPartSlots]

@@ -198,8 +198,8 @@ __device__ __forceinline__ void block_rows(const BlockLds& L, const int32_t* __r
 // the span fits the staging array `stage` (stage_cap doubles of LDS that may
 // overlap L, and cmin <= cmax), B[cmin..cmax] is first copied into it with
 // coalesced loads and the gathers read LDS; the products then overwrite it.
-// Callers without the bounds pass cmin > cmax.
-template <typename VT, typename BT, bool ACC = false>
+// STAGE = false compiles the path out (callers without column bounds).
+template <typename VT, typename BT, bool ACC = false, bool STAGE = false>
 __device__ __forceinline__ void lds_block(BlockLds& L, const int32_t* __restrict__ rp,
                                           const int32_t* __restrict__ ci,
                                           const VT* __restrict__ val, const BT* __restrict__ B,
@@ -212,7 +212,7 @@ __device__ __forceinline__ void lds_block(BlockLds& L, const int32_t* __restrict
   const int32_t nin = cend - S;
   const bool tail = E > cend;
   const int32_t span = cmax - cmin + 1;
-  const bool staged = stage && cmin <= cmax && span <= stage_cap;
+  const bool staged = STAGE && stage && cmin <= cmax && span <= stage_cap;
 
   // phase 1: products of the chunk into LDS; all loads issued before use
   constexpr int kPer = kBlockBudget / kWG;
@@ -227,16 +227,19 @@ __device__ __forceinline__ void lds_block(BlockLds& L, const int32_t* __restrict
     }
   }
   double b[kPer];
-  if (staged) {
-    for (int32_t k = tid; k < span; k += kWG) stage[k] = widen(B[cmin + k]);
-    __syncthreads();
+  if constexpr (STAGE) {
+    if (staged) {
+      for (int32_t k = tid; k < span; k += kWG) stage[k] = widen(B[cmin + k]);
+      __syncthreads();
 #pragma unroll
-    for (int u = 0; u < kPer; ++u) {
-      const int k = tid + u * kWG;
-      if (k < nin) b[u] = stage[c[u] - cmin];
+      for (int u = 0; u < kPer; ++u) {
+        const int k = tid + u * kWG;
+        if (k < nin) b[u] = stage[c[u] - cmin];
+      }
+      __syncthreads();  // every staged entry read before the products overwrite them
     }
-    __syncthreads();  // every staged entry read before the products overwrite them
-  } else {
+  }
+  if (!staged) {
 #pragma unroll
     for (int u = 0; u < kPer; ++u) {
       const int k = tid + u * kWG;

@@ -108,6 +108,39 @@ __global__ __launch_bounds__(kWG) void k_lds_block(int64_t nblocks, const int2* 
   dev::lds_block<VT, BT, ACC>(L, rp, ci, val, B, C, m0.x, m1.x, m0.y, m1.y);
 }
 
+// The same with B staging: a block whose chunk's columns span at most the
+// LDS product array gathers B from a staged copy of B[cmin..cmax] (banded and
+// stencil-like blocks). The staging path costs registers and changes the
+// compiler's load schedule, so it is a kernel of its own, used by a plan only
+// when at least a quarter of its blocks can stage.
+template <typename VT, typename BT, bool ACC>
+__global__ __launch_bounds__(kWG) void k_lds_block_staged(int64_t nblocks,
+                                                          const int2* __restrict__ blocks,
+                                                          const int2* __restrict__ spans,
+                                                          const int32_t* __restrict__ rp,
+                                                          const int32_t* __restrict__ ci,
+                                                          const VT* __restrict__ val,
+                                                          const BT* __restrict__ B,
+                                                          double* __restrict__ C) {
+  __shared__ dev::BlockLds L;
+  const int64_t b = dev::xcd_remap(blockIdx.x, nblocks);
+  const int2 m0 = blocks[b], m1 = blocks[b + 1], sp = spans[b];
+  if (m0.x >= m1.x) return;
+  dev::lds_block<VT, BT, ACC, true>(L, rp, ci, val, B, C, m0.x, m1.x, m0.y, m1.y, sp.x, sp.y,
+                                    L.prod, kBlockBudget);
+}
+
+template <typename VT, typename BT, bool ACC>
+void launch_lds_block(const Plan& p, const VT* val, const BT* B, double* C, hipStream_t s) {
+  if (p.nblocks <= 0) return;
+  if (p.staged_blocks * 4 >= p.nblocks)
+    k_lds_block_staged<VT, BT, ACC><<<(unsigned)p.nblocks, kWG, 0, s>>>(
+        p.nblocks, p.blocks, p.spans, p.row_ptr, p.col_idx, val, B, C);
+  else
+    k_lds_block<VT, BT, ACC><<<(unsigned)p.nblocks, kWG, 0, s>>>(p.nblocks, p.blocks, p.row_ptr,
+                                                                 p.col_idx, val, B, C);
+}
+
 // ---------------------------------------------------------------- SpMM
 // LPR lanes per row; lane l owns columns [c0, c0+CPL) with c0 = l*CPL + t*LPR*CPL.
 // Each gathered B row segment is loaded as 16-byte vectors (CPL = 4 in
@@ -256,9 +289,7 @@ int spmv_typed(const Plan& p, int variant, const BT* B, double* C, hipStream_t s
           n, nullptr, p.row_ptr, p.col_idx, val, B, C);
       break;
     case SPMV_V4_LDS_BLOCK:
-      if (p.nblocks > 0)
-        k_lds_block<VT, BT, false><<<(unsigned)p.nblocks, kWG, 0, s>>>(p.nblocks, p.blocks, p.row_ptr,
-                                                                p.col_idx, val, B, C);
+      launch_lds_block<VT, BT, false>(p, val, B, C, s);
       break;
     case SPMV_V5_BINNED: {
       const int32_t* L = p.bin_rows;
@@ -327,9 +358,7 @@ int spmm_store(const Plan& p, int k, const BT* B, int64_t ldb, double* C, int64_
 
 template <typename VT, typename BT>
 int spmv_accumulate_typed(const Plan& p, const BT* B, double* C, hipStream_t s) {
-  if (p.nblocks > 0)
-    k_lds_block<VT, BT, true><<<(unsigned)p.nblocks, kWG, 0, s>>>(
-        p.nblocks, p.blocks, p.row_ptr, p.col_idx, static_cast<const VT*>(p.val), B, C);
+  launch_lds_block<VT, BT, true>(p, static_cast<const VT*>(p.val), B, C, s);
   SPMV_HIP(hipGetLastError());
   return SPMV_OK;
 }
