@@ -431,3 +431,38 @@ def test_sell_layout_rounds_and_ragged_tail(n, half, jitter, dt):
     M.apply(_gpu(Bh), C)
     ok, worst = oracle.bound_ok(C.cpu().numpy(), Cref, A.row_ptr, S)
     assert ok, worst
+
+
+def test_batch_full_size_4096():
+    """The batch the benchmark times (4096 matrices, seed 6, N log-uniform in
+    [100, 5000]) in its launch mode (one tile-grid launch): every row of every
+    matrix against the oracle, and the graph of the one launch bitwise equal."""
+    mats = _batch_mats(4096, 6)
+    Bt = pkg.Batch(mats, device=DEV)
+    Bh = crsgen.uniform_vec(int(Bt.n_cols.sum()), 6)
+    B_all = _gpu(Bh)
+    C_all = torch.full((int(Bt.n_rows.sum()),), float("nan"), dtype=torch.float64, device=DEV)
+    Bd, Cd, bh, ch = Bt.pointers(B_all, C_all)
+    Bt.set_mode(pkg.SPMV_BATCH_TILE_GRID)
+    Bt.apply(Bd, Cd)
+    got = C_all.cpu().numpy()
+    for m, A in enumerate(mats):
+        b = Bh[Bt.col_off[m]:Bt.col_off[m + 1]]
+        Cref, S = oracle.spmv(A.n_rows, A.row_ptr, A.col_idx, A.val, b)
+        ok, worst = oracle.bound_ok(got[Bt.row_off[m]:Bt.row_off[m + 1]], Cref, A.row_ptr, S)
+        assert ok, (m, worst)
+    first = C_all.clone()
+    s = torch.cuda.Stream()
+    torch.cuda.synchronize()
+    pkg.spmv_graph_begin(s)
+    Bt.apply(Bd, Cd, stream=s)
+    g = pkg.spmv_graph_end(s)
+    try:
+        for _ in range(3):
+            C_all.fill_(float("nan"))
+            torch.cuda.synchronize()
+            pkg.spmv_graph_launch(g, s)
+            s.synchronize()
+            assert torch.equal(C_all, first)
+    finally:
+        pkg.spmv_graph_destroy(g)
