@@ -202,8 +202,9 @@ def time_create(A, pkg, dev):
     for name, flags in (("fixed", pkg.SPMV_FLAG_VARIANT(4)), ("selector", pkg.SPMV_SELECT_DEFAULT),
                         ("autotune", pkg.SPMV_SELECT_AUTOTUNE),
                         ("fixed_v6_with_copy", pkg.SPMV_FLAG_VARIANT(6) | pkg.SPMV_FLAG_SELL),
+                        ("selector_with_v6_copy", pkg.SPMV_SELECT_DEFAULT | pkg.SPMV_FLAG_SELL),
                         ("autotune_with_v6_copy", pkg.SPMV_SELECT_AUTOTUNE | pkg.SPMV_FLAG_SELL)):
-        if name == "selector":
+        if name.startswith("selector"):
             pkg.load_selector()
         nb = pkg.spmv_workspace_size(A.n_rows, A.n_cols, A.nnz, flags)
         ws = torch.empty(nb, dtype=torch.uint8, device=dev)

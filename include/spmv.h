@@ -75,7 +75,8 @@ typedef enum {
   SPMV_NUM_VARIANTS = 7
 } spmv_variant;
 
-/* The MLP selector ranks V0..V5; V6 is chosen by autotune or by name. */
+/* The MLP selector ranks V0..V5; V6 is chosen by autotune, by a timed duel
+ * with the selector's pick (SPMV_FLAG_SELL), or by name. */
 #define SPMV_NUM_SELECTOR_OUTPUTS 6
 
 /* spmv_create flags. The low byte selects how the variant is chosen. */
@@ -90,7 +91,11 @@ typedef enum {
  * column index + value; the reserve is 1.5 nnz + 4096 slots (rounded up to
  * 64) at 12 bytes each whatever val_dtype is. A pattern whose padded size
  * exceeds it still gets a plan, without V6 (spmv_get_sell_slots reports
- * SPMV_ERR_STATE); asking for V6 by name then fails with UNSUPPORTED. */
+ * SPMV_ERR_STATE); asking for V6 by name then fails with UNSUPPORTED. The
+ * selector ranks V0..V5 only: with SPMV_SELECT_DEFAULT or SPMV_SELECT_MLP and
+ * a built copy, its pick is timed against V6 at create (a warm-up and three
+ * launches each, on a B of ones) and the faster is kept; autotune times V6
+ * with the others. */
 #define SPMV_FLAG_SELL 0x20000u
 
 #define SPMV_NUM_FEATURES 16

@@ -39,9 +39,13 @@ def test_workspace_size_is_stable_and_checked():
     assert pkg.spmv_workspace_size(6_000_000, 6_000_000, 87_000_000, pkg.SPMV_SELECT_AUTOTUNE) > a
     assert pkg.spmv_workspace_size(0, 0, 0) > 0
     # the V6 reserve: 1.5 nnz + 4096 slots (rounded up to 64) of 4 + 8 bytes
-    s = pkg.spmv_workspace_size(6_000_000, 6_000_000, 87_000_000, pkg.SPMV_FLAG_SELL)
+    at = pkg.spmv_workspace_size(6_000_000, 6_000_000, 87_000_000, pkg.SPMV_SELECT_AUTOTUNE)
+    s = pkg.spmv_workspace_size(6_000_000, 6_000_000, 87_000_000,
+                                pkg.SPMV_SELECT_AUTOTUNE | pkg.SPMV_FLAG_SELL)
     cap = (87_000_000 + 43_500_000 + 4096 + 63) // 64 * 64
-    assert 12 * cap <= s - a <= 12 * cap + 4 * 6_000_000 // 64 * 3 + 4096
+    assert 12 * cap <= s - at <= 12 * cap + 4 * 6_000_000 // 64 * 3 + 4096
+    # a default-mode plan with the copy also reserves the timing scratch of its V6 duel
+    assert pkg.spmv_workspace_size(6_000_000, 6_000_000, 87_000_000, pkg.SPMV_FLAG_SELL) == s
     with pytest.raises(pkg.SpmvError) as e:
         pkg.spmv_workspace_size(-1, 5, 5)
     assert e.value.status == pkg.SPMV_ERR_INVALID_ARG

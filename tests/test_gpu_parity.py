@@ -466,3 +466,19 @@ def test_batch_full_size_4096():
             assert torch.equal(C_all, first)
     finally:
         pkg.spmv_graph_destroy(g)
+
+
+@pytest.mark.parametrize("mode", ["default", "mlp"])
+def test_selector_plan_duels_with_v6(mode):
+    """With the V6 copy, a selector plan keeps either the network's pick or V6
+    (whichever its timed duel found faster) and multiplies correctly; without
+    the copy it keeps the network's pick."""
+    A, B = case("hamiltonian_200k")
+    flags = pkg.SPMV_SELECT_DEFAULT if mode == "default" else pkg.SPMV_SELECT_MLP
+    M0 = pkg.CRSMatrix.from_crs(A, flags=flags, device=DEV)
+    M = pkg.CRSMatrix.from_crs(A, flags=flags | SELL, device=DEV)
+    assert M.sell_slots is not None
+    if M0.variant != 6 and pkg.spmv_selector_loaded():
+        assert M.variant in (M0.variant, pkg.SPMV_V6_SELL64)
+    Cref, S = oracle.spmv(A.n_rows, A.row_ptr, A.col_idx, A.val, B)
+    assert oracle.bound_ok(M.apply(_gpu(B)).cpu().numpy(), Cref, A.row_ptr, S)[0]
