@@ -22,7 +22,7 @@ sys.path.insert(0, ROOT)
 
 METRIC = "CRS spMVM GFlop/s and effective HBM GB/s (% roofline) at 1 MI355X, FP64 vs mixed"
 HBM_PEAK = 8000.0  # GB/s, MI355X nominal
-KERNEL_NAMES = {"V4_lds_block": "k_lds_block<double,double>", "V6_sell64": "k_sell<double,double>"}
+KERNEL_NAMES = {"V4_lds_block": "k_lds_block<double,double>", "V6_sell64": "k_sell_pairs<double,double>"}
 SELL = 0  # plan flag requesting the V6 chunked copy; set in main()
 
 

@@ -4,12 +4,13 @@
 // 64 w slots; slot (j, lane) holds the j-th nonzero of row 64 k + lane.
 // Shorter rows are padded with col = -1, val = 0. This is a sliced ELLPACK
 // layout with slice height 64 (the SELL-C-sigma family with C = 64,
-// sigma = 1). Inside a chunk the slots are stored in lane-interleaved pairs:
-// with P = floor(w / 2), slots 2p and 2p + 1 of lane l sit at 2 (64 p + l) and
-// 2 (64 p + l) + 1, and for odd w the last slot of lane l at 128 P + l. Each
-// lane then loads two slots of its row per instruction, and every load is one
-// contiguous 1 KB (val, float64) or 512-byte access per wavefront; no LDS or
-// barrier is needed, and each row is still summed in CRS order by one lane.
+// sigma = 1). Inside a chunk the slots are stored in lane-interleaved groups
+// of G (G = 2 for float64 values, 4 for float32): with Q = floor(w / G), slot
+// j < G Q of lane l sits at G (64 floor(j / G) + l) + j mod G, and each of the
+// w - G Q tail slots t at 64 G Q + 64 t + l. A lane then loads G slots of its
+// row per instruction (16-byte val loads), every load is one contiguous
+// access per wavefront, no LDS or barrier is needed, and each row is summed by
+// one lane.
 //
 // The copy is built on the device at plan creation in three passes: chunk
 // widths, an exclusive scan of the widths, and the fill. Its capacity is
@@ -31,10 +32,18 @@ template <typename VT> struct Pair;
 template <> struct Pair<double> { using type = f64x2; };
 template <> struct Pair<float> { using type = f32x2; };
 
-// Offset of slot j of `lane` inside a chunk of width w (see the layout above).
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef int32_t i32x4 __attribute__((ext_vector_type(4)));
+
+// Slots per lane-interleaved group for a value type (see the layout above).
+template <typename VT> constexpr int kGroup = sizeof(VT) == 8 ? 2 : 4;
+
+// Offset of slot j of `lane` inside a chunk of width w with groups of G.
+template <int G>
 __device__ __forceinline__ int64_t slot_offset(int64_t j, int lane, int64_t w) {
-  const int64_t P = w >> 1;
-  return j < 2 * P ? 2 * ((j >> 1) * kChunk + lane) + (j & 1) : 2 * P * kChunk + lane;
+  const int64_t Q = w / G;
+  return j < G * Q ? G * ((j / G) * kChunk + lane) + j % G
+                   : G * Q * kChunk + (j - G * Q) * kChunk + lane;
 }
 
 // Clamped row range: an invalid pattern (reported by validation, which runs
@@ -102,7 +111,7 @@ __global__ __launch_bounds__(kWG) void k_sell_fill(
     for (int u = 0; u < kU; ++u) {
       const int64_t j = j0 + u;
       if (j < w) {
-        const int64_t o = slot_offset(j, lane, w);
+        const int64_t o = slot_offset<kGroup<VT>>(j, lane, w);
         dc[o] = c[u];
         dv[o] = v[u];
       }
@@ -115,7 +124,7 @@ __global__ __launch_bounds__(kWG) void k_sell_fill(
 // slot after the rounds. The width is uniform over the wavefront, so the loop
 // and its masked last round are uniform branches.
 template <typename VT, typename BT>
-__global__ __launch_bounds__(kWG) void k_sell(int64_t nch, int64_t n,
+__global__ __launch_bounds__(kWG) void k_sell_pairs(int64_t nch, int64_t n,
                                               const int32_t* __restrict__ off,
                                               const int32_t* __restrict__ sci,
                                               const VT* __restrict__ sval,
@@ -167,6 +176,84 @@ __global__ __launch_bounds__(kWG) void k_sell(int64_t nch, int64_t n,
   if (row < n) C[row] = acc;
 }
 
+// float32 values: groups of four slots, kSellUQ groups per round; the up to
+// three tail slots are loaded before the first round and summed in it.
+constexpr int kSellUQ = 2;
+
+template <typename BT>
+__global__ __launch_bounds__(kWG) void k_sell_quads(int64_t nch, int64_t n,
+                                                    const int32_t* __restrict__ off,
+                                                    const int32_t* __restrict__ sci,
+                                                    const float* __restrict__ sval,
+                                                    const BT* __restrict__ B,
+                                                    double* __restrict__ C) {
+  const int64_t chunk = ((int64_t)blockIdx.x * kWG + threadIdx.x) / kChunk;
+  if (chunk >= nch) return;
+  const int lane = threadIdx.x % kChunk;
+  const int64_t a = off[chunk];
+  const int32_t w = (int32_t)(off[chunk + 1] - a);
+  const int32_t Q = w >> 2, T = w & 3;
+  const f32x4* vp = reinterpret_cast<const f32x4*>(sval + a * kChunk) + lane;
+  const i32x4* cp = reinterpret_cast<const i32x4*>(sci + a * kChunk) + lane;
+  float tv[3];
+  int32_t tc[3];
+#pragma unroll
+  for (int t = 0; t < 3; ++t) {
+    if (t < T) {
+      const int64_t o = a * kChunk + 4 * (int64_t)Q * kChunk + t * kChunk + lane;
+      tv[t] = dev::ld_stream(sval + o);
+      tc[t] = dev::ld_stream(sci + o);
+    } else {
+      tv[t] = 0.0f;
+      tc[t] = -1;
+    }
+  }
+  double acc = 0.0;
+  // padded and masked slots contribute fma(0, 0, acc) = acc exactly
+  int32_t q = 0;
+  bool first = true;
+  do {
+    f32x4 v[kSellUQ];
+    i32x4 c[kSellUQ];
+#pragma unroll
+    for (int u = 0; u < kSellUQ; ++u) {
+      if (q + u < Q) {
+        v[u] = dev::ld_stream(vp + (int64_t)(q + u) * kChunk);
+        c[u] = dev::ld_stream(cp + (int64_t)(q + u) * kChunk);
+      } else {
+        v[u] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+        c[u] = i32x4{-1, -1, -1, -1};
+      }
+    }
+    double tx[3];
+#pragma unroll
+    for (int t = 0; t < 3; ++t) tx[t] = (first && tc[t] >= 0) ? (double)B[tc[t]] : 0.0;
+    double x[kSellUQ][4];
+#pragma unroll
+    for (int u = 0; u < kSellUQ; ++u) {
+      x[u][0] = c[u].x >= 0 ? (double)B[c[u].x] : 0.0;
+      x[u][1] = c[u].y >= 0 ? (double)B[c[u].y] : 0.0;
+      x[u][2] = c[u].z >= 0 ? (double)B[c[u].z] : 0.0;
+      x[u][3] = c[u].w >= 0 ? (double)B[c[u].w] : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < kSellUQ; ++u) {
+      acc = fma((double)v[u].x, x[u][0], acc);
+      acc = fma((double)v[u].y, x[u][1], acc);
+      acc = fma((double)v[u].z, x[u][2], acc);
+      acc = fma((double)v[u].w, x[u][3], acc);
+    }
+    if (first) {
+#pragma unroll
+      for (int t = 0; t < 3; ++t) acc = fma((double)tv[t], tx[t], acc);
+    }
+    first = false;
+    q += kSellUQ;
+  } while (q < Q);
+  const int64_t row = chunk * kChunk + lane;
+  if (row < n) C[row] = acc;
+}
+
 inline unsigned grid_chunks(int64_t nch) {
   return (unsigned)((nch * kChunk + kWG - 1) / kWG);
 }
@@ -204,11 +291,11 @@ int launch_sell(const Plan& p, const void* B, double* C, hipStream_t s) {
   if (!p.sell_ok) return fail(SPMV_ERR_STATE, "V6 is not built for this plan");
   if (p.sell_nch == 0) return SPMV_OK;
   if (p.vdt == SPMV_F64)
-    k_sell<double, double><<<grid_chunks(p.sell_nch), kWG, 0, s>>>(
+    k_sell_pairs<double, double><<<grid_chunks(p.sell_nch), kWG, 0, s>>>(
         p.sell_nch, p.n_rows, p.sell_off, p.sell_ci, static_cast<const double*>(p.sell_val),
         static_cast<const double*>(B), C);
   else
-    k_sell<float, float><<<grid_chunks(p.sell_nch), kWG, 0, s>>>(
+    k_sell_quads<float><<<grid_chunks(p.sell_nch), kWG, 0, s>>>(
         p.sell_nch, p.n_rows, p.sell_off, p.sell_ci, static_cast<const float*>(p.sell_val),
         static_cast<const float*>(B), C);
   SPMV_HIP(hipGetLastError());
