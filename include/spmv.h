@@ -127,7 +127,8 @@ int spmv_workspace_size(int64_t n_rows, int64_t n_cols, int64_t nnz, uint32_t fl
  * Unless SPMV_FLAG_SKIP_VALIDATE is set, the CRS arrays are checked on the
  * device (row_ptr[0]=0, nondecreasing, row_ptr[n_rows]=nnz, 0<=col<n_cols)
  * and SPMV_ERR_BAD_CRS is returned on violation. This call synchronises the
- * stream once (to read back the analysis); it is the only call that does.
+ * stream: once to read back the analysis, and again for every timed launch
+ * of autotune or of the V6 duel (see SPMV_FLAG_SELL). Apply calls never do.
  */
 int spmv_create(spmv_handle* h, int64_t n_rows, int64_t n_cols, int64_t nnz,
                 const int32_t* row_ptr, const int32_t* col_idx, const void* val,
