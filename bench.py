@@ -22,7 +22,9 @@ sys.path.insert(0, ROOT)
 
 METRIC = "CRS spMVM GFlop/s and effective HBM GB/s (% roofline) at 1 MI355X, FP64 vs mixed"
 HBM_PEAK = 8000.0  # GB/s, MI355X nominal
-KERNEL_NAMES = {"V4_lds_block": "k_lds_block<double,double>", "V6_sell64": "k_sell_pairs<double,double>"}
+KERNEL_NAMES = {"V4_lds_block": "k_lds_block<double,double>",
+                "V4_lds_block_staged": "k_lds_block_staged<double,double>",
+                "V6_sell64": "k_sell_pairs<double,double>"}
 SELL = 0  # plan flag requesting the V6 chunked copy; set in main()
 
 
@@ -57,6 +59,12 @@ def stored_traffic(workload: str, variant_name: str):
     except (ValueError, KeyError):
         pass
     return None
+
+
+def variant_name(pkg, M) -> str:
+    """The plan's variant, with V4's B-staging form (its own kernel) named apart."""
+    v = pkg.VARIANTS[M.variant]
+    return "V4_lds_block_staged" if v == "V4_lds_block" and M.v4_staged else v
 
 
 def time_launches(fn, steps, warmup, stream):
@@ -135,7 +143,7 @@ def main():
     flags = pkg.SPMV_SELECT_AUTOTUNE if args.variant < 0 else pkg.SPMV_FLAG_VARIANT(args.variant)
     flags |= SELL
     M = pkg.CRSMatrix.from_crs(A, flags=flags, device=dev)
-    vname = pkg.VARIANTS[M.variant]
+    vname = variant_name(pkg, M)
     log(f"plan ready: nnz={A.nnz} variant={vname} blocks={M.num_blocks} "
         f"sell_slots={M.sell_slots}")
     Bd = torch.from_numpy(B).to(dev)
@@ -262,7 +270,7 @@ def run_extra(A, B, M, pkg, pm, dev, stream, args):
     ex["mixed_fp32_storage"] = {
         "gflops": round(pm.gflops(A.nnz, t), 1),
         "eff_gbs": round(pm.effective_gbs(A.n_rows, A.n_cols, A.nnz, t, 1, 4, 4), 1),
-        "variant": pkg.VARIANTS[M32.variant], "kernel_ms": round(t * 1000, 5)}
+        "variant": variant_name(pkg, M32), "kernel_ms": round(t * 1000, 5)}
     log(f"mixed: {ex['mixed_fp32_storage']}")
     del M32
     # triad ceiling
@@ -369,7 +377,7 @@ def run_rcm(pkg, pm, dev, stream):
             per, _ = time_launches(lambda: pkg.spmv_apply(M.handle, Bd, pkg.SPMV_F64, C), 30, 3,
                                    stream)
             t = float(np.median(per)) / 1000
-            res[tag] = {"variant": pkg.VARIANTS[M.variant], "kernel_ms": round(t * 1e3, 4),
+            res[tag] = {"variant": variant_name(pkg, M), "kernel_ms": round(t * 1e3, 4),
                         "gflops": round(pm.gflops(A.nnz, t), 1),
                         "eff_gbs": round(comp / t / 1e9, 1)}
             del M, Bd
@@ -455,7 +463,7 @@ def run_small(pkg, pm, dev, stream):
         torch.cuda.synchronize()
         cold.append(a.elapsed_time(b))
     cold_t = float(np.median(cold)) / 1000
-    res = {"variant": pkg.VARIANTS[M.variant], "warm_us": round(warm * 1e6, 2),
+    res = {"variant": variant_name(pkg, M), "warm_us": round(warm * 1e6, 2),
            "cold_us": round(cold_t * 1e6, 2), "warm_gflops": round(pm.gflops(L.nnz, warm), 1),
            "cold_gflops": round(pm.gflops(L.nnz, cold_t), 1),
            "warm_eff_gbs": round(comp / warm / 1e9, 1), "cold_eff_gbs": round(comp / cold_t / 1e9, 1)}
@@ -483,7 +491,7 @@ def run_mesh(pkg, pm, dev, stream):
         per, _ = time_launches(lambda: pkg.spmv_apply(M.handle, Bd, code, C), 30, 3, stream)
         t = float(np.median(per)) / 1000
         eff = pm.effective_gbs(A.n_rows, A.n_cols, A.nnz, t, 1, sv, sv)
-        res[tag] = {"variant": pkg.VARIANTS[M.variant], "kernel_ms": round(t * 1e3, 4),
+        res[tag] = {"variant": variant_name(pkg, M), "kernel_ms": round(t * 1e3, 4),
                     "gflops": round(pm.gflops(A.nnz, t), 1), "eff_gbs": round(eff, 1),
                     "pct_of_8tbs": round(100 * eff / HBM_PEAK, 1)}
         del M, Bd

@@ -97,6 +97,13 @@ typedef enum {
  * launches each, on a B of ones) and the faster is kept; autotune times V6
  * with the others. */
 #define SPMV_FLAG_SELL 0x20000u
+/* V4 in its B-staging form: each row block copies a range of B into LDS (its
+ * exact column span when that fits 2048 entries, else the 2048 columns around
+ * its rows) and gathers from it where it can. By default a plan stages when at
+ * least a quarter of its blocks fit exactly, and autotune times both forms;
+ * these flags force one form (setting both is SPMV_ERR_INVALID_ARG). */
+#define SPMV_FLAG_V4_STAGE_ON 0x40000u
+#define SPMV_FLAG_V4_STAGE_OFF 0x80000u
 
 #define SPMV_NUM_FEATURES 16
 #define SPMV_MLP_PARAMS 5638 /* 16->64->64->6: W1 b1 W2 b2 W3 b3, [out,in] row-major */
@@ -168,6 +175,9 @@ int spmv_get_autotune_times(spmv_handle h, double* us);
 /* Slots of the V6 copy (host out): 64 * sum of chunk widths, >= nnz; the
  * padding is slots - nnz. SPMV_ERR_STATE if the plan has no V6 copy. */
 int spmv_get_sell_slots(spmv_handle h, int64_t* slots);
+/* Whether V4 runs in its B-staging form (host out: 1 or 0; see
+ * SPMV_FLAG_V4_STAGE_ON). */
+int spmv_get_v4_staged(spmv_handle h, int* staged);
 /* Number of row blocks of the LDS-block variant (host out). */
 int spmv_get_num_blocks(spmv_handle h, int64_t* nblocks);
 int spmv_destroy(spmv_handle h);

@@ -275,11 +275,13 @@ __global__ void k_blocks(int64_t n, int64_t nblocks, const int32_t* __restrict__
   blocks[b] = make_int2((int32_t)lo, rp[lo]);
 }
 
-// Column bounds of every row block's chunk [S, min(E, S + budget)) (one
-// workgroup per block), so the product can stage B[cmin..cmax] in LDS when it
-// fits. S and E are clamped to [0, nnz] so an invalid pattern (reported by
-// validation in the same pass) reads nothing out of bounds.
-__global__ __launch_bounds__(kWG) void k_block_spans(int64_t nblocks, int64_t nnz,
+// Staging range of every row block (one workgroup per block): the exact
+// column bounds of its chunk [S, min(E, S + budget)) when they span at most
+// the LDS array (counted in staged_blocks), else the budget-wide window of
+// columns centred on the block's rows (clamped to [0, n_cols)). S and E are
+// clamped to [0, nnz] so an invalid pattern (reported by validation in the
+// same pass) reads nothing out of bounds.
+__global__ __launch_bounds__(kWG) void k_block_spans(int64_t nblocks, int64_t nnz, int64_t n_cols,
                                                      const int2* __restrict__ blocks,
                                                      const int32_t* __restrict__ ci,
                                                      int2* __restrict__ spans, WsHeader* h) {
@@ -311,9 +313,19 @@ __global__ __launch_bounds__(kWG) void k_block_spans(int64_t nblocks, int64_t nn
       a = lo[w] < a ? lo[w] : a;
       z = hi[w] > z ? hi[w] : z;
     }
-    // an empty chunk gets cmin > cmax (nothing staged)
-    spans[b] = a <= z ? make_int2(a, z) : make_int2(0, -1);
-    if (a <= z && (int64_t)z - a < kBlockBudget) atomicAdd(&h->staged_blocks, 1);
+    if (a > z) {
+      spans[b] = make_int2(0, -1);  // empty chunk: nothing staged
+    } else if ((int64_t)z - a < kBlockBudget) {
+      spans[b] = make_int2(a, z);
+      atomicAdd(&h->staged_blocks, 1);
+    } else {
+      const int64_t mid = ((int64_t)blocks[b].x + blocks[b + 1].x) / 2;
+      int64_t w0 = mid - kBlockBudget / 2;
+      w0 = w0 < 0 ? 0 : w0;
+      const int64_t w1 = w0 + kBlockBudget < n_cols ? w0 + kBlockBudget : n_cols;
+      w0 = w1 - kBlockBudget > 0 ? w1 - kBlockBudget : 0;
+      spans[b] = w0 < w1 ? make_int2((int32_t)w0, (int32_t)(w1 - 1)) : make_int2(0, -1);
+    }
   }
 }
 
@@ -356,8 +368,8 @@ int launch_analysis(Plan& p, const float* mu, const float* sigma, hipStream_t s)
                                                                p.blocks);
     SPMV_HIP(hipGetLastError());
     if (p.nblocks > 0) {
-      k_block_spans<<<(unsigned)p.nblocks, kWG, 0, s>>>(p.nblocks, p.nnz, p.blocks, p.col_idx,
-                                                        p.spans, p.hdr);
+      k_block_spans<<<(unsigned)p.nblocks, kWG, 0, s>>>(p.nblocks, p.nnz, p.n_cols, p.blocks,
+                                                        p.col_idx, p.spans, p.hdr);
       SPMV_HIP(hipGetLastError());
     }
   }

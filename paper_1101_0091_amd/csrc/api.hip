@@ -109,20 +109,29 @@ int autotune(Plan& p, hipStream_t s) {
       p.at_us[v] = INFINITY;
       continue;
     }
-    st = launch_spmv(p, v, p.at_B, p.at_C, s);
-    if (st) break;
-    float ms[kReps];
-    st = timed(v, &ms[0]);
-    if (st) break;
-    int reps = 1;
-    if (ms[0] <= 1.5f * best) {
-      for (; reps < kReps && !st; ++reps) st = timed(v, &ms[reps]);
+    // V4 is timed in both forms (with and without B staging); the faster stays
+    const int forms = v == SPMV_V4_LDS_BLOCK && p.nblocks > 0 && !p.v4_stage_forced ? 2 : 1;
+    const bool staged0 = p.v4_staged;
+    float form_med[2] = {INFINITY, INFINITY};
+    for (int f = 0; f < forms && !st; ++f) {
+      if (forms == 2) p.v4_staged = f == 1;
+      st = launch_spmv(p, v, p.at_B, p.at_C, s);
       if (st) break;
+      float ms[kReps];
+      st = timed(v, &ms[0]);
+      if (st) break;
+      int reps = 1;
+      if (ms[0] <= 1.5f * best) {
+        for (; reps < kReps && !st; ++reps) st = timed(v, &ms[reps]);
+        if (st) break;
+      }
+      std::sort(ms, ms + reps);
+      form_med[f] = ms[reps / 2];
+      best = std::min(best, form_med[f]);
     }
-    std::sort(ms, ms + reps);
-    const float med = ms[reps / 2];
-    p.at_us[v] = 1000.0 * med;
-    best = std::min(best, med);
+    if (st) break;
+    p.v4_staged = forms == 2 ? form_med[1] < form_med[0] : staged0;
+    p.at_us[v] = 1000.0 * std::min(form_med[0], form_med[1]);
   }
   hipEventDestroy(e0);
   hipEventDestroy(e1);
@@ -262,8 +271,11 @@ int plan_build(Plan& p, int64_t n_rows, int64_t n_cols, int64_t nnz, const int32
   if (mode > SPMV_SELECT_FIXED) return fail(SPMV_ERR_INVALID_ARG, "unknown selection mode");
   if (mode == SPMV_SELECT_FIXED && fixed >= SPMV_NUM_VARIANTS)
     return fail(SPMV_ERR_INVALID_ARG, "variant out of range");
-  if (flags & ~(0xFFFu | SPMV_FLAG_SKIP_VALIDATE | SPMV_FLAG_SELL))
+  if (flags & ~(0xFFFu | SPMV_FLAG_SKIP_VALIDATE | SPMV_FLAG_SELL | SPMV_FLAG_V4_STAGE_ON |
+                SPMV_FLAG_V4_STAGE_OFF))
     return fail(SPMV_ERR_INVALID_ARG, "unknown flag bits");
+  if ((flags & SPMV_FLAG_V4_STAGE_ON) && (flags & SPMV_FLAG_V4_STAGE_OFF))
+    return fail(SPMV_ERR_INVALID_ARG, "SPMV_FLAG_V4_STAGE_ON and _OFF together");
   if (mode == SPMV_SELECT_FIXED && fixed == SPMV_V6_SELL64 && !(flags & SPMV_FLAG_SELL))
     return fail(SPMV_ERR_INVALID_ARG, "variant V6 needs SPMV_FLAG_SELL");
   const PlanLayout L = plan_layout(n_rows, n_cols, nnz, flags);
@@ -331,6 +343,10 @@ int plan_build(Plan& p, int64_t n_rows, int64_t n_cols, int64_t nnz, const int32
   if (st) return st;
   std::memcpy(p.features, hh.features, sizeof(p.features));
   p.staged_blocks = hh.staged_blocks;
+  p.v4_stage_forced = (flags & (SPMV_FLAG_V4_STAGE_ON | SPMV_FLAG_V4_STAGE_OFF)) != 0;
+  p.v4_staged = (flags & SPMV_FLAG_V4_STAGE_ON)    ? true
+                : (flags & SPMV_FLAG_V4_STAGE_OFF) ? false
+                                                   : p.staged_blocks * 4 >= p.nblocks;
   for (int b = 0; b < kNumBins; ++b) {
     p.bin_count[b] = hh.bin_count[b];
     p.bin_offset[b] = hh.bin_offset[b];
@@ -437,6 +453,12 @@ int spmv_get_autotune_times(spmv_handle h, double* us) {
   if (!h || !us) return fail(SPMV_ERR_INVALID_ARG, "null argument");
   if (!h->p.have_autotune) return fail(SPMV_ERR_STATE, "autotune did not run for this plan");
   std::memcpy(us, h->p.at_us, sizeof(h->p.at_us));
+  return SPMV_OK;
+}
+
+int spmv_get_v4_staged(spmv_handle h, int* staged) {
+  if (!h || !staged) return fail(SPMV_ERR_INVALID_ARG, "null argument");
+  *staged = h->p.v4_staged ? 1 : 0;
   return SPMV_OK;
 }
 

@@ -59,6 +59,8 @@ struct Plan {
   int2* blocks = nullptr;         // device [nblocks+1]: (first row, row_ptr[first row])
   int2* spans = nullptr;          // device [nblocks]: (smallest, largest) column of the block's chunk
   int64_t staged_blocks = 0;      // blocks with a span that fits the LDS staging array
+  bool v4_staged = false;         // V4 runs the staging kernel (span rule, flag or autotune)
+  bool v4_stage_forced = false;   // the form was fixed by a plan flag
   int64_t nblocks = 0;
   int32_t* bin_rows = nullptr;    // device int32[n_rows]
   unsigned long long* stats_part = nullptr;  // device [kStatsGrid][kPartSlots]

@@ -194,11 +194,13 @@ __device__ __forceinline__ void block_rows(const BlockLds& L, const int32_t* __r
 
 // S = row_ptr[r0] and E = row_ptr[r1] come from the block table, so the
 // workgroup's first dependent round trip already yields the stream bounds.
-// [cmin, cmax] bounds the columns of the chunk [S, min(E, S + budget)); when
-// the span fits the staging array `stage` (stage_cap doubles of LDS that may
-// overlap L, and cmin <= cmax), B[cmin..cmax] is first copied into it with
-// coalesced loads and the gathers read LDS; the products then overwrite it.
-// STAGE = false compiles the path out (callers without column bounds).
+// When cmin <= cmax and the range fits the staging array `stage` (stage_cap
+// doubles of LDS that may overlap L), B[cmin..cmax] is first copied into it
+// with coalesced loads; gathers of columns inside the range read LDS, the
+// others B; the products then overwrite the array. The range is either the
+// exact column span of the chunk [S, min(E, S + budget)) or, for blocks whose
+// span is wider, a window around the block's rows.
+// STAGE = false compiles the path out (callers without a range).
 template <typename VT, typename BT, bool ACC = false, bool STAGE = false>
 __device__ __forceinline__ void lds_block(BlockLds& L, const int32_t* __restrict__ rp,
                                           const int32_t* __restrict__ ci,
@@ -234,7 +236,7 @@ __device__ __forceinline__ void lds_block(BlockLds& L, const int32_t* __restrict
 #pragma unroll
       for (int u = 0; u < kPer; ++u) {
         const int k = tid + u * kWG;
-        if (k < nin) b[u] = stage[c[u] - cmin];
+        if (k < nin) b[u] = (c[u] >= cmin && c[u] <= cmax) ? stage[c[u] - cmin] : widen(B[c[u]]);
       }
       __syncthreads();  // every staged entry read before the products overwrite them
     }

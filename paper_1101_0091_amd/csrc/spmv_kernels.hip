@@ -108,11 +108,12 @@ __global__ __launch_bounds__(kWG) void k_lds_block(int64_t nblocks, const int2* 
   dev::lds_block<VT, BT, ACC>(L, rp, ci, val, B, C, m0.x, m1.x, m0.y, m1.y);
 }
 
-// The same with B staging: a block whose chunk's columns span at most the
-// LDS product array gathers B from a staged copy of B[cmin..cmax] (banded and
-// stencil-like blocks). The staging path costs registers and changes the
-// compiler's load schedule, so it is a kernel of its own, used by a plan only
-// when at least a quarter of its blocks can stage.
+// The same with B staging: each block copies its staging range of B (the
+// exact column span when it fits the LDS product array, else a window around
+// the block's rows) into LDS and gathers from it where it can. The staging
+// path costs registers and changes the compiler's load schedule, so it is a
+// kernel of its own; a plan uses it when at least a quarter of its blocks fit
+// exactly, or when autotune measured it faster.
 template <typename VT, typename BT, bool ACC>
 __global__ __launch_bounds__(kWG) void k_lds_block_staged(int64_t nblocks,
                                                           const int2* __restrict__ blocks,
@@ -133,7 +134,7 @@ __global__ __launch_bounds__(kWG) void k_lds_block_staged(int64_t nblocks,
 template <typename VT, typename BT, bool ACC>
 void launch_lds_block(const Plan& p, const VT* val, const BT* B, double* C, hipStream_t s) {
   if (p.nblocks <= 0) return;
-  if (p.staged_blocks * 4 >= p.nblocks)
+  if (p.v4_staged)
     k_lds_block_staged<VT, BT, ACC><<<(unsigned)p.nblocks, kWG, 0, s>>>(
         p.nblocks, p.blocks, p.spans, p.row_ptr, p.col_idx, val, B, C);
   else

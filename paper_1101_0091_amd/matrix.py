@@ -6,7 +6,7 @@ from __future__ import annotations
 import numpy as np
 
 from . import (SPMV_ERR_STATE, SPMV_F32, SPMV_F64, SPMV_SELECT_DEFAULT, SPMV_SELECT_MLP,
-               SpmvError, dtype_code, spmv_get_sell_slots,
+               SpmvError, dtype_code, spmv_get_sell_slots, spmv_get_v4_staged,
                load_selector, spmv_selector_loaded, spmm_apply, spmv_apply, spmv_batch_apply,
                spmv_batch_apply_each, spmv_batch_create, spmv_batch_destroy, spmv_batch_set_mode,
                spmv_batch_get_num_tiles, spmv_batch_workspace_size, spmv_create, spmv_destroy,
@@ -72,6 +72,11 @@ class CRSMatrix:
     @property
     def num_blocks(self) -> int:
         return spmv_get_num_blocks(self.handle)
+
+    @property
+    def v4_staged(self) -> bool:
+        """Whether V4 runs in its B-staging form."""
+        return spmv_get_v4_staged(self.handle)
 
     @property
     def sell_slots(self):

@@ -76,6 +76,7 @@ def _create(**kw):
     (dict(flags=pkg.SPMV_FLAG_VARIANT(6) | pkg.SPMV_FLAG_SELL, ws_bytes=1 << 12),
      pkg.SPMV_ERR_WORKSPACE),
     (dict(flags=1 << 20), pkg.SPMV_ERR_INVALID_ARG),
+    (dict(flags=pkg.SPMV_FLAG_V4_STAGE_ON | pkg.SPMV_FLAG_V4_STAGE_OFF), pkg.SPMV_ERR_INVALID_ARG),
     (dict(workspace=None), pkg.SPMV_ERR_WORKSPACE),
     (dict(workspace=0x10010), pkg.SPMV_ERR_WORKSPACE),
     (dict(ws_bytes=16), pkg.SPMV_ERR_WORKSPACE),

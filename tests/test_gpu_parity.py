@@ -75,6 +75,31 @@ def test_all_variants_vs_oracle(name, dt):
 
 
 @pytest.mark.parametrize("dt", ["f64", "f32"])
+@pytest.mark.parametrize("name", list(CASES))
+def test_v4_both_staging_forms(name, dt):
+    """V4 with B staging forced on (exact spans, and windows around the rows
+    for wider blocks, where gathers outside the window read B) and forced off."""
+    A, B = case(name)
+    if dt == "f32":
+        val_h, B_h, tdt = A.val.astype(np.float32), B.astype(np.float32), torch.float32
+    else:
+        val_h, B_h, tdt = A.val, B, torch.float64
+    Cref, S = oracle.spmv(A.n_rows, A.row_ptr, A.col_idx, val_h, B_h)
+    Bd = _gpu(B_h)
+    outs = []
+    for form in (pkg.SPMV_FLAG_V4_STAGE_ON, pkg.SPMV_FLAG_V4_STAGE_OFF):
+        M = pkg.CRSMatrix(A.n_rows, A.n_cols, A.row_ptr, A.col_idx, val_h, val_dtype=tdt,
+                          flags=pkg.SPMV_FLAG_VARIANT(4) | form, device=DEV)
+        C = torch.full((A.n_rows,), float("nan"), dtype=torch.float64, device=DEV)
+        M.apply(Bd, C)
+        ok, worst = oracle.bound_ok(C.cpu().numpy(), Cref, A.row_ptr, S)
+        assert ok, (name, dt, form, worst)
+        outs.append(C)
+    # staging changes where B is read from, not the arithmetic: bitwise equal
+    assert torch.equal(outs[0], outs[1])
+
+
+@pytest.mark.parametrize("dt", ["f64", "f32"])
 def test_integer_inputs_bit_exact(dt):
     A = crsgen.random_crs(30_000, 20_000, seed=41, max_len=3000, empty_frac=0.05,
                           integer=True)
@@ -154,6 +179,12 @@ def test_full_size_hamiltonian_and_mesh():
             M.variant = v
             ok, worst = oracle.bound_ok(M.apply(Bd).cpu().numpy(), Cref, A.row_ptr, S)
             assert ok, (name, v, worst)
+        # V4 with B staging forced on (row windows on these wide-span blocks)
+        Ms = pkg.CRSMatrix.from_crs(A, flags=pkg.SPMV_FLAG_VARIANT(4) | pkg.SPMV_FLAG_V4_STAGE_ON,
+                                    device=DEV)
+        ok, worst = oracle.bound_ok(Ms.apply(Bd).cpu().numpy(), Cref, A.row_ptr, S)
+        assert ok, (name, "v4 staged", worst)
+        del Ms
         # FP32 storage against the widened-input oracle
         v32, b32 = A.val.astype(np.float32), B.astype(np.float32)
         C32ref, S32 = oracle.spmv(A.n_rows, A.row_ptr, A.col_idx, v32, b32)
