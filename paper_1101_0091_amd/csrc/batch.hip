@@ -76,12 +76,15 @@ __global__ __launch_bounds__(kWG) void k_batch_tiles(int32_t count,
   }
 }
 
-// Column bounds of every tile's chunk [S, min(E, S + budget)) (one workgroup
-// per tile), so the apply can stage B[cmin..cmax] in LDS when it fits. S and
-// E are clamped to [0, nnz] so an invalid pattern (reported by validation in
-// the same pass) reads nothing out of bounds.
+// Staging range of every tile (one workgroup per tile): the column bounds of
+// its chunk [S, min(E, S + budget)) when they span at most the LDS array, else
+// the budget-wide window of columns centred on the tile's rows (clamped to
+// the matrix's columns). S and E are clamped to [0, nnz] so an invalid
+// pattern (reported by validation in the same pass) reads nothing out of
+// bounds.
 __global__ __launch_bounds__(kWG) void k_batch_spans(int64_t ntiles,
                                                      const int64_t* __restrict__ nz,
+                                                     const int64_t* __restrict__ nc,
                                                      const int32_t* const* __restrict__ cis,
                                                      int32_t* __restrict__ tiles) {
   __shared__ int32_t lo[kWG / 64], hi[kWG / 64];
@@ -118,9 +121,22 @@ __global__ __launch_bounds__(kWG) void k_batch_spans(int64_t ntiles,
     }
     a = lo[0] < a ? lo[0] : a;
     z = hi[0] > z ? hi[0] : z;
-    // an empty chunk keeps cmin > cmax (nothing staged)
-    tl[5] = a <= z ? a : 0;
-    tl[6] = a <= z ? z : -1;
+    if (a > z) {  // empty chunk: nothing staged
+      tl[5] = 0;
+      tl[6] = -1;
+    } else if ((int64_t)z - a < kBlockBudget) {
+      tl[5] = a;
+      tl[6] = z;
+    } else {
+      const int64_t ncol = nc[m];
+      const int64_t mid = ((int64_t)tl[1] + tl[2]) / 2;
+      int64_t w0 = mid - kBlockBudget / 2;
+      w0 = w0 < 0 ? 0 : w0;
+      const int64_t w1 = w0 + kBlockBudget < ncol ? w0 + kBlockBudget : ncol;
+      w0 = w1 - kBlockBudget > 0 ? w1 - kBlockBudget : 0;
+      tl[5] = w0 < w1 ? (int32_t)w0 : 0;
+      tl[6] = w0 < w1 ? (int32_t)(w1 - 1) : -1;
+    }
   }
 }
 
@@ -139,10 +155,12 @@ __device__ __forceinline__ void batch_tile(dev::BlockLds& L, const int32_t* __re
   const int32_t m = tl[0], r0 = tl[1], r1 = tl[2], S = tl[3], E = tl[4], cmin = tl[5],
                 cmax = tl[6];
   if (r0 >= r1) return;
-  const BT* B = Bs ? static_cast<const BT*>(Bs[m]) : B1;
-  double* C = Cs ? Cs[m] : C1;
-  dev::lds_block<VT, BT, false, true>(L, rps[m], cis[m], static_cast<const VT*>(vals[m]), B, C,
-                                      r0, r1, S, E, cmin, cmax, L.prod, kBlockBudget);
+  const BT* B = static_cast<const BT*>(dev::global_ptr_or(Bs, m, static_cast<const void*>(B1)));
+  double* C = dev::global_ptr_or(Cs, m, C1);
+  dev::lds_block<VT, BT, false, true>(
+      L, dev::global_ptr_at(rps, m), dev::global_ptr_at(cis, m),
+      static_cast<const VT*>(dev::global_ptr_at(vals, m)), B, C, r0, r1, S, E, cmin, cmax,
+      L.prod, kBlockBudget);
 }
 
 // Persistent, static: workgroup w owns one contiguous range of tiles.
@@ -243,7 +261,7 @@ int launch_batch_build(Batch& b, const int64_t* toff, const int64_t* nr, const i
   k_batch_tiles<<<b.count, kWG, 0, s>>>(b.count, nr, toff, b.row_ptrs, b.tiles);
   SPMV_HIP(hipGetLastError());
   if (b.ntiles > 0) {
-    k_batch_spans<<<(unsigned)b.ntiles, kWG, 0, s>>>(b.ntiles, nz, b.col_idxs, b.tiles);
+    k_batch_spans<<<(unsigned)b.ntiles, kWG, 0, s>>>(b.ntiles, nz, nc, b.col_idxs, b.tiles);
     SPMV_HIP(hipGetLastError());
   }
   return SPMV_OK;

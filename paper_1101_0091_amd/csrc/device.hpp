@@ -58,6 +58,27 @@ __device__ __forceinline__ double group_sum(double x) {
 }
 
 // ------------------------------------------------------------ loads
+// A pointer read from device memory (the batch's arrays of matrix and vector
+// pointers) is generic to the compiler, and generic (flat) loads also count
+// against the LDS wait counter, so every LDS wait would wait for the streams
+// too. All such pointers address global memory: reading the element through
+// a global-pointer view of the array lets the compiler emit global loads and
+// stores for everything derived from it.
+template <typename T>
+__device__ __forceinline__ T* global_ptr_at(T* const* arr, int64_t i) {
+  using GP = __attribute__((address_space(1))) T*;
+  return (T*)reinterpret_cast<const GP*>(arr)[i];
+}
+
+// arr ? arr[i] : alt, chosen between global pointers (a select of generic
+// pointers would be generic again).
+template <typename T>
+__device__ __forceinline__ T* global_ptr_or(T* const* arr, int64_t i, T* alt) {
+  using GP = __attribute__((address_space(1))) T*;
+  const GP g = arr ? reinterpret_cast<const GP*>(arr)[i] : (GP)alt;
+  return (T*)g;
+}
+
 template <typename T>
 __device__ __forceinline__ T ld_stream(const T* p) {
   return __builtin_nontemporal_load(p);
@@ -236,7 +257,18 @@ __device__ __forceinline__ void lds_block(BlockLds& L, const int32_t* __restrict
 #pragma unroll
       for (int u = 0; u < kPer; ++u) {
         const int k = tid + u * kWG;
-        if (k < nin) b[u] = (c[u] >= cmin && c[u] <= cmax) ? stage[c[u] - cmin] : widen(B[c[u]]);
+        if (k < nin) {
+          // the LDS read is unconditional (clamped index) and its value is
+          // pinned by an empty register barrier, so that the compiler cannot
+          // fold it and the global load into one flat load from a selected
+          // address (flat loads also wait on the LDS counter)
+          const bool in = c[u] >= cmin && c[u] <= cmax;
+          double xs = stage[in ? c[u] - cmin : 0];
+          asm volatile("" : "+v"(xs));
+          double xg = 0.0;
+          if (!in) xg = widen(B[c[u]]);
+          b[u] = in ? xs : xg;
+        }
       }
       __syncthreads();  // every staged entry read before the products overwrite them
     }
