@@ -21,8 +21,8 @@ __global__ __launch_bounds__(kWG) void k_batch_validate(
   const int32_t m = blockIdx.x;
   if (m >= count) return;
   const int64_t n = nr[m], ncol = nc[m], nnz = nz[m];
-  const int32_t* rp = rps[m];
-  const int32_t* ci = cis[m];
+  const int32_t* rp = dev::global_ptr_at(rps, m);
+  const int32_t* ci = dev::global_ptr_at(cis, m);
   int bad = 0;
   for (int64_t i = threadIdx.x; i < n; i += kWG)
     if (rp[i + 1] < rp[i]) bad |= 1;
@@ -60,7 +60,7 @@ __global__ __launch_bounds__(kWG) void k_batch_tiles(int32_t count,
   if (m >= count) return;
   const int64_t n = nr[m];
   const int64_t nb = toff[m + 1] - toff[m];
-  const int32_t* rp = rps[m];
+  const int32_t* rp = dev::global_ptr_at(rps, m);
   for (int64_t b = threadIdx.x; b < nb; b += kWG) {
     const int32_t r0 = first_row_at(rp, n, b * kBlockBudget);
     const int32_t r1 = (b + 1 == nb) ? (int32_t)n : first_row_at(rp, n, (b + 1) * kBlockBudget);
@@ -97,7 +97,7 @@ __global__ __launch_bounds__(kWG) void k_batch_spans(int64_t ntiles,
   S = S < 0 ? 0 : S > nnz ? nnz : S;
   E = E < S ? S : E > nnz ? nnz : E;
   if (E - S > kBlockBudget) E = S + kBlockBudget;
-  const int32_t* ci = cis[m];
+  const int32_t* ci = dev::global_ptr_at(cis, m);
   int32_t a = INT32_MAX, z = INT32_MIN;
   for (int64_t j = S + threadIdx.x; j < E; j += kWG) {
     const int32_t c = ci[j];
