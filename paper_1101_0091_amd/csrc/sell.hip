@@ -26,12 +26,7 @@ constexpr int kChunk = 64;  // rows per chunk = lanes per wavefront
 constexpr int kSellUP = 8;  // slot pairs of one row loaded before the first is used
 
 typedef double f64x2 __attribute__((ext_vector_type(2)));
-typedef float f32x2 __attribute__((ext_vector_type(2)));
 typedef int32_t i32x2 __attribute__((ext_vector_type(2)));
-template <typename VT> struct Pair;
-template <> struct Pair<double> { using type = f64x2; };
-template <> struct Pair<float> { using type = f32x2; };
-
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 typedef int32_t i32x4 __attribute__((ext_vector_type(4)));
 
@@ -119,17 +114,18 @@ __global__ __launch_bounds__(kWG) void k_sell_fill(
   }
 }
 
-// C = A*B from the chunked copy: lane l of the wavefront of chunk k owns row
-// 64 k + l and sums its slots in order, kSellUP pairs per round, the odd last
-// slot after the rounds. The width is uniform over the wavefront, so the loop
-// and its masked last round are uniform branches.
-template <typename VT, typename BT>
+// C = A*B from the chunked copy with float64 values: lane l of the wavefront
+// of chunk k owns row 64 k + l and sums its slots in order, kSellUP pairs per
+// round, the odd last slot after the rounds. The width is uniform over the
+// wavefront, so the loop and its masked last round are uniform branches.
 __global__ __launch_bounds__(kWG) void k_sell_pairs(int64_t nch, int64_t n,
-                                              const int32_t* __restrict__ off,
-                                              const int32_t* __restrict__ sci,
-                                              const VT* __restrict__ sval,
-                                              const BT* __restrict__ B, double* __restrict__ C) {
-  using V2 = typename Pair<VT>::type;
+                                                    const int32_t* __restrict__ off,
+                                                    const int32_t* __restrict__ sci,
+                                                    const double* __restrict__ sval,
+                                                    const double* __restrict__ B,
+                                                    double* __restrict__ C) {
+  using VT = double;
+  using V2 = f64x2;
   const int64_t chunk = ((int64_t)blockIdx.x * kWG + threadIdx.x) / kChunk;
   if (chunk >= nch) return;
   const int lane = threadIdx.x % kChunk;
@@ -291,7 +287,7 @@ int launch_sell(const Plan& p, const void* B, double* C, hipStream_t s) {
   if (!p.sell_ok) return fail(SPMV_ERR_STATE, "V6 is not built for this plan");
   if (p.sell_nch == 0) return SPMV_OK;
   if (p.vdt == SPMV_F64)
-    k_sell_pairs<double, double><<<grid_chunks(p.sell_nch), kWG, 0, s>>>(
+    k_sell_pairs<<<grid_chunks(p.sell_nch), kWG, 0, s>>>(
         p.sell_nch, p.n_rows, p.sell_off, p.sell_ci, static_cast<const double*>(p.sell_val),
         static_cast<const double*>(B), C);
   else
