@@ -34,7 +34,10 @@ def log(msg):
 
 # sources that define each variant's product kernel (a stored counter record
 # is valid only while these files are unchanged)
-KERNEL_SOURCES = {"V6_sell64": ("sell.hip", "device.hpp", "common.hpp")}
+KERNEL_SOURCES = {"V6_sell64": ("sell.hip", "device.hpp", "common.hpp"),
+                  # the staged form's B ranges are chosen at create (analysis.hip)
+                  "V4_lds_block_staged": ("spmv_kernels.hip", "device.hpp", "common.hpp",
+                                          "analysis.hip")}
 DEFAULT_SOURCES = ("spmv_kernels.hip", "device.hpp", "common.hpp")
 
 

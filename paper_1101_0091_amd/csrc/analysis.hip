@@ -277,10 +277,14 @@ __global__ void k_blocks(int64_t n, int64_t nblocks, const int32_t* __restrict__
 
 // Staging range of every row block (one workgroup per block): the exact
 // column bounds of its chunk [S, min(E, S + budget)) when they span at most
-// the LDS array (counted in staged_blocks), else the budget-wide window of
-// columns centred on the block's rows (clamped to [0, n_cols)). S and E are
-// clamped to [0, nnz] so an invalid pattern (reported by validation in the
-// same pass) reads nothing out of bounds.
+// the LDS array (counted in staged_blocks), else a budget-wide window of
+// columns: of kWinCand windows starting at the one centred on the block's
+// rows shifted by multiples of kWinStep columns (clamped to [0, n_cols)), the
+// one holding most of the chunk's entries (ties to the least shift). S and E
+// are clamped to [0, nnz] so an invalid pattern (reported by validation in
+// the same pass) reads nothing out of bounds.
+constexpr int kWinCand = 9;     // candidate windows per block
+constexpr int kWinStep = 256;   // shift between candidates, in columns
 __global__ __launch_bounds__(kWG) void k_block_spans(int64_t nblocks, int64_t nnz, int64_t n_cols,
                                                      const int2* __restrict__ blocks,
                                                      const int32_t* __restrict__ ci,
@@ -313,19 +317,54 @@ __global__ __launch_bounds__(kWG) void k_block_spans(int64_t nblocks, int64_t nn
       a = lo[w] < a ? lo[w] : a;
       z = hi[w] > z ? hi[w] : z;
     }
+    lo[0] = a;  // the block-wide bounds, read by every lane after the barrier
+    hi[0] = z;
     if (a > z) {
       spans[b] = make_int2(0, -1);  // empty chunk: nothing staged
     } else if ((int64_t)z - a < kBlockBudget) {
       spans[b] = make_int2(a, z);
       atomicAdd(&h->staged_blocks, 1);
-    } else {
-      const int64_t mid = ((int64_t)blocks[b].x + blocks[b + 1].x) / 2;
-      int64_t w0 = mid - kBlockBudget / 2;
-      w0 = w0 < 0 ? 0 : w0;
-      const int64_t w1 = w0 + kBlockBudget < n_cols ? w0 + kBlockBudget : n_cols;
-      w0 = w1 - kBlockBudget > 0 ? w1 - kBlockBudget : 0;
-      spans[b] = w0 < w1 ? make_int2((int32_t)w0, (int32_t)(w1 - 1)) : make_int2(0, -1);
     }
+  }
+  // wide chunk: every lane counts its entries inside each candidate window
+  __syncthreads();
+  const int32_t a0 = lo[0], z0 = hi[0];
+  if (!(a0 <= z0) || (int64_t)z0 - a0 < kBlockBudget) return;  // block-uniform
+  const int64_t mid = ((int64_t)blocks[b].x + blocks[b + 1].x) / 2;
+  int64_t w0c[kWinCand];
+  int32_t cnt[kWinCand];
+  for (int q = 0; q < kWinCand; ++q) {
+    int64_t w0 = mid - kBlockBudget / 2 + (int64_t)(q - kWinCand / 2) * kWinStep;
+    w0 = w0 + kBlockBudget > n_cols ? n_cols - kBlockBudget : w0;
+    w0c[q] = w0 < 0 ? 0 : w0;
+    cnt[q] = 0;
+  }
+  for (int64_t j = S + threadIdx.x; j < E; j += kWG) {
+    const int64_t c = ci[j];
+    for (int q = 0; q < kWinCand; ++q) cnt[q] += c >= w0c[q] && c < w0c[q] + kBlockBudget;
+  }
+  __shared__ int32_t wc[kWG / 64][kWinCand];
+  for (int q = 0; q < kWinCand; ++q) {
+    int32_t x = cnt[q];
+    for (int o = 32; o >= 1; o >>= 1) x += __shfl_xor(x, o);
+    if (threadIdx.x % 64 == 0) wc[threadIdx.x / 64][q] = x;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int best = kWinCand / 2, best_n = -1;
+    for (int k = 0; k < kWinCand; ++k) {
+      // candidates in order of increasing shift: centre, -1, +1, -2, +2, ...
+      const int q = kWinCand / 2 + ((k & 1) ? -(k + 1) / 2 : k / 2);
+      int32_t n = 0;
+      for (int w = 0; w < kWG / 64; ++w) n += wc[w][q];
+      if (n > best_n) {
+        best_n = n;
+        best = q;
+      }
+    }
+    const int64_t w1 = w0c[best] + kBlockBudget < n_cols ? w0c[best] + kBlockBudget : n_cols;
+    spans[b] = w0c[best] < w1 ? make_int2((int32_t)w0c[best], (int32_t)(w1 - 1))
+                              : make_int2(0, -1);
   }
 }
 
