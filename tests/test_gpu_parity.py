@@ -513,3 +513,44 @@ def test_selector_plan_duels_with_v6(mode):
         assert M.variant in (M0.variant, pkg.SPMV_V6_SELL64)
     Cref, S = oracle.spmv(A.n_rows, A.row_ptr, A.col_idx, A.val, B)
     assert oracle.bound_ok(M.apply(_gpu(B)).cpu().numpy(), Cref, A.row_ptr, S)[0]
+
+
+@pytest.mark.parametrize("dt", ["f64", "f32"])
+@pytest.mark.parametrize("name", ["laplace2d_256", "hamiltonian_200k", "powerlaw_60k",
+                                  "long_rows", "mostly_empty"])
+def test_nonfinite_B_propagates(name, dt):
+    """NaN and infinite B entries propagate by IEEE rules in every variant
+    (and both V4 forms): C is NaN exactly where the oracle's is, infinite
+    where it is infinite with the same sign, and within the bound elsewhere.
+    Padded and masked slots never touch B."""
+    A, B = case(name)
+    B = B.copy()
+    rng = np.random.default_rng(17)
+    pick = rng.choice(A.n_cols, size=min(A.n_cols, 40), replace=False)
+    B[pick[:20]] = np.nan
+    B[pick[20:30]] = np.inf
+    B[pick[30:]] = -np.inf
+    if dt == "f32":
+        val_h, B_h, tdt = A.val.astype(np.float32), B.astype(np.float32), torch.float32
+    else:
+        val_h, B_h, tdt = A.val, B, torch.float64
+    Cref, S = oracle.spmv(A.n_rows, A.row_ptr, A.col_idx, val_h, B_h)
+    fin = np.isfinite(Cref)
+    Bd = _gpu(B_h)
+    for form in (pkg.SPMV_FLAG_V4_STAGE_ON, pkg.SPMV_FLAG_V4_STAGE_OFF):
+        M = pkg.CRSMatrix(A.n_rows, A.n_cols, A.row_ptr, A.col_idx, val_h, val_dtype=tdt,
+                          flags=pkg.SPMV_FLAG_VARIANT(4) | SELL | form, device=DEV)
+        for v in variants(M):
+            M.variant = v
+            C = M.apply(Bd).cpu().numpy()
+            assert np.array_equal(np.isnan(C), np.isnan(Cref)), (name, dt, v)
+            assert np.array_equal(C[np.isinf(Cref)], Cref[np.isinf(Cref)]), (name, dt, v)
+            rp = A.row_ptr
+            ok, worst = oracle.bound_ok(np.where(fin, C, 0.0), np.where(fin, Cref, 0.0), rp,
+                                        np.where(fin, S, 0.0))
+            assert ok, (name, dt, v, worst)
+    # the multi-RHS form on the same inputs, two columns
+    Bk = np.stack([B_h, B_h[::-1].copy()], axis=1)
+    Ck_ref, Sk = oracle.spmm(A.n_rows, A.row_ptr, A.col_idx, val_h, Bk)
+    Ck = M.spmm(_gpu(Bk)).cpu().numpy()
+    assert np.array_equal(np.isnan(Ck), np.isnan(Ck_ref))
