@@ -308,6 +308,18 @@ def run_extra(A, B, M, pkg, pm, dev, stream, args):
                         "mixed_gflops": round(pm.gflops(L.nnz, t32, k), 1)}
     ex["spmm_laplace2d_256"] = spmm
     log(f"spmm: {spmm}")
+    # multi-RHS on the headline matrix with its own plan (V6 copy: one pass for k <= 8)
+    big = {"variant": variant_name(pkg, M)}
+    for k in (2, 4, 8, 16):
+        Bk = torch.from_numpy(crsgen.uniform_vec(A.n_cols * k, 4).reshape(A.n_cols, k)).to(dev)
+        Ck = torch.empty((A.n_rows, k), dtype=torch.float64, device=dev)
+        per, _ = time_launches(lambda: pkg.spmm_apply(M.handle, k, Bk, k, pkg.SPMV_F64, Ck, k),
+                               20, 3, stream)
+        t = float(np.median(per)) / 1000
+        big[str(k)] = {"us": round(t * 1e6, 1), "fp64_gflops": round(pm.gflops(A.nnz, t, k), 1)}
+        del Bk, Ck
+    ex["spmm_" + ("hamiltonian_like_N6M" if A.n_rows == 6_000_000 else "workload")] = big
+    log(f"spmm on the workload: {big}")
     ex["split_shard"] = run_split(A, B, pkg, pm, dev, stream)
     ex["batch_4096"] = run_batch(pkg, pm, dev, stream)
     ex["laplace2d_256"] = run_small(pkg, pm, dev, stream)

@@ -418,6 +418,11 @@ int spmm_apply(spmv_handle h, int32_t k, const void* B, int64_t ldb, int b_dtype
   if ((!B && p.n_cols > 0 && p.nnz > 0) || (!C && p.n_rows > 0))
     return fail(SPMV_ERR_INVALID_ARG, "B or C is null");
   if ((int64_t)p.n_rows * ldc > INT64_MAX / 2) return fail(SPMV_ERR_UNSUPPORTED, "C too large");
+  // a plan running V6 multiplies up to 8 right-hand sides from its chunked copy
+  // (one pass over it); wider blocks use the row-group kernel, which reads
+  // the matrix once for any k
+  if (p.variant == SPMV_V6_SELL64 && p.sell_ok && k <= 8)
+    return launch_sell_spmm(p, k, B, ldb, C, ldc, as_stream(stream));
   return launch_spmm(p, k, B, ldb, C, ldc, as_stream(stream));
 }
 

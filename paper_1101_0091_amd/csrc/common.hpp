@@ -177,6 +177,8 @@ int64_t sell_chunks(int64_t n_rows);
 int64_t sell_capacity(int64_t nnz);
 int launch_sell_build(Plan& p, hipStream_t s);
 int launch_sell(const Plan& p, const void* B, double* C, hipStream_t s);
+int launch_sell_spmm(const Plan& p, int k, const void* B, int64_t ldb, double* C, int64_t ldc,
+                     hipStream_t s);
 // stream.hip
 int launch_triad(double* a, const double* b, const double* c, double s, int64_t n,
                  hipStream_t st);

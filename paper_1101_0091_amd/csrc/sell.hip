@@ -16,6 +16,8 @@
 // widths, an exclusive scan of the widths, and the fill. Its capacity is
 // reserved in the plan workspace; a pattern whose padded size does not fit
 // is reported back and V6 is then unavailable for that plan.
+#include <type_traits>
+
 #include "common.hpp"
 #include "device.hpp"
 
@@ -250,6 +252,80 @@ __global__ __launch_bounds__(kWG) void k_sell_quads(int64_t nch, int64_t n,
   if (row < n) C[row] = acc;
 }
 
+// Multi-RHS form from the chunked copy: C[i, c0 + t] = sum_j val(j) B[col(j), c0 + t]
+// for t < kc = min(KB, k - c0). Lane l of chunk k owns row 64 k + l and keeps
+// KB accumulators; every slot gathers the row segment B[col, c0 .. c0 + KB)
+// (16-byte loads when VEC: float64 B, 16-byte aligned rows and segments).
+// Slots per round shrink with KB to bound the registers in flight.
+template <typename VT, typename BT, int KB, bool VEC>
+__global__ __launch_bounds__(kWG) void k_sell_spmm(int64_t nch, int64_t n,
+                                                   const int32_t* __restrict__ off,
+                                                   const int32_t* __restrict__ sci,
+                                                   const VT* __restrict__ sval,
+                                                   const BT* __restrict__ B, int64_t ldb,
+                                                   double* __restrict__ C, int64_t ldc,
+                                                   int32_t k, int32_t c0) {
+  constexpr int G = kGroup<VT>;
+  constexpr int U = KB <= 4 ? 8 : 4;
+  const int64_t chunk = ((int64_t)blockIdx.x * kWG + threadIdx.x) / kChunk;
+  if (chunk >= nch) return;
+  const int lane = threadIdx.x % kChunk;
+  const int64_t a = off[chunk];
+  const int32_t w = (int32_t)(off[chunk + 1] - a);
+  const int32_t kc = k - c0 < KB ? k - c0 : KB;
+  double acc[KB];
+#pragma unroll
+  for (int t = 0; t < KB; ++t) acc[t] = 0.0;
+  for (int32_t j = 0; j < w; j += U) {
+    double v[U];
+    int32_t c[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      if (j + u < w) {
+        const int64_t o = a * kChunk + slot_offset<G>(j + u, lane, w);
+        v[u] = dev::widen(dev::ld_stream(sval + o));
+        c[u] = dev::ld_stream(sci + o);
+      } else {
+        v[u] = 0.0;
+        c[u] = -1;
+      }
+    }
+    double x[U][KB];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const BT* bp = B + (int64_t)(c[u] >= 0 ? c[u] : 0) * ldb + c0;
+      if constexpr (VEC && KB >= 2 && std::is_same<BT, double>::value) {
+        if (c[u] >= 0) {
+#pragma unroll
+          for (int t = 0; t < KB; t += 2) {
+            const f64x2 q = *reinterpret_cast<const f64x2*>(bp + t);
+            x[u][t] = q.x;
+            x[u][t + 1] = q.y;
+          }
+        } else {
+#pragma unroll
+          for (int t = 0; t < KB; ++t) x[u][t] = 0.0;
+        }
+      } else {
+#pragma unroll
+        for (int t = 0; t < KB; ++t) x[u][t] = (c[u] >= 0 && t < kc) ? (double)bp[t] : 0.0;
+      }
+    }
+    // masked slots add fma(0, 0, acc) = acc exactly (acc is never -0)
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+#pragma unroll
+      for (int t = 0; t < KB; ++t) acc[t] = fma(v[u], x[u][t], acc[t]);
+  }
+  const int64_t row = chunk * kChunk + lane;
+  if (row < n) {
+    double* out = C + row * ldc + c0;
+#pragma unroll
+    for (int t = 0; t < KB; ++t)
+      if (t < kc) out[t] = acc[t];
+  }
+}
+
 inline unsigned grid_chunks(int64_t nch) {
   return (unsigned)((nch * kChunk + kWG - 1) / kWG);
 }
@@ -281,6 +357,57 @@ int launch_sell_build(Plan& p, hipStream_t s) {
         p.sell_off, cap64, p.sell_ci, static_cast<float*>(p.sell_val), &p.hdr->sell_total);
   SPMV_HIP(hipGetLastError());
   return SPMV_OK;
+}
+
+namespace {
+template <typename VT, typename BT, int KB, bool VEC>
+int sell_spmm_pass(const Plan& p, int k, int c0, const BT* B, int64_t ldb, double* C, int64_t ldc,
+                   hipStream_t s) {
+  k_sell_spmm<VT, BT, KB, VEC><<<grid_chunks(p.sell_nch), kWG, 0, s>>>(
+      p.sell_nch, p.n_rows, p.sell_off, p.sell_ci, static_cast<const VT*>(p.sell_val), B, ldb, C,
+      ldc, k, c0);
+  SPMV_HIP(hipGetLastError());
+  return SPMV_OK;
+}
+
+template <typename VT, typename BT>
+int sell_spmm_typed(const Plan& p, int k, const BT* B, int64_t ldb, double* C, int64_t ldc,
+                    hipStream_t s) {
+  // columns in blocks of KB = the smallest of 1, 2, 4, 8 covering min(k, 8)
+  const int KB = k >= 5 ? 8 : k >= 3 ? 4 : k == 2 ? 2 : 1;
+  const bool vec = std::is_same<BT, double>::value && KB >= 2 &&
+                   reinterpret_cast<uintptr_t>(B) % 16 == 0 && ldb % 2 == 0;
+  for (int c0 = 0; c0 < k; c0 += KB) {
+    // a full-width block takes the vector path; a partial last block the scalar one
+    const bool full = c0 + KB <= k;
+    int st = SPMV_OK;
+    switch (KB) {
+      case 1: st = sell_spmm_pass<VT, BT, 1, false>(p, k, c0, B, ldb, C, ldc, s); break;
+      case 2:
+        st = vec && full ? sell_spmm_pass<VT, BT, 2, true>(p, k, c0, B, ldb, C, ldc, s)
+                         : sell_spmm_pass<VT, BT, 2, false>(p, k, c0, B, ldb, C, ldc, s);
+        break;
+      case 4:
+        st = vec && full ? sell_spmm_pass<VT, BT, 4, true>(p, k, c0, B, ldb, C, ldc, s)
+                         : sell_spmm_pass<VT, BT, 4, false>(p, k, c0, B, ldb, C, ldc, s);
+        break;
+      default:
+        st = vec && full ? sell_spmm_pass<VT, BT, 8, true>(p, k, c0, B, ldb, C, ldc, s)
+                         : sell_spmm_pass<VT, BT, 8, false>(p, k, c0, B, ldb, C, ldc, s);
+    }
+    if (st) return st;
+  }
+  return SPMV_OK;
+}
+}  // namespace
+
+int launch_sell_spmm(const Plan& p, int k, const void* B, int64_t ldb, double* C, int64_t ldc,
+                     hipStream_t s) {
+  if (!p.sell_ok) return fail(SPMV_ERR_STATE, "V6 is not built for this plan");
+  if (p.sell_nch == 0) return SPMV_OK;
+  if (p.vdt == SPMV_F64)
+    return sell_spmm_typed<double, double>(p, k, static_cast<const double*>(B), ldb, C, ldc, s);
+  return sell_spmm_typed<float, float>(p, k, static_cast<const float*>(B), ldb, C, ldc, s);
 }
 
 int launch_sell(const Plan& p, const void* B, double* C, hipStream_t s) {

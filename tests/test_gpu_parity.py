@@ -162,6 +162,34 @@ def test_spmm_vs_oracle(k, dt):
     assert np.all(Cp[:, k] == 7.0)  # untouched padding column
 
 
+@pytest.mark.parametrize("dt", ["f64", "f32"])
+@pytest.mark.parametrize("k", [1, 2, 3, 4, 5, 8, 9, 16, 17])
+@pytest.mark.parametrize("name", ["hamiltonian_200k", "laplace2d_256"])
+def test_spmm_from_v6_copy(name, k, dt):
+    """A plan running V6 multiplies blocks of right-hand sides from its chunked
+    copy (column blocks of up to 8, vector loads of B row segments, a scalar
+    partial last block); also with padded leading dimensions."""
+    A, _ = case(name)
+    Bh = crsgen.uniform_vec(A.n_cols * k, 5).reshape(A.n_cols, k)
+    tdt = torch.float32 if dt == "f32" else torch.float64
+    val = A.val.astype(np.float32) if dt == "f32" else A.val
+    if dt == "f32":
+        Bh = Bh.astype(np.float32)
+    Cref, S = oracle.spmm(A.n_rows, A.row_ptr, A.col_idx, val, Bh)
+    M = pkg.CRSMatrix(A.n_rows, A.n_cols, A.row_ptr, A.col_idx, val, val_dtype=tdt,
+                      flags=pkg.SPMV_FLAG_VARIANT(6) | SELL, device=DEV)
+    C = M.spmm(_gpu(Bh)).cpu().numpy()
+    ok, worst = oracle.bound_ok(C, Cref, A.row_ptr, S)
+    assert ok, worst
+    Bp = torch.zeros((A.n_cols, k + 3), dtype=tdt, device=DEV)
+    Bp[:, :k] = _gpu(Bh)
+    Cp = torch.full((A.n_rows, k + 1), 7.0, dtype=torch.float64, device=DEV)
+    pkg.spmm_apply(M.handle, k, Bp, k + 3, M.code, Cp, k + 1)
+    Cp = Cp.cpu().numpy()
+    assert oracle.bound_ok(Cp[:, :k], Cref, A.row_ptr, S)[0]
+    assert np.all(Cp[:, k] == 7.0)
+
+
 def test_full_size_hamiltonian_and_mesh():
     """Workloads at full size (N = 6.0M and 21.95M), every row checked, with
     the plans the benchmark builds (V6 copy requested; it fits the
