@@ -23,3 +23,11 @@ def test_kernel_source_hash_is_per_variant():
     assert len(h6) == 16 and h6 == bench.kernel_source_hash("V6_sell64")
     assert h6 != h4 and h4 == bench.kernel_source_hash("V0_thread_row")
     assert "spmv_kernels.hip" not in bench.KERNEL_SOURCES["V6_sell64"]
+
+
+def test_kernel_source_hash_ignores_comments():
+    import bench
+    a = "int f(int x) {  // one\n  return x + 1; /* two */ }\n"
+    b = "int f(int x) {\n  return x + 1;\n}  // changed comment\n"
+    assert bench._code_only(a) == bench._code_only(b)
+    assert bench._code_only(a) != bench._code_only(a.replace("x + 1", "x + 2"))
