@@ -180,9 +180,11 @@ __global__ __launch_bounds__(kWG) void k_batch_static(
   }
 }
 
-// Persistent, dynamic: workgroups claim the next tile from a counter. The
-// last workgroup to finish returns both counters to zero, so consecutive
-// launches (and graph replays) need no clearing step.
+// Persistent, dynamic: workgroups claim the next kClaim consecutive tiles
+// from a counter (one atomic per claim). The last workgroup to finish returns
+// both counters to zero, so consecutive launches (and graph replays) need no
+// clearing step.
+constexpr int kClaim = 4;
 template <typename VT, typename BT>
 __global__ __launch_bounds__(kWG) void k_batch_dynamic(
     int64_t t0, int64_t t1, const int32_t* __restrict__ tiles,
@@ -194,11 +196,15 @@ __global__ __launch_bounds__(kWG) void k_batch_dynamic(
   __shared__ int64_t claim;
   for (;;) {
     __syncthreads();  // previous tile done with LDS and with `claim`
-    if (threadIdx.x == 0) claim = t0 + (int64_t)atomicAdd(&counters[0], 1u);
+    if (threadIdx.x == 0) claim = t0 + kClaim * (int64_t)atomicAdd(&counters[0], 1u);
     __syncthreads();
-    const int64_t t = claim;
-    if (t >= t1) break;
-    batch_tile<VT, BT>(L, tiles, t, rps, cis, vals, Bs, Cs, B1, C1);
+    const int64_t c = claim;
+    if (c >= t1) break;
+    const int64_t ce = c + kClaim < t1 ? c + kClaim : t1;
+    for (int64_t t = c; t < ce; ++t) {  // same trip count in every lane
+      if (t > c) __syncthreads();       // previous tile done with LDS
+      batch_tile<VT, BT>(L, tiles, t, rps, cis, vals, Bs, Cs, B1, C1);
+    }
   }
   if (threadIdx.x == 0) {
     __threadfence();
