@@ -4,7 +4,10 @@
 // scalars (alpha, beta, norms) stay in device memory, so an iteration is a
 // fixed launch sequence that can be captured into a HIP graph. Dot products
 // use a fixed grid and a fixed summation order: results are bitwise
-// reproducible.
+// reproducible. The workgroup that finishes a reduction last (one counter
+// atomic per workgroup) sums the partials and updates the scalars in the same
+// launch, so an iteration is four launches: the product, the fused p.Ap
+// reduction, the fused x/r update with r.r, and the p update.
 #include <cmath>
 #include <vector>
 
@@ -15,6 +18,17 @@ namespace spmv {
 namespace {
 
 constexpr int kRed = 1024;  // workgroups of every reduction (fixed: deterministic order)
+// Arrival counters of a reduction: kGroups group counters of kRed / kGroups
+// workgroups each, one 128-byte line apart, then a top counter. A single
+// counter hit by all 1024 workgroups serialises their atomics (a CG iteration
+// took 43 us against 22 us with a separate finishing launch).
+constexpr int kGroups = 32;
+constexpr int kLine = 32;  // unsigned words per 128-byte line
+constexpr int kCountWords = kLine * (kGroups + 1);
+static_assert(kRed % kGroups == 0 && kGroups < 64, "group counters");
+// scalar block: 64 double slots, then the counters
+constexpr size_t kScBlock = ((sizeof(double) * 64 + sizeof(unsigned) * kCountWords) + 255) &
+                            ~size_t(255);
 
 // scalar slots in the solver workspace
 enum : int { S_RR = 0, S_PAP = 1, S_ALPHA = 2, S_BETA = 3, S_BB = 4, S_TMP = 5 };
@@ -28,61 +42,108 @@ __device__ __forceinline__ double block_sum(double v, double* sh) {
   return s;
 }
 
-// partials[g] = sum over this workgroup's strided indices of x*y
+// What the last workgroup of a reduction does with its result: the scalar
+// update op (0: sc[dst] = sum; 1: sc[dst] = sqrt(sum); 2: alpha = rr / sum;
+// 3: beta = sum / rr, rr = sum) and an optional copy into a history array.
+struct Finish {
+  double* sc;
+  unsigned* count;  // kCountWords arrival counters, zero between launches
+  double* hist;
+  int op;
+  int dst;
+};
+
+// Called by every workgroup of a kRed-workgroup reduction with its partial
+// sum in thread 0. Thread 0 stores the partial as a device-scope atomic (a
+// store that is coherent across the XCDs' L2 caches) and, once the store is
+// acknowledged, counts the arrival in its group's counter; the workgroup that
+// completes a group counts the group in the top counter, and the workgroup
+// that completes the top counter has every partial behind it: it reads them
+// with device-scope atomic loads in index order, applies the op and clears the
+// counters for the next launch. No cache writeback or invalidation is needed
+// (a __threadfence in each of the 1024 workgroups made a CG iteration three
+// times slower), and no workgroup waits for another, so nothing can stall.
+__device__ __forceinline__ void finish_if_last(double* __restrict__ partials, double part,
+                                               const Finish& f, double* sh) {
+  __shared__ unsigned last;
+  if (threadIdx.x == 0) {
+    __hip_atomic_store(partials + blockIdx.x, part, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    // the arrival is counted only once the store is acknowledged
+    asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+    const unsigned grp = blockIdx.x / (kRed / kGroups);
+    unsigned l = 0;
+    if (atomicAdd(f.count + kLine * (1 + grp), 1u) == (unsigned)(kRed / kGroups - 1))
+      l = atomicAdd(f.count, 1u) == (unsigned)(kGroups - 1);
+    last = l;
+  }
+  __syncthreads();
+  if (!last) return;
+  // all loads issued before the first add; the sum keeps index order
+  static_assert(kRed == 4 * kWG, "four partials per thread");
+  double v[4];
+#pragma unroll
+  for (int u = 0; u < 4; ++u)
+    v[u] = __hip_atomic_load(partials + threadIdx.x + u * kWG, __ATOMIC_RELAXED,
+                             __HIP_MEMORY_SCOPE_AGENT);
+  double s = 0.0;
+#pragma unroll
+  for (int u = 0; u < 4; ++u) s += v[u];
+  s = block_sum(s, sh);
+  if (threadIdx.x == 0) {
+    double* sc = f.sc;
+    if (f.op == 0) sc[f.dst] = s;
+    if (f.op == 1) sc[f.dst] = sqrt(s);
+    if (f.op == 2) sc[S_ALPHA] = sc[S_RR] / s;
+    if (f.op == 3) {
+      sc[S_BETA] = s / sc[S_RR];
+      sc[S_RR] = s;
+    }
+    if (f.hist) *f.hist = f.op == 1 ? sqrt(s) : s;
+  }
+  if (threadIdx.x <= kGroups)
+    __hip_atomic_store(f.count + kLine * threadIdx.x, 0u, __ATOMIC_RELAXED,
+                       __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// sum of x*y over all n, then the Finish op
 __global__ __launch_bounds__(kWG) void k_dot(const double* __restrict__ x,
                                              const double* __restrict__ y, int64_t n,
-                                             double* __restrict__ partials) {
+                                             double* __restrict__ partials, Finish f) {
   __shared__ double sh[4];
   double s = 0.0;
   for (int64_t i = (int64_t)blockIdx.x * kWG + threadIdx.x; i < n; i += (int64_t)kRed * kWG)
     s = fma(x[i], y[i], s);
   s = block_sum(s, sh);
-  if (threadIdx.x == 0) partials[blockIdx.x] = s;
+  finish_if_last(partials, s, f, sh);
 }
 
-// Sum of the kRed partials in fixed order, then a scalar update:
-// op 0: sc[dst] = sum; 1: sc[dst] = sqrt(sum); 2: alpha = rr / sum;
-// 3: beta = sum / rr, rr = sum.
-__global__ __launch_bounds__(kWG) void k_finish(const double* __restrict__ partials,
-                                                double* __restrict__ sc, int op, int dst,
-                                                double* __restrict__ hist) {
-  __shared__ double sh[4];
-  double s = 0.0;
-  for (int g = threadIdx.x; g < kRed; g += kWG) s += partials[g];
-  s = block_sum(s, sh);
-  if (threadIdx.x == 0) {
-    if (op == 0) sc[dst] = s;
-    if (op == 1) sc[dst] = sqrt(s);
-    if (op == 2) sc[S_ALPHA] = sc[S_RR] / s;
-    if (op == 3) {
-      sc[S_BETA] = s / sc[S_RR];
-      sc[S_RR] = s;
-    }
-    if (hist) *hist = op == 1 ? sqrt(s) : s;
-  }
+__global__ __launch_bounds__(64) void k_clear_count(unsigned* count) {
+  if (threadIdx.x <= kGroups)
+    __hip_atomic_store(count + kLine * threadIdx.x, 0u, __ATOMIC_RELAXED,
+                       __HIP_MEMORY_SCOPE_AGENT);
 }
 
-// r = b - Ap ; p = r
+// r = b - Ap ; p = r (and its float32 copy for FP32-storage plans)
 __global__ __launch_bounds__(kWG) void k_cg_init(const double* __restrict__ b,
                                                  const double* __restrict__ Ap,
                                                  double* __restrict__ r, double* __restrict__ p,
-                                                 int64_t n) {
+                                                 float* __restrict__ p32, int64_t n) {
   for (int64_t i = (int64_t)blockIdx.x * kWG + threadIdx.x; i < n;
        i += (int64_t)gridDim.x * kWG) {
     const double v = b[i] - Ap[i];
     r[i] = v;
     p[i] = v;
+    if (p32) p32[i] = (float)v;
   }
 }
 
-// x += alpha p ; r -= alpha Ap ; partials of r.r
+// x += alpha p ; r -= alpha Ap ; r.r, then beta = r.r / rr, rr = r.r
 __global__ __launch_bounds__(kWG) void k_cg_xr(double* __restrict__ x, double* __restrict__ r,
                                                const double* __restrict__ p,
-                                               const double* __restrict__ Ap,
-                                               const double* __restrict__ sc, int64_t n,
-                                               double* __restrict__ partials) {
+                                               const double* __restrict__ Ap, int64_t n,
+                                               double* __restrict__ partials, Finish f) {
   __shared__ double sh[4];
-  const double a = sc[S_ALPHA];
+  const double a = f.sc[S_ALPHA];
   double s = 0.0;
   for (int64_t i = (int64_t)blockIdx.x * kWG + threadIdx.x; i < n; i += (int64_t)kRed * kWG) {
     x[i] = fma(a, p[i], x[i]);
@@ -91,16 +152,20 @@ __global__ __launch_bounds__(kWG) void k_cg_xr(double* __restrict__ x, double* _
     s = fma(ri, ri, s);
   }
   s = block_sum(s, sh);
-  if (threadIdx.x == 0) partials[blockIdx.x] = s;
+  finish_if_last(partials, s, f, sh);
 }
 
-// p = r + beta p
-__global__ __launch_bounds__(kWG) void k_cg_p(double* __restrict__ p, const double* __restrict__ r,
+// p = r + beta p (and its float32 copy for FP32-storage plans)
+__global__ __launch_bounds__(kWG) void k_cg_p(double* __restrict__ p, float* __restrict__ p32,
+                                              const double* __restrict__ r,
                                               const double* __restrict__ sc, int64_t n) {
   const double be = sc[S_BETA];
   for (int64_t i = (int64_t)blockIdx.x * kWG + threadIdx.x; i < n;
-       i += (int64_t)gridDim.x * kWG)
-    p[i] = fma(be, p[i], r[i]);
+       i += (int64_t)gridDim.x * kWG) {
+    const double v = fma(be, p[i], r[i]);
+    p[i] = v;
+    if (p32) p32[i] = (float)v;
+  }
 }
 
 __global__ __launch_bounds__(kWG) void k_to_f32(float* __restrict__ d, const double* __restrict__ s,
@@ -110,12 +175,13 @@ __global__ __launch_bounds__(kWG) void k_to_f32(float* __restrict__ d, const dou
     d[i] = (float)s[i];
 }
 
-// Lanczos: w -= beta_j v_prev (beta from the history array) and partials of w.v
+// Lanczos: w -= beta_j v_prev (beta from the history array), then
+// alpha_j = w.v into the history
 __global__ __launch_bounds__(kWG) void k_lz_a(double* __restrict__ w,
                                               const double* __restrict__ v,
                                               const double* __restrict__ vprev,
                                               const double* __restrict__ beta_j, int64_t n,
-                                              double* __restrict__ partials) {
+                                              double* __restrict__ partials, Finish f) {
   __shared__ double sh[4];
   const double be = *beta_j;
   double s = 0.0;
@@ -125,14 +191,14 @@ __global__ __launch_bounds__(kWG) void k_lz_a(double* __restrict__ w,
     s = fma(wi, v[i], s);
   }
   s = block_sum(s, sh);
-  if (threadIdx.x == 0) partials[blockIdx.x] = s;
+  finish_if_last(partials, s, f, sh);
 }
 
-// w -= alpha_j v and partials of w.w
+// w -= alpha_j v, then beta_{j+1} = ||w|| into the history
 __global__ __launch_bounds__(kWG) void k_lz_b(double* __restrict__ w,
                                               const double* __restrict__ v,
                                               const double* __restrict__ alpha_j, int64_t n,
-                                              double* __restrict__ partials) {
+                                              double* __restrict__ partials, Finish f) {
   __shared__ double sh[4];
   const double al = *alpha_j;
   double s = 0.0;
@@ -142,17 +208,21 @@ __global__ __launch_bounds__(kWG) void k_lz_b(double* __restrict__ w,
     s = fma(wi, wi, s);
   }
   s = block_sum(s, sh);
-  if (threadIdx.x == 0) partials[blockIdx.x] = s;
+  finish_if_last(partials, s, f, sh);
 }
 
-// v_out = w / beta (beta = norm stored at *beta_next)
-__global__ __launch_bounds__(kWG) void k_scale(double* __restrict__ out,
+// v_out = w / beta (beta = norm stored at *beta_next), with its float32 copy
+// for FP32-storage plans
+__global__ __launch_bounds__(kWG) void k_scale(double* __restrict__ out, float* __restrict__ out32,
                                                const double* __restrict__ in,
                                                const double* __restrict__ denom, int64_t n) {
   const double d = *denom;
   for (int64_t i = (int64_t)blockIdx.x * kWG + threadIdx.x; i < n;
-       i += (int64_t)gridDim.x * kWG)
-    out[i] = in[i] / d;
+       i += (int64_t)gridDim.x * kWG) {
+    const double v = in[i] / d;
+    out[i] = v;
+    if (out32) out32[i] = (float)v;
+  }
 }
 
 unsigned vgrid(int64_t n) {
@@ -161,6 +231,7 @@ unsigned vgrid(int64_t n) {
 
 struct SolverWs {
   double* sc;
+  unsigned* count;  // the reductions' arrival counters, in the scalar block
   double* partials;
   double* r;
   double* p;
@@ -170,7 +241,7 @@ struct SolverWs {
 
 size_t solver_ws_bytes(int64_t n, int64_t hist) {
   const size_t n1 = (size_t)std::max<int64_t>(n, 1);
-  return align256(sizeof(double) * 64) + align256(sizeof(double) * kRed) +
+  return kScBlock + align256(sizeof(double) * kRed) +
          3 * align256(sizeof(double) * n1) + align256(sizeof(float) * n1) +
          align256(sizeof(double) * (size_t)std::max<int64_t>(hist, 1));
 }
@@ -180,7 +251,8 @@ SolverWs carve(void* ws, int64_t n) {
   const size_t n1 = (size_t)std::max<int64_t>(n, 1);
   SolverWs w;
   w.sc = reinterpret_cast<double*>(c);
-  c += align256(sizeof(double) * 64);
+  w.count = reinterpret_cast<unsigned*>(c + sizeof(double) * 64);
+  c += kScBlock;
   w.partials = reinterpret_cast<double*>(c);
   c += align256(sizeof(double) * kRed);
   w.r = reinterpret_cast<double*>(c);
@@ -196,7 +268,7 @@ SolverWs carve(void* ws, int64_t n) {
 double* history(void* ws, int64_t n) {
   char* c = static_cast<char*>(ws);
   const size_t n1 = (size_t)std::max<int64_t>(n, 1);
-  return reinterpret_cast<double*>(c + align256(sizeof(double) * 64) +
+  return reinterpret_cast<double*>(c + kScBlock +
                                    align256(sizeof(double) * kRed) +
                                    3 * align256(sizeof(double) * n1) +
                                    align256(sizeof(float) * n1));
@@ -210,11 +282,20 @@ int plan_apply(const Plan& p, const double* x, float* x32, double* y, hipStream_
   return launch_spmv(p, p.variant, x32, y, s);
 }
 
+// y = A x where x already has its float32 copy x32 for FP32 plans
+int plan_apply_cast(const Plan& p, const double* x, const float* x32, double* y,
+                    hipStream_t s) {
+  if (p.vdt == SPMV_F64) return launch_spmv(p, p.variant, x, y, s);
+  return launch_spmv(p, p.variant, x32, y, s);
+}
+
+Finish fin(const SolverWs& w, int op, int dst, double* hist) {
+  return Finish{w.sc, w.count, hist, op, dst};
+}
+
 int dot(const double* x, const double* y, int64_t n, SolverWs& w, int op, int dst,
         double* hist, hipStream_t s) {
-  k_dot<<<kRed, kWG, 0, s>>>(x, y, n, w.partials);
-  SPMV_HIP(hipGetLastError());
-  k_finish<<<1, kWG, 0, s>>>(w.partials, w.sc, op, dst, hist);
+  k_dot<<<kRed, kWG, 0, s>>>(x, y, n, w.partials, fin(w, op, dst, hist));
   SPMV_HIP(hipGetLastError());
   return SPMV_OK;
 }
@@ -222,14 +303,12 @@ int dot(const double* x, const double* y, int64_t n, SolverWs& w, int op, int ds
 // one CG iteration: Ap = A p; alpha = rr/(p.Ap); x += alpha p; r -= alpha Ap;
 // beta = r.r/rr; rr = r.r; p = r + beta p
 int cg_iteration(const Plan& P, double* x, SolverWs& w, int64_t n, hipStream_t s) {
-  int st = plan_apply(P, w.p, w.p32, w.Ap, s);
+  int st = plan_apply_cast(P, w.p, w.p32, w.Ap, s);
   if (!st) st = dot(w.p, w.Ap, n, w, 2, 0, nullptr, s);
   if (st) return st;
-  k_cg_xr<<<kRed, kWG, 0, s>>>(x, w.r, w.p, w.Ap, w.sc, n, w.partials);
+  k_cg_xr<<<kRed, kWG, 0, s>>>(x, w.r, w.p, w.Ap, n, w.partials, fin(w, 3, 0, nullptr));
   SPMV_HIP(hipGetLastError());
-  k_finish<<<1, kWG, 0, s>>>(w.partials, w.sc, 3, 0, nullptr);
-  SPMV_HIP(hipGetLastError());
-  k_cg_p<<<vgrid(n), kWG, 0, s>>>(w.p, w.r, w.sc, n);
+  k_cg_p<<<vgrid(n), kWG, 0, s>>>(w.p, P.vdt == SPMV_F64 ? nullptr : w.p32, w.r, w.sc, n);
   SPMV_HIP(hipGetLastError());
   return SPMV_OK;
 }
@@ -247,11 +326,13 @@ int run_cg(const Plan& P, const double* b, double* x, double tol, int maxit, int
            bool use_graph, void* ws, int* iters, double* relres, hipStream_t s) {
   const int64_t n = P.n_rows;
   SolverWs w = carve(ws, n);
+  k_clear_count<<<1, 64, 0, s>>>(w.count);
+  SPMV_HIP(hipGetLastError());
   // ||b||^2 and the initial residual
   int st = dot(b, b, n, w, 0, S_BB, nullptr, s);
   if (!st) st = plan_apply(P, x, w.p32, w.Ap, s);
   if (st) return st;
-  k_cg_init<<<vgrid(n), kWG, 0, s>>>(b, w.Ap, w.r, w.p, n);
+  k_cg_init<<<vgrid(n), kWG, 0, s>>>(b, w.Ap, w.r, w.p, P.vdt == SPMV_F64 ? nullptr : w.p32, n);
   SPMV_HIP(hipGetLastError());
   st = dot(w.r, w.r, n, w, 0, S_RR, nullptr, s);
   if (st) return st;
@@ -323,28 +404,29 @@ int run_lanczos(const Plan& P, const double* v0, int k, double* alpha, double* b
   double* V[3] = {reinterpret_cast<double*>(vec), reinterpret_cast<double*>(vec + vb),
                   reinterpret_cast<double*>(vec + 2 * vb)};
   double* wv = w.Ap;
+  float* v32 = P.vdt == SPMV_F64 ? nullptr : w.p32;  // float32 copy of the current vector
+  k_clear_count<<<1, 64, 0, s>>>(w.count);
+  SPMV_HIP(hipGetLastError());
   // beta_0 = 0, v_prev = 0, v = v0 / ||v0||
   int st = dot(v0, v0, n, w, 1, S_TMP, hb, s);
   if (st) return st;
-  k_scale<<<vgrid(n), kWG, 0, s>>>(V[1], v0, hb, n);
+  k_scale<<<vgrid(n), kWG, 0, s>>>(V[1], v32, v0, hb, n);
   SPMV_HIP(hipGetLastError());
-  k_scale<<<vgrid(n), kWG, 0, s>>>(V[0], v0, hb, n);  // any finite vector; scaled by beta_0 = 0
+  // any finite vector; it is scaled by beta_0 = 0
+  k_scale<<<vgrid(n), kWG, 0, s>>>(V[0], nullptr, v0, hb, n);
   SPMV_HIP(hipGetLastError());
   static const double zero = 0.0;
   SPMV_HIP(hipMemcpyAsync(hb, &zero, sizeof(double), hipMemcpyHostToDevice, s));
   int prev = 0, cur = 1, nxt = 2;
   for (int j = 0; j < k; ++j) {
-    st = plan_apply(P, V[cur], w.p32, wv, s);
+    st = plan_apply_cast(P, V[cur], v32, wv, s);
     if (st) return st;
-    k_lz_a<<<kRed, kWG, 0, s>>>(wv, V[cur], V[prev], hb + j, n, w.partials);
+    k_lz_a<<<kRed, kWG, 0, s>>>(wv, V[cur], V[prev], hb + j, n, w.partials,
+                                fin(w, 0, S_TMP, ha + j));
     SPMV_HIP(hipGetLastError());
-    k_finish<<<1, kWG, 0, s>>>(w.partials, w.sc, 0, S_TMP, ha + j);
+    k_lz_b<<<kRed, kWG, 0, s>>>(wv, V[cur], ha + j, n, w.partials, fin(w, 1, S_TMP, hb + j + 1));
     SPMV_HIP(hipGetLastError());
-    k_lz_b<<<kRed, kWG, 0, s>>>(wv, V[cur], ha + j, n, w.partials);
-    SPMV_HIP(hipGetLastError());
-    k_finish<<<1, kWG, 0, s>>>(w.partials, w.sc, 1, S_TMP, hb + j + 1);
-    SPMV_HIP(hipGetLastError());
-    k_scale<<<vgrid(n), kWG, 0, s>>>(V[nxt], wv, hb + j + 1, n);
+    k_scale<<<vgrid(n), kWG, 0, s>>>(V[nxt], v32, wv, hb + j + 1, n);
     SPMV_HIP(hipGetLastError());
     const int t = prev;
     prev = cur;

@@ -114,3 +114,54 @@ def test_lanczos_extreme_eigenvalues(dt):
     tol = 1e-10 if dt == "f64" else 1e-5
     assert abs(th[-1] - (4 + 4 * c)) <= tol
     assert abs(th[0] - (4 - 4 * c)) <= tol
+
+
+def _cpu_cg(A, b, iters):
+    """Textbook CG in float64 with the oracle's product (no stopping test)."""
+    x = np.zeros_like(b)
+    r = b.copy()
+    p = r.copy()
+    rr = r @ r
+    for _ in range(iters):
+        Ap, _ = oracle.spmv(A.n_rows, A.row_ptr, A.col_idx, A.val, p)
+        a = rr / (p @ Ap)
+        x += a * p
+        r -= a * Ap
+        rr, rr_old = r @ r, rr
+        p = r + (rr / rr_old) * p
+    return x, math.sqrt(rr) / np.linalg.norm(b)
+
+
+@pytest.mark.parametrize("graph", [False, True])
+def test_cg_fixed_iterations_match_cpu_cg(lap128, graph):
+    """Each iteration's scalars come from the fused reductions (the last
+    workgroup sums the partials); 25 iterations against a CPU CG pin every
+    alpha and beta along the way."""
+    A, xs, b = lap128
+    M = pkg.CRSMatrix.from_crs(A, flags=pkg.SPMV_FLAG_VARIANT(4), device=DEV)
+    for rep in range(2):  # the counter must be back at zero for a second solve
+        x, it, rr = _cg(M, b, 0.0, maxit=25, graph=graph, check_every=5)
+        xr, rr_ref = _cpu_cg(A, b, 25)
+        assert it == 25
+        assert np.linalg.norm(x - xr) <= 1e-11 * np.linalg.norm(xr)
+        assert abs(rr - rr_ref) <= 1e-9 * rr_ref
+
+
+def test_lanczos_first_steps_match_cpu():
+    m, k = 48, 12
+    A = crsgen.laplace2d(m)
+    M = pkg.CRSMatrix.from_crs(A, device=DEV)
+    v0 = crsgen.uniform_vec(A.n_rows, 9)
+    nb = pkg.spmv_lanczos_workspace_size(A.n_rows, k)
+    ws = torch.empty(nb, dtype=torch.uint8, device=DEV)
+    al, be = pkg.spmv_lanczos(M.handle, torch.from_numpy(v0).to(DEV), k, ws, nb)
+    v, vp, bprev = v0 / np.linalg.norm(v0), np.zeros_like(v0), 0.0
+    for j in range(k):
+        w, _ = oracle.spmv(A.n_rows, A.row_ptr, A.col_idx, A.val, v)
+        w = w - bprev * vp
+        a = w @ v
+        w = w - a * v
+        bn = np.linalg.norm(w)
+        assert abs(al[j] - a) <= 1e-12 * 8
+        assert abs(be[j] - bn) <= 1e-12 * 8
+        v, vp, bprev = w / bn, v, bn
