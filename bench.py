@@ -25,7 +25,7 @@ METRIC = "CRS spMVM GFlop/s and effective HBM GB/s (% roofline) at 1 MI355X, FP6
 HBM_PEAK = 8000.0  # GB/s, MI355X nominal
 KERNEL_NAMES = {"V4_lds_block": "k_lds_block<double,double>",
                 "V4_lds_block_staged": "k_lds_block_staged<double,double>",
-                "V6_sell64": "k_sell_pairs<double,double>"}
+                "V6_sell64": "k_sell_pairs"}
 SELL = 0  # plan flag requesting the V6 chunked copy; set in main()
 
 

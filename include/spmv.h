@@ -88,8 +88,12 @@ typedef enum {
 #define SPMV_FLAG_SKIP_VALIDATE 0x10000u /* trust the CRS arrays (no device check) */
 /* Reserve workspace for the V6 copy and build it at create. The copy holds
  * 64 * (sum over chunks of the longest row in the chunk) slots of 4-byte
- * column index + value; the reserve is 1.5 nnz + 4096 slots (rounded up to
- * 64) at 12 bytes each whatever val_dtype is. A pattern whose padded size
+ * column index + value, plus a 2-byte column delta per slot and a 4-byte base
+ * per 64 slots; the reserve is 1.5 nnz + 4096 slots (rounded up to 64) at 14
+ * bytes each whatever val_dtype is, plus the bases. A chunk whose every slot
+ * has its 64 columns within 65535 of each other is read through the deltas
+ * (10 instead of 12 bytes per float64 slot); other chunks read the 4-byte
+ * columns. Both give the same products in the same order. A pattern whose padded size
  * exceeds it still gets a plan, without V6 (spmv_get_sell_slots reports
  * SPMV_ERR_STATE); asking for V6 by name then fails with UNSUPPORTED. The
  * selector ranks V0..V5 only: with SPMV_SELECT_DEFAULT or SPMV_SELECT_MLP and
@@ -104,6 +108,10 @@ typedef enum {
  * these flags force one form (setting both is SPMV_ERR_INVALID_ARG). */
 #define SPMV_FLAG_V4_STAGE_ON 0x40000u
 #define SPMV_FLAG_V4_STAGE_OFF 0x80000u
+/* With SPMV_FLAG_SELL: read every chunk of the V6 copy through its 4-byte
+ * columns (the deltas are not built). Without SPMV_FLAG_SELL it is
+ * SPMV_ERR_INVALID_ARG. */
+#define SPMV_FLAG_SELL_WIDE 0x100000u
 
 #define SPMV_NUM_FEATURES 16
 #define SPMV_MLP_PARAMS 5638 /* 16->64->64->6: W1 b1 W2 b2 W3 b3, [out,in] row-major */
@@ -175,6 +183,11 @@ int spmv_get_autotune_times(spmv_handle h, double* us);
 /* Slots of the V6 copy (host out): 64 * sum of chunk widths, >= nnz; the
  * padding is slots - nnz. SPMV_ERR_STATE if the plan has no V6 copy. */
 int spmv_get_sell_slots(spmv_handle h, int64_t* slots);
+/* Chunks of the V6 copy read through 16-bit column deltas, and all chunks
+ * (host out). Copies the per-chunk flags to the host (a blocking copy after
+ * the device work of create, which has completed when create returns).
+ * SPMV_ERR_STATE if the plan has no V6 copy. */
+int spmv_get_sell_narrow(spmv_handle h, int64_t* narrow_chunks, int64_t* chunks);
 /* Whether V4 runs in its B-staging form (host out: 1 or 0; see
  * SPMV_FLAG_V4_STAGE_ON). */
 int spmv_get_v4_staged(spmv_handle h, int* staged);

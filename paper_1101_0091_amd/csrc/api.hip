@@ -31,6 +31,7 @@ bool dtype_ok(int dt) { return dt == SPMV_F64 || dt == SPMV_F32; }
 struct PlanLayout {
   size_t header = 0, blocks = 0, spans = 0, bins = 0, stats = 0, bin_base = 0, at_B = 0, at_C = 0;
   size_t sell_width = 0, sell_off = 0, sell_partials = 0, sell_ci = 0, sell_val = 0;
+  size_t sell_base = 0, sell_dl = 0, sell_flag = 0;
   size_t total = 0;
 };
 
@@ -71,6 +72,12 @@ PlanLayout plan_layout(int64_t n_rows, int64_t n_cols, int64_t nnz, uint32_t fla
     o += align256(4 * (size_t)cap);
     L.sell_val = o;
     o += align256(8 * (size_t)cap);
+    L.sell_base = o;
+    o += align256(4 * (size_t)(cap / 64));
+    L.sell_dl = o;
+    o += align256(2 * (size_t)cap);
+    L.sell_flag = o;
+    o += align256(4 * (size_t)std::max<int64_t>(nch, 1));
   }
   L.total = o;
   return L;
@@ -272,8 +279,10 @@ int plan_build(Plan& p, int64_t n_rows, int64_t n_cols, int64_t nnz, const int32
   if (mode == SPMV_SELECT_FIXED && fixed >= SPMV_NUM_VARIANTS)
     return fail(SPMV_ERR_INVALID_ARG, "variant out of range");
   if (flags & ~(0xFFFu | SPMV_FLAG_SKIP_VALIDATE | SPMV_FLAG_SELL | SPMV_FLAG_V4_STAGE_ON |
-                SPMV_FLAG_V4_STAGE_OFF))
+                SPMV_FLAG_V4_STAGE_OFF | SPMV_FLAG_SELL_WIDE))
     return fail(SPMV_ERR_INVALID_ARG, "unknown flag bits");
+  if ((flags & SPMV_FLAG_SELL_WIDE) && !(flags & SPMV_FLAG_SELL))
+    return fail(SPMV_ERR_INVALID_ARG, "SPMV_FLAG_SELL_WIDE needs SPMV_FLAG_SELL");
   if ((flags & SPMV_FLAG_V4_STAGE_ON) && (flags & SPMV_FLAG_V4_STAGE_OFF))
     return fail(SPMV_ERR_INVALID_ARG, "SPMV_FLAG_V4_STAGE_ON and _OFF together");
   if (mode == SPMV_SELECT_FIXED && fixed == SPMV_V6_SELL64 && !(flags & SPMV_FLAG_SELL))
@@ -314,6 +323,10 @@ int plan_build(Plan& p, int64_t n_rows, int64_t n_cols, int64_t nnz, const int32
     p.sell_partials = reinterpret_cast<int32_t*>(p.ws + L.sell_partials);
     p.sell_ci = reinterpret_cast<int32_t*>(p.ws + L.sell_ci);
     p.sell_val = p.ws + L.sell_val;
+    p.sell_base = reinterpret_cast<int32_t*>(p.ws + L.sell_base);
+    p.sell_dl = reinterpret_cast<uint16_t*>(p.ws + L.sell_dl);
+    p.sell_flag = reinterpret_cast<int32_t*>(p.ws + L.sell_flag);
+    p.sell_wide = (flags & SPMV_FLAG_SELL_WIDE) != 0;
   }
   hipGetDevice(&p.device);
 
@@ -471,6 +484,22 @@ int spmv_get_sell_slots(spmv_handle h, int64_t* slots) {
   if (!h || !slots) return fail(SPMV_ERR_INVALID_ARG, "null argument");
   if (!h->p.sell_ok) return fail(SPMV_ERR_STATE, "this plan has no V6 copy");
   *slots = h->p.sell_slots;
+  return SPMV_OK;
+}
+
+int spmv_get_sell_narrow(spmv_handle h, int64_t* narrow_chunks, int64_t* chunks) {
+  if (!h || !narrow_chunks || !chunks) return fail(SPMV_ERR_INVALID_ARG, "null argument");
+  if (!h->p.sell_ok) return fail(SPMV_ERR_STATE, "this plan has no V6 copy");
+  const int64_t nch = h->p.sell_nch;
+  int64_t narrow = 0;
+  if (nch > 0 && !h->p.sell_wide) {
+    std::vector<int32_t> f((size_t)nch);
+    SPMV_HIP(hipMemcpy(f.data(), h->p.sell_flag, sizeof(int32_t) * (size_t)nch,
+                       hipMemcpyDeviceToHost));
+    for (int32_t x : f) narrow += x != 0;
+  }
+  *narrow_chunks = narrow;
+  *chunks = nch;
   return SPMV_OK;
 }
 

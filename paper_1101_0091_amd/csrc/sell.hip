@@ -12,10 +12,19 @@
 // access per wavefront, no LDS or barrier is needed, and each row is summed by
 // one lane.
 //
-// The copy is built on the device at plan creation in three passes: chunk
-// widths, an exclusive scan of the widths, and the fill. Its capacity is
-// reserved in the plan workspace; a pattern whose padded size does not fit
-// is reported back and V6 is then unavailable for that plan.
+// Column deltas: within a chunk, slot j of the 64 rows often points at 64
+// nearby columns (a band, a diagonal, a stencil). Each slot j then gets a
+// 4-byte base (the smallest of its columns) and every entry a 2-byte delta
+// from it (0xFFFF for padding). A chunk whose every slot spans at most 0xFFFE
+// columns is read through the deltas, 10 instead of 12 bytes per float64 slot
+// (6 instead of 8 for float32); other chunks read the 4-byte columns. The
+// column, and hence every product and the order of the sum, is the same
+// either way.
+//
+// The copy is built on the device at plan creation in four passes: chunk
+// widths, an exclusive scan of the widths, the fill, and the deltas. Its
+// capacity is reserved in the plan workspace; a pattern whose padded size
+// does not fit is reported back and V6 is then unavailable for that plan.
 #include <type_traits>
 
 #include "common.hpp"
@@ -31,6 +40,9 @@ typedef double f64x2 __attribute__((ext_vector_type(2)));
 typedef int32_t i32x2 __attribute__((ext_vector_type(2)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 typedef int32_t i32x4 __attribute__((ext_vector_type(4)));
+typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
+
+constexpr uint32_t kPadDelta = 0xFFFFu;  // delta of a padding slot
 
 // Slots per lane-interleaved group for a value type (see the layout above).
 template <typename VT> constexpr int kGroup = sizeof(VT) == 8 ? 2 : 4;
@@ -116,26 +128,69 @@ __global__ __launch_bounds__(kWG) void k_sell_fill(
   }
 }
 
+// Column deltas of the filled copy (one wavefront per chunk): for each slot j
+// the smallest column over the chunk's rows becomes base[off + j], every entry
+// stores its column minus that base (kPadDelta for padding), and flag[k] = 1
+// when every slot of chunk k spans at most kPadDelta - 1 columns (the deltas
+// of a chunk with flag 0 are never read). Nothing is written unless the copy
+// fit its reserve.
+template <int G>
+__global__ __launch_bounds__(kWG) void k_sell_narrow(int64_t nch, const int32_t* __restrict__ off,
+                                                     int64_t cap64,
+                                                     const int32_t* __restrict__ sci,
+                                                     int32_t* __restrict__ sbase,
+                                                     uint16_t* __restrict__ sdl,
+                                                     int32_t* __restrict__ flag) {
+  const int64_t total = off[nch];
+  const int64_t chunk = ((int64_t)blockIdx.x * kWG + threadIdx.x) / kChunk;
+  if (chunk >= nch || total < 0 || total > cap64) return;
+  const int64_t a = off[chunk], b = off[chunk + 1];
+  if (a < 0 || b < a || b > total) return;
+  const int lane = threadIdx.x % kChunk;
+  const int64_t w = b - a;
+  bool ok = true;
+  for (int64_t j = 0; j < w; ++j) {
+    const int64_t o = a * kChunk + slot_offset<G>(j, lane, w);
+    const int32_t c = sci[o];
+    int32_t mn = c >= 0 ? c : INT32_MAX, mx = c;  // padding: c = -1
+    for (int m = 32; m >= 1; m >>= 1) {
+      const int32_t x = __shfl_xor(mn, m), y = __shfl_xor(mx, m);
+      mn = x < mn ? x : mn;
+      mx = y > mx ? y : mx;
+    }
+    // slot j < w of the chunk's longest row is a real entry, so mn <= mx
+    ok = ok && (int64_t)mx - (int64_t)mn < (int64_t)kPadDelta;
+    if (lane == 0) sbase[a + j] = mn;
+    sdl[o] = c >= 0 ? (uint16_t)(uint32_t)(c - mn) : (uint16_t)kPadDelta;
+  }
+  if (lane == 0) flag[chunk] = ok ? 1 : 0;
+}
+
+// Column of a slot read through its delta (-1 for padding).
+__device__ __forceinline__ int32_t delta_col(uint32_t d, int32_t base) {
+  return d != kPadDelta ? base + (int32_t)d : -1;
+}
+
 // C = A*B from the chunked copy with float64 values: lane l of the wavefront
 // of chunk k owns row 64 k + l and sums its slots in order, kSellUP pairs per
 // round, the odd last slot after the rounds. The width is uniform over the
 // wavefront, so the loop and its masked last round are uniform branches.
-__global__ __launch_bounds__(kWG) void k_sell_pairs(int64_t nch, int64_t n,
-                                                    const int32_t* __restrict__ off,
-                                                    const int32_t* __restrict__ sci,
-                                                    const double* __restrict__ sval,
-                                                    const double* __restrict__ B,
-                                                    double* __restrict__ C) {
+// NARROW reads the columns as base + 16-bit delta (a pair of deltas per
+// 4-byte load, the bases as wavefront-uniform loads).
+template <bool NARROW>
+__device__ __forceinline__ double sell_pairs_row(int64_t a, int32_t w, int lane,
+                                                 const int32_t* __restrict__ sci,
+                                                 const uint16_t* __restrict__ sdl,
+                                                 const int32_t* __restrict__ sbase,
+                                                 const double* __restrict__ sval,
+                                                 const double* __restrict__ B) {
   using VT = double;
   using V2 = f64x2;
-  const int64_t chunk = ((int64_t)blockIdx.x * kWG + threadIdx.x) / kChunk;
-  if (chunk >= nch) return;
-  const int lane = threadIdx.x % kChunk;
-  const int64_t a = off[chunk];
-  const int32_t w = (int32_t)(off[chunk + 1] - a);
   const int32_t P = w >> 1;
   const V2* vp = reinterpret_cast<const V2*>(sval + a * kChunk) + lane;
   const i32x2* cp = reinterpret_cast<const i32x2*>(sci + a * kChunk) + lane;
+  const uint32_t* dp = reinterpret_cast<const uint32_t*>(sdl + a * kChunk) + lane;
+  const int32_t* bp = sbase + a;
   double acc = 0.0;
   // padded and masked slots contribute fma(0, 0, acc) = acc exactly: acc
   // starts at +0, and a round-to-nearest sum with a +0 operand is never -0,
@@ -144,14 +199,35 @@ __global__ __launch_bounds__(kWG) void k_sell_pairs(int64_t nch, int64_t n,
     V2 v[kSellUP];
     i32x2 c[kSellUP];
     double x0[kSellUP], x1[kSellUP];
+    if constexpr (NARROW) {
+      // every load of the round is issued before any delta is decoded
+      uint32_t d[kSellUP];
+      i32x2 b[kSellUP];
 #pragma unroll
-    for (int u = 0; u < kSellUP; ++u) {
-      if (p + u < P) {
-        v[u] = dev::ld_stream(vp + (int64_t)(p + u) * kChunk);
-        c[u] = dev::ld_stream(cp + (int64_t)(p + u) * kChunk);
-      } else {
-        v[u] = V2{(VT)0, (VT)0};
-        c[u] = i32x2{-1, -1};
+      for (int u = 0; u < kSellUP; ++u) {
+        if (p + u < P) {
+          v[u] = dev::ld_stream(vp + (int64_t)(p + u) * kChunk);
+          d[u] = dev::ld_stream(dp + (int64_t)(p + u) * kChunk);
+          b[u] = *reinterpret_cast<const i32x2*>(bp + 2 * (p + u));
+        } else {
+          v[u] = V2{(VT)0, (VT)0};
+          d[u] = 0xFFFFFFFFu;
+          b[u] = i32x2{0, 0};
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < kSellUP; ++u)
+        c[u] = i32x2{delta_col(d[u] & 0xFFFFu, b[u].x), delta_col(d[u] >> 16, b[u].y)};
+    } else {
+#pragma unroll
+      for (int u = 0; u < kSellUP; ++u) {
+        if (p + u < P) {
+          v[u] = dev::ld_stream(vp + (int64_t)(p + u) * kChunk);
+          c[u] = dev::ld_stream(cp + (int64_t)(p + u) * kChunk);
+        } else {
+          v[u] = V2{(VT)0, (VT)0};
+          c[u] = i32x2{-1, -1};
+        }
       }
     }
 #pragma unroll
@@ -167,9 +243,40 @@ __global__ __launch_bounds__(kWG) void k_sell_pairs(int64_t nch, int64_t n,
   }
   if (w & 1) {
     const int64_t o = a * kChunk + 2 * (int64_t)P * kChunk + lane;
-    const int32_t c = dev::ld_stream(sci + o);
+    int32_t c;
+    if constexpr (NARROW)
+      c = delta_col(dev::ld_stream(sdl + o), bp[2 * P]);
+    else
+      c = dev::ld_stream(sci + o);
     if (c >= 0) acc = fma(dev::widen(dev::ld_stream(sval + o)), (double)B[c], acc);
   }
+  return acc;
+}
+
+// Wavefront-uniform chunk index (one chunk per wavefront).
+__device__ __forceinline__ int64_t chunk_of_wave() {
+  return __builtin_amdgcn_readfirstlane((int32_t)(((int64_t)blockIdx.x * kWG + threadIdx.x) /
+                                                  kChunk));
+}
+
+// flag is null when the plan keeps 4-byte columns only.
+__global__ __launch_bounds__(kWG) void k_sell_pairs(int64_t nch, int64_t n,
+                                                    const int32_t* __restrict__ off,
+                                                    const int32_t* __restrict__ sci,
+                                                    const int32_t* __restrict__ flag,
+                                                    const int32_t* __restrict__ sbase,
+                                                    const uint16_t* __restrict__ sdl,
+                                                    const double* __restrict__ sval,
+                                                    const double* __restrict__ B,
+                                                    double* __restrict__ C) {
+  const int64_t chunk = chunk_of_wave();
+  if (chunk >= nch) return;
+  const int lane = threadIdx.x % kChunk;
+  const int64_t a = off[chunk];
+  const int32_t w = (int32_t)(off[chunk + 1] - a);
+  const double acc = flag && flag[chunk]
+                         ? sell_pairs_row<true>(a, w, lane, sci, sdl, sbase, sval, B)
+                         : sell_pairs_row<false>(a, w, lane, sci, sdl, sbase, sval, B);
   const int64_t row = chunk * kChunk + lane;
   if (row < n) C[row] = acc;
 }
@@ -178,32 +285,40 @@ __global__ __launch_bounds__(kWG) void k_sell_pairs(int64_t nch, int64_t n,
 // three tail slots are loaded before the first round and summed in it.
 constexpr int kSellUQ = 2;
 
-template <typename BT>
-__global__ __launch_bounds__(kWG) void k_sell_quads(int64_t nch, int64_t n,
-                                                    const int32_t* __restrict__ off,
-                                                    const int32_t* __restrict__ sci,
-                                                    const float* __restrict__ sval,
-                                                    const BT* __restrict__ B,
-                                                    double* __restrict__ C) {
-  const int64_t chunk = ((int64_t)blockIdx.x * kWG + threadIdx.x) / kChunk;
-  if (chunk >= nch) return;
-  const int lane = threadIdx.x % kChunk;
-  const int64_t a = off[chunk];
-  const int32_t w = (int32_t)(off[chunk + 1] - a);
+// NARROW reads the columns as base + 16-bit delta (four deltas per 8-byte
+// load).
+template <bool NARROW, typename BT>
+__device__ __forceinline__ double sell_quads_row(int64_t a, int32_t w, int lane,
+                                                 const int32_t* __restrict__ sci,
+                                                 const uint16_t* __restrict__ sdl,
+                                                 const int32_t* __restrict__ sbase,
+                                                 const float* __restrict__ sval,
+                                                 const BT* __restrict__ B) {
   const int32_t Q = w >> 2, T = w & 3;
   const f32x4* vp = reinterpret_cast<const f32x4*>(sval + a * kChunk) + lane;
   const i32x4* cp = reinterpret_cast<const i32x4*>(sci + a * kChunk) + lane;
+  const u32x2* dp = reinterpret_cast<const u32x2*>(sdl + a * kChunk) + lane;
+  const int32_t* bp = sbase + a;
+  // tail slots: raw column words now, decoded at their gather in the first
+  // round, so no tail load is waited for before the round's loads are issued
   float tv[3];
-  int32_t tc[3];
+  uint32_t tr[3];
+  int32_t tb[3];
 #pragma unroll
   for (int t = 0; t < 3; ++t) {
+    tb[t] = 0;
     if (t < T) {
       const int64_t o = a * kChunk + 4 * (int64_t)Q * kChunk + t * kChunk + lane;
       tv[t] = dev::ld_stream(sval + o);
-      tc[t] = dev::ld_stream(sci + o);
+      if constexpr (NARROW) {
+        tr[t] = dev::ld_stream(sdl + o);
+        tb[t] = bp[4 * Q + t];
+      } else {
+        tr[t] = (uint32_t)dev::ld_stream(sci + o);
+      }
     } else {
       tv[t] = 0.0f;
-      tc[t] = -1;
+      tr[t] = NARROW ? kPadDelta : 0xFFFFFFFFu;
     }
   }
   double acc = 0.0;
@@ -213,41 +328,97 @@ __global__ __launch_bounds__(kWG) void k_sell_quads(int64_t nch, int64_t n,
   do {
     f32x4 v[kSellUQ];
     i32x4 c[kSellUQ];
+    if constexpr (NARROW) {
+      // every load of the round is issued before any delta is decoded
+      u32x2 d[kSellUQ];
+      i32x4 b[kSellUQ];
 #pragma unroll
-    for (int u = 0; u < kSellUQ; ++u) {
-      if (q + u < Q) {
-        v[u] = dev::ld_stream(vp + (int64_t)(q + u) * kChunk);
-        c[u] = dev::ld_stream(cp + (int64_t)(q + u) * kChunk);
-      } else {
-        v[u] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
-        c[u] = i32x4{-1, -1, -1, -1};
+      for (int u = 0; u < kSellUQ; ++u) {
+        if (q + u < Q) {
+          v[u] = dev::ld_stream(vp + (int64_t)(q + u) * kChunk);
+          d[u] = dev::ld_stream(dp + (int64_t)(q + u) * kChunk);
+          b[u] = *reinterpret_cast<const i32x4*>(bp + 4 * (q + u));
+        } else {
+          v[u] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+          d[u] = u32x2{0xFFFFFFFFu, 0xFFFFFFFFu};
+          b[u] = i32x4{0, 0, 0, 0};
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < kSellUQ; ++u)
+        c[u] = i32x4{delta_col(d[u].x & 0xFFFFu, b[u].x), delta_col(d[u].x >> 16, b[u].y),
+                     delta_col(d[u].y & 0xFFFFu, b[u].z), delta_col(d[u].y >> 16, b[u].w)};
+    } else {
+#pragma unroll
+      for (int u = 0; u < kSellUQ; ++u) {
+        if (q + u < Q) {
+          v[u] = dev::ld_stream(vp + (int64_t)(q + u) * kChunk);
+          c[u] = dev::ld_stream(cp + (int64_t)(q + u) * kChunk);
+        } else {
+          v[u] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+          c[u] = i32x4{-1, -1, -1, -1};
+        }
       }
     }
-    double tx[3];
+    // gathered in B's own type and widened at the multiply, after every
+    // gather of the round is issued (the empty asm keeps the compiler from
+    // moving the widening into the masked gather, where each gather then
+    // waited for its own load)
+    BT tx[3];
 #pragma unroll
-    for (int t = 0; t < 3; ++t) tx[t] = (first && tc[t] >= 0) ? (double)B[tc[t]] : 0.0;
-    double x[kSellUQ][4];
+    for (int t = 0; t < 3; ++t) {
+      const int32_t tc = NARROW ? delta_col(tr[t], tb[t]) : (int32_t)tr[t];
+      tx[t] = (first && tc >= 0) ? B[tc] : (BT)0;
+    }
+    BT x[kSellUQ][4];
 #pragma unroll
     for (int u = 0; u < kSellUQ; ++u) {
-      x[u][0] = c[u].x >= 0 ? (double)B[c[u].x] : 0.0;
-      x[u][1] = c[u].y >= 0 ? (double)B[c[u].y] : 0.0;
-      x[u][2] = c[u].z >= 0 ? (double)B[c[u].z] : 0.0;
-      x[u][3] = c[u].w >= 0 ? (double)B[c[u].w] : 0.0;
+      x[u][0] = c[u].x >= 0 ? B[c[u].x] : (BT)0;
+      x[u][1] = c[u].y >= 0 ? B[c[u].y] : (BT)0;
+      x[u][2] = c[u].z >= 0 ? B[c[u].z] : (BT)0;
+      x[u][3] = c[u].w >= 0 ? B[c[u].w] : (BT)0;
     }
 #pragma unroll
+    for (int t = 0; t < 3; ++t) asm volatile("" : "+v"(tx[t]), "+v"(tv[t]));
+#pragma unroll
+    for (int u = 0; u < kSellUQ; ++u)
+#pragma unroll
+      for (int k = 0; k < 4; ++k) asm volatile("" : "+v"(x[u][k]));
+#pragma unroll
     for (int u = 0; u < kSellUQ; ++u) {
-      acc = fma((double)v[u].x, x[u][0], acc);
-      acc = fma((double)v[u].y, x[u][1], acc);
-      acc = fma((double)v[u].z, x[u][2], acc);
-      acc = fma((double)v[u].w, x[u][3], acc);
+      acc = fma((double)v[u].x, (double)x[u][0], acc);
+      acc = fma((double)v[u].y, (double)x[u][1], acc);
+      acc = fma((double)v[u].z, (double)x[u][2], acc);
+      acc = fma((double)v[u].w, (double)x[u][3], acc);
     }
     if (first) {
 #pragma unroll
-      for (int t = 0; t < 3; ++t) acc = fma((double)tv[t], tx[t], acc);
+      for (int t = 0; t < 3; ++t) acc = fma((double)tv[t], (double)tx[t], acc);
     }
     first = false;
     q += kSellUQ;
   } while (q < Q);
+  return acc;
+}
+
+template <typename BT>
+__global__ __launch_bounds__(kWG) void k_sell_quads(int64_t nch, int64_t n,
+                                                    const int32_t* __restrict__ off,
+                                                    const int32_t* __restrict__ sci,
+                                                    const int32_t* __restrict__ flag,
+                                                    const int32_t* __restrict__ sbase,
+                                                    const uint16_t* __restrict__ sdl,
+                                                    const float* __restrict__ sval,
+                                                    const BT* __restrict__ B,
+                                                    double* __restrict__ C) {
+  const int64_t chunk = chunk_of_wave();
+  if (chunk >= nch) return;
+  const int lane = threadIdx.x % kChunk;
+  const int64_t a = off[chunk];
+  const int32_t w = (int32_t)(off[chunk + 1] - a);
+  const double acc = flag && flag[chunk]
+                         ? sell_quads_row<true, BT>(a, w, lane, sci, sdl, sbase, sval, B)
+                         : sell_quads_row<false, BT>(a, w, lane, sci, sdl, sbase, sval, B);
   const int64_t row = chunk * kChunk + lane;
   if (row < n) C[row] = acc;
 }
@@ -356,6 +527,15 @@ int launch_sell_build(Plan& p, hipStream_t s) {
         p.n_rows, p.nnz, p.row_ptr, p.col_idx, static_cast<const float*>(p.val), nch,
         p.sell_off, cap64, p.sell_ci, static_cast<float*>(p.sell_val), &p.hdr->sell_total);
   SPMV_HIP(hipGetLastError());
+  if (!p.sell_wide) {
+    if (p.vdt == SPMV_F64)
+      k_sell_narrow<kGroup<double>><<<grid_chunks(nch), kWG, 0, s>>>(
+          nch, p.sell_off, cap64, p.sell_ci, p.sell_base, p.sell_dl, p.sell_flag);
+    else
+      k_sell_narrow<kGroup<float>><<<grid_chunks(nch), kWG, 0, s>>>(
+          nch, p.sell_off, cap64, p.sell_ci, p.sell_base, p.sell_dl, p.sell_flag);
+    SPMV_HIP(hipGetLastError());
+  }
   return SPMV_OK;
 }
 
@@ -415,11 +595,13 @@ int launch_sell(const Plan& p, const void* B, double* C, hipStream_t s) {
   if (p.sell_nch == 0) return SPMV_OK;
   if (p.vdt == SPMV_F64)
     k_sell_pairs<<<grid_chunks(p.sell_nch), kWG, 0, s>>>(
-        p.sell_nch, p.n_rows, p.sell_off, p.sell_ci, static_cast<const double*>(p.sell_val),
+        p.sell_nch, p.n_rows, p.sell_off, p.sell_ci, p.sell_wide ? nullptr : p.sell_flag,
+        p.sell_base, p.sell_dl, static_cast<const double*>(p.sell_val),
         static_cast<const double*>(B), C);
   else
     k_sell_quads<float><<<grid_chunks(p.sell_nch), kWG, 0, s>>>(
-        p.sell_nch, p.n_rows, p.sell_off, p.sell_ci, static_cast<const float*>(p.sell_val),
+        p.sell_nch, p.n_rows, p.sell_off, p.sell_ci, p.sell_wide ? nullptr : p.sell_flag,
+        p.sell_base, p.sell_dl, static_cast<const float*>(p.sell_val),
         static_cast<const float*>(B), C);
   SPMV_HIP(hipGetLastError());
   return SPMV_OK;

@@ -38,12 +38,18 @@ def test_workspace_size_is_stable_and_checked():
     assert a == pkg.spmv_workspace_size(6_000_000, 6_000_000, 87_000_000)
     assert pkg.spmv_workspace_size(6_000_000, 6_000_000, 87_000_000, pkg.SPMV_SELECT_AUTOTUNE) > a
     assert pkg.spmv_workspace_size(0, 0, 0) > 0
-    # the V6 reserve: 1.5 nnz + 4096 slots (rounded up to 64) of 4 + 8 bytes
+    # the V6 reserve: 1.5 nnz + 4096 slots (rounded up to 64) of 4 + 8 + 2
+    # bytes, a 4-byte base per 64 slots, and per-chunk widths, offsets and flags
     at = pkg.spmv_workspace_size(6_000_000, 6_000_000, 87_000_000, pkg.SPMV_SELECT_AUTOTUNE)
     s = pkg.spmv_workspace_size(6_000_000, 6_000_000, 87_000_000,
                                 pkg.SPMV_SELECT_AUTOTUNE | pkg.SPMV_FLAG_SELL)
     cap = (87_000_000 + 43_500_000 + 4096 + 63) // 64 * 64
-    assert 12 * cap <= s - at <= 12 * cap + 4 * 6_000_000 // 64 * 3 + 4096
+    lo = 14 * cap + 4 * (cap // 64)
+    assert lo <= s - at <= lo + 4 * 6_000_000 // 64 * 4 + 8192
+    # the flag that keeps 4-byte columns only does not change the reserve
+    assert pkg.spmv_workspace_size(
+        6_000_000, 6_000_000, 87_000_000,
+        pkg.SPMV_SELECT_AUTOTUNE | pkg.SPMV_FLAG_SELL | pkg.SPMV_FLAG_SELL_WIDE) == s
     # a default-mode plan with the copy also reserves the timing scratch of its V6 duel
     assert pkg.spmv_workspace_size(6_000_000, 6_000_000, 87_000_000, pkg.SPMV_FLAG_SELL) == s
     with pytest.raises(pkg.SpmvError) as e:
@@ -75,7 +81,8 @@ def _create(**kw):
     (dict(flags=pkg.SPMV_FLAG_VARIANT(6)), pkg.SPMV_ERR_INVALID_ARG),  # V6 without its flag
     (dict(flags=pkg.SPMV_FLAG_VARIANT(6) | pkg.SPMV_FLAG_SELL, ws_bytes=1 << 12),
      pkg.SPMV_ERR_WORKSPACE),
-    (dict(flags=1 << 20), pkg.SPMV_ERR_INVALID_ARG),
+    (dict(flags=1 << 21), pkg.SPMV_ERR_INVALID_ARG),
+    (dict(flags=pkg.SPMV_FLAG_SELL_WIDE), pkg.SPMV_ERR_INVALID_ARG),  # without SPMV_FLAG_SELL
     (dict(flags=pkg.SPMV_FLAG_V4_STAGE_ON | pkg.SPMV_FLAG_V4_STAGE_OFF), pkg.SPMV_ERR_INVALID_ARG),
     (dict(workspace=None), pkg.SPMV_ERR_WORKSPACE),
     (dict(workspace=0x10010), pkg.SPMV_ERR_WORKSPACE),
@@ -102,6 +109,8 @@ def test_null_handle_calls():
     slots = ctypes.c_int64(-7)
     assert L.spmv_get_sell_slots(None, ctypes.byref(slots)) == pkg.SPMV_ERR_INVALID_ARG
     assert slots.value == -7  # untouched on error
+    assert L.spmv_get_sell_narrow(None, ctypes.byref(slots), ctypes.byref(slots)) == \
+        pkg.SPMV_ERR_INVALID_ARG
     assert L.spmv_set_variant(None, pkg.SPMV_V6_SELL64) == pkg.SPMV_ERR_INVALID_ARG
     times = (ctypes.c_double * pkg.SPMV_NUM_VARIANTS)()
     assert L.spmv_get_autotune_times(None, times) == pkg.SPMV_ERR_INVALID_ARG

@@ -492,6 +492,75 @@ def test_sell_layout_rounds_and_ragged_tail(n, half, jitter, dt):
     assert ok, worst
 
 
+def _span_matrix(spans, n_cols):
+    """One 64-row chunk per entry of `spans`: row l of chunk k has a nonzero
+    in column 1000 k + (l spans[k]) // 63, so slot 0 of chunk k covers exactly
+    spans[k] + 1 columns, and even rows a second one in the next column (odd
+    rows pad slot 1)."""
+    rng = np.random.default_rng(len(spans))
+    cols = []
+    for k, sp in enumerate(spans):
+        for l in range(64):
+            c = 1000 * k + (l * sp) // 63
+            cols.append([c, c + 1] if l % 2 == 0 else [c])
+    lens = np.array([len(c) for c in cols])
+    rp = np.concatenate([[0], np.cumsum(lens)]).astype(np.int32)
+    ci = np.concatenate(cols).astype(np.int32)
+    return crsgen.CRS(len(cols), n_cols, rp, ci, rng.standard_normal(ci.shape[0]))
+
+
+@pytest.mark.parametrize("dt", ["f64", "f32"])
+def test_sell_column_deltas_at_their_limit(dt):
+    """A chunk is read through 16-bit deltas exactly when each of its slots
+    spans at most 0xFFFE columns (0xFFFF marks padding); either way the
+    product is bitwise the one read through the 4-byte columns, and within the
+    bound of the oracle."""
+    spans = [0, 1, 63, 0xFFFE, 0xFFFF, 0x10000, 1_000_000]
+    A = _span_matrix(spans, 2_000_000)
+    B = crsgen.uniform_vec(A.n_cols, 12)
+    tdt = torch.float32 if dt == "f32" else torch.float64
+    val = A.val.astype(np.float32) if dt == "f32" else A.val
+    Bh = B.astype(np.float32) if dt == "f32" else B
+    Cref, S = oracle.spmv(A.n_rows, A.row_ptr, A.col_idx, val, Bh)
+    outs = []
+    for wide, expect in ((False, 4), (True, 0)):
+        fl = pkg.SPMV_FLAG_VARIANT(6) | SELL | (pkg.SPMV_FLAG_SELL_WIDE if wide else 0)
+        M = pkg.CRSMatrix(A.n_rows, A.n_cols, A.row_ptr, A.col_idx, val, val_dtype=tdt,
+                          flags=fl, device=DEV)
+        assert M.sell_narrow == (expect, len(spans))
+        C = M.apply(_gpu(Bh)).cpu().numpy()
+        ok, worst = oracle.bound_ok(C, Cref, A.row_ptr, S)
+        assert ok, (wide, worst)
+        outs.append(C)
+    assert np.array_equal(outs[0], outs[1])
+
+
+@pytest.mark.parametrize("dt", ["f64", "f32"])
+@pytest.mark.parametrize("name", ["hand", "laplace2d_256", "hamiltonian_200k", "banded_40k",
+                                  "nnz0", "rows0"])  # the cases whose copy fits its reserve
+def test_sell_deltas_bitwise_equal_wide(name, dt):
+    """Every case read through the deltas where they fit gives bitwise the
+    product of the copy read through its 4-byte columns."""
+    A, B = case(name)
+    tdt = torch.float32 if dt == "f32" else torch.float64
+    val = A.val.astype(np.float32) if dt == "f32" else A.val
+    Bd = _gpu(B.astype(np.float32) if dt == "f32" else B)
+    outs, narrow = [], []
+    for wide in (False, True):
+        fl = pkg.SPMV_FLAG_VARIANT(4) | SELL | (pkg.SPMV_FLAG_SELL_WIDE if wide else 0)
+        M = pkg.CRSMatrix(A.n_rows, A.n_cols, A.row_ptr, A.col_idx, val, val_dtype=tdt,
+                          flags=fl, device=DEV)
+        M.variant = 6
+        narrow.append(M.sell_narrow)
+        outs.append(M.apply(Bd).cpu().numpy())
+    assert narrow[1][0] == 0
+    if name in ("laplace2d_256", "banded_40k"):
+        assert narrow[0][0] == narrow[0][1]  # a band: every chunk narrow
+    if name == "hamiltonian_200k":  # narrow except near the ends of the long diagonals
+        assert narrow[0][0] >= 0.9 * narrow[0][1]
+    assert np.array_equal(outs[0], outs[1])
+
+
 def test_batch_full_size_4096():
     """The batch the benchmark times (4096 matrices, seed 6, N log-uniform in
     [100, 5000]) in its launch mode (one tile-grid launch): every row of every
