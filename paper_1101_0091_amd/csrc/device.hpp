@@ -6,6 +6,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <type_traits>
 
 #include "common.hpp"
 
@@ -274,10 +275,30 @@ __device__ __forceinline__ void lds_block(BlockLds& L, const int32_t* __restrict
     }
   }
   if (!staged) {
+    // (the staging kernel keeps the plain gather for its unstaged blocks: the
+    // deferred widening below made its float32 form 5% slower on the
+    // permuted mesh through the schedule of the whole kernel)
+    if constexpr (std::is_same<BT, double>::value || STAGE) {
 #pragma unroll
-    for (int u = 0; u < kPer; ++u) {
-      const int k = tid + u * kWG;
-      if (k < nin) b[u] = widen(B[c[u]]);
+      for (int u = 0; u < kPer; ++u) {
+        const int k = tid + u * kWG;
+        if (k < nin) b[u] = widen(B[c[u]]);
+      }
+    } else {
+      // narrower B: gathered in its own type and widened after every gather
+      // is issued (the pin keeps each widening out of its masked gather,
+      // where it would wait for that load before the next is issued)
+      BT xg[kPer];
+#pragma unroll
+      for (int u = 0; u < kPer; ++u) {
+        const int k = tid + u * kWG;
+        xg[u] = (BT)0;
+        if (k < nin) xg[u] = B[c[u]];
+      }
+#pragma unroll
+      for (int u = 0; u < kPer; ++u) asm volatile("" : "+v"(xg[u]));
+#pragma unroll
+      for (int u = 0; u < kPer; ++u) b[u] = widen(xg[u]);
     }
   }
 #pragma unroll

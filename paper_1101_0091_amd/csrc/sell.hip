@@ -447,20 +447,51 @@ __global__ __launch_bounds__(kWG) void k_sell_spmm(int64_t nch, int64_t n,
   double acc[KB];
 #pragma unroll
   for (int t = 0; t < KB; ++t) acc[t] = 0.0;
+  // narrower value or B types are loaded and gathered in their own type and
+  // widened only after every load of the round is issued (empty asm pins
+  // keep the compiler from moving a widening next to its load, which then
+  // waits for that load before the next one is issued)
+  constexpr bool kPinV = !std::is_same<VT, double>::value;
+  constexpr bool kPinB = !std::is_same<BT, double>::value;
   for (int32_t j = 0; j < w; j += U) {
-    double v[U];
+    VT vr[U];
     int32_t c[U];
 #pragma unroll
     for (int u = 0; u < U; ++u) {
       if (j + u < w) {
         const int64_t o = a * kChunk + slot_offset<G>(j + u, lane, w);
-        v[u] = dev::widen(dev::ld_stream(sval + o));
+        vr[u] = dev::ld_stream(sval + o);
         c[u] = dev::ld_stream(sci + o);
       } else {
-        v[u] = 0.0;
+        vr[u] = (VT)0;
         c[u] = -1;
       }
     }
+    if constexpr (kPinB) {
+      BT xb[U][KB];
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const BT* bp = B + (int64_t)(c[u] >= 0 ? c[u] : 0) * ldb + c0;
+#pragma unroll
+        for (int t = 0; t < KB; ++t) xb[u][t] = (c[u] >= 0 && t < kc) ? bp[t] : (BT)0;
+      }
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        if constexpr (kPinV) asm volatile("" : "+v"(vr[u]));
+#pragma unroll
+        for (int t = 0; t < KB; ++t) asm volatile("" : "+v"(xb[u][t]));
+      }
+      // masked slots add fma(0, 0, acc) = acc exactly (acc is never -0)
+#pragma unroll
+      for (int u = 0; u < U; ++u)
+#pragma unroll
+        for (int t = 0; t < KB; ++t)
+          acc[t] = fma(dev::widen(vr[u]), (double)xb[u][t], acc[t]);
+      continue;
+    }
+    double v[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) v[u] = dev::widen(vr[u]);
     double x[U][KB];
 #pragma unroll
     for (int u = 0; u < U; ++u) {

@@ -210,6 +210,48 @@ __global__ __launch_bounds__(kWG) void k_spmm(int32_t nrows, int32_t k,
     double* out = C + row * ldc + c0;
     if (c0 + CPL <= k) {
       // full column group: vector loads of B, masked entries read nothing
+      if constexpr (!std::is_same<VT, double>::value || !std::is_same<BT, double>::value) {
+        // narrower types: loaded in their own type and widened only after
+        // every load of the round is issued (the empty asm pins keep each
+        // widening from being moved next to its load, where it would wait)
+        using V = typename Vec<BT, CPL>::type;
+        for (int32_t j = s; j < e; j += kSpmmU) {
+          VT vr[kSpmmU];
+          int32_t c[kSpmmU];
+#pragma unroll
+          for (int u = 0; u < kSpmmU; ++u) {
+            const bool in = j + u < e;
+            vr[u] = in ? val[j + u] : (VT)0;
+            c[u] = in ? ci[j + u] : -1;
+          }
+          BT b[kSpmmU][CPL];
+#pragma unroll
+          for (int u = 0; u < kSpmmU; ++u) {
+            V x{};
+            if (c[u] >= 0) x = *reinterpret_cast<const V*>(B + (int64_t)c[u] * ldb + c0);
+            static_assert(CPL == 1 || CPL == 4, "float column groups are 1 or 4 wide");
+            if constexpr (CPL == 1) {
+              b[u][0] = x;
+            } else {
+              b[u][0] = x.x;
+              b[u][1] = x.y;
+              b[u][2] = x.z;
+              b[u][3] = x.w;
+            }
+          }
+#pragma unroll
+          for (int u = 0; u < kSpmmU; ++u) {
+            asm volatile("" : "+v"(vr[u]));
+#pragma unroll
+            for (int t = 0; t < CPL; ++t) asm volatile("" : "+v"(b[u][t]));
+          }
+#pragma unroll
+          for (int u = 0; u < kSpmmU; ++u)
+#pragma unroll
+            for (int t = 0; t < CPL; ++t)
+              acc[t] = fma(widen(vr[u]), (double)b[u][t], acc[t]);
+        }
+      } else
       for (int32_t j = s; j < e; j += kSpmmU) {
         double v[kSpmmU];
         int32_t c[kSpmmU];
