@@ -91,9 +91,10 @@ typedef enum {
  * column index + value, plus a 2-byte column delta per slot and a 4-byte base
  * per 64 slots; the reserve is 1.5 nnz + 4096 slots (rounded up to 64) at 14
  * bytes each whatever val_dtype is, plus the bases. A chunk whose every slot
- * has its 64 columns within 65535 of each other is read through the deltas
- * (10 instead of 12 bytes per float64 slot); other chunks read the 4-byte
- * columns. Both give the same products in the same order. A pattern whose padded size
+ * has its 64 columns within 254 of each other is read through 8-bit deltas (9
+ * instead of 12 bytes per float64 slot), else within 65534 through 16-bit
+ * deltas (10 bytes); other chunks read the 4-byte columns. All give the same
+ * products in the same order. A pattern whose padded size
  * exceeds it still gets a plan, without V6 (spmv_get_sell_slots reports
  * SPMV_ERR_STATE); asking for V6 by name then fails with UNSUPPORTED. The
  * selector ranks V0..V5 only: with SPMV_SELECT_DEFAULT or SPMV_SELECT_MLP and
@@ -183,11 +184,11 @@ int spmv_get_autotune_times(spmv_handle h, double* us);
 /* Slots of the V6 copy (host out): 64 * sum of chunk widths, >= nnz; the
  * padding is slots - nnz. SPMV_ERR_STATE if the plan has no V6 copy. */
 int spmv_get_sell_slots(spmv_handle h, int64_t* slots);
-/* Chunks of the V6 copy read through 16-bit column deltas, and all chunks
- * (host out). Copies the per-chunk flags to the host (a blocking copy after
- * the device work of create, which has completed when create returns).
- * SPMV_ERR_STATE if the plan has no V6 copy. */
-int spmv_get_sell_narrow(spmv_handle h, int64_t* narrow_chunks, int64_t* chunks);
+/* Chunks of the V6 copy read through 8-bit and through 16-bit column deltas,
+ * and all chunks (host out). Copies the per-chunk flags to the host (a
+ * blocking copy after the device work of create, which has completed when
+ * create returns). SPMV_ERR_STATE if the plan has no V6 copy. */
+int spmv_get_sell_deltas(spmv_handle h, int64_t* chunks8, int64_t* chunks16, int64_t* chunks);
 /* Whether V4 runs in its B-staging form (host out: 1 or 0; see
  * SPMV_FLAG_V4_STAGE_ON). */
 int spmv_get_v4_staged(spmv_handle h, int* staged);

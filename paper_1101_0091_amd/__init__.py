@@ -40,7 +40,7 @@ SPMV_MLP_PARAMS = 5638
 EXPORTS = (
     "spmv_workspace_size", "spmv_create", "spmv_apply", "spmm_apply", "spmv_get_variant",
     "spmv_set_variant", "spmv_get_features", "spmv_get_predictions", "spmv_get_autotune_times",
-    "spmv_get_num_blocks", "spmv_get_sell_slots", "spmv_get_sell_narrow", "spmv_get_v4_staged", "spmv_destroy", "spmv_batch_workspace_size", "spmv_batch_create",
+    "spmv_get_num_blocks", "spmv_get_sell_slots", "spmv_get_sell_deltas", "spmv_get_v4_staged", "spmv_destroy", "spmv_batch_workspace_size", "spmv_batch_create",
     "spmv_batch_apply", "spmv_batch_apply_each", "spmv_batch_get_num_tiles", "spmv_batch_set_mode",
     "spmv_batch_destroy", "spmv_graph_begin", "spmv_graph_end", "spmv_graph_launch",
     "spmv_graph_destroy", "spmv_selector_load", "spmv_selector_loaded",
@@ -89,7 +89,7 @@ def lib():
             "spmv_get_autotune_times": [P, P],
             "spmv_get_num_blocks": [P, P],
             "spmv_get_sell_slots": [P, P],
-            "spmv_get_sell_narrow": [P, P, P],
+            "spmv_get_sell_deltas": [P, P, P, P],
             "spmv_get_v4_staged": [P, P],
             "spmv_destroy": [P],
             "spmv_batch_workspace_size": [i32, i64, i64, P],
@@ -249,11 +249,12 @@ def spmv_get_sell_slots(h) -> int:
     return int(n.value)
 
 
-def spmv_get_sell_narrow(h):
-    """(chunks read through 16-bit column deltas, all chunks) of the V6 copy."""
-    a, b = ctypes.c_int64(0), ctypes.c_int64(0)
-    _check(lib().spmv_get_sell_narrow(h, ctypes.byref(a), ctypes.byref(b)))
-    return int(a.value), int(b.value)
+def spmv_get_sell_deltas(h):
+    """(chunks read through 8-bit column deltas, through 16-bit ones, all
+    chunks) of the V6 copy."""
+    a, b, c = ctypes.c_int64(0), ctypes.c_int64(0), ctypes.c_int64(0)
+    _check(lib().spmv_get_sell_deltas(h, ctypes.byref(a), ctypes.byref(b), ctypes.byref(c)))
+    return int(a.value), int(b.value), int(c.value)
 
 
 def spmv_get_v4_staged(h) -> bool:

@@ -487,18 +487,22 @@ int spmv_get_sell_slots(spmv_handle h, int64_t* slots) {
   return SPMV_OK;
 }
 
-int spmv_get_sell_narrow(spmv_handle h, int64_t* narrow_chunks, int64_t* chunks) {
-  if (!h || !narrow_chunks || !chunks) return fail(SPMV_ERR_INVALID_ARG, "null argument");
+int spmv_get_sell_deltas(spmv_handle h, int64_t* chunks8, int64_t* chunks16, int64_t* chunks) {
+  if (!h || !chunks8 || !chunks16 || !chunks) return fail(SPMV_ERR_INVALID_ARG, "null argument");
   if (!h->p.sell_ok) return fail(SPMV_ERR_STATE, "this plan has no V6 copy");
   const int64_t nch = h->p.sell_nch;
-  int64_t narrow = 0;
+  int64_t n8 = 0, n16 = 0;
   if (nch > 0 && !h->p.sell_wide) {
     std::vector<int32_t> f((size_t)nch);
     SPMV_HIP(hipMemcpy(f.data(), h->p.sell_flag, sizeof(int32_t) * (size_t)nch,
                        hipMemcpyDeviceToHost));
-    for (int32_t x : f) narrow += x != 0;
+    for (int32_t x : f) {
+      n8 += x == 8;
+      n16 += x == 16;
+    }
   }
-  *narrow_chunks = narrow;
+  *chunks8 = n8;
+  *chunks16 = n16;
   *chunks = nch;
   return SPMV_OK;
 }

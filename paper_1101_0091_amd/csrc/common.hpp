@@ -85,9 +85,10 @@ struct Plan {
   int32_t* sell_partials = nullptr;
   int32_t* sell_ci = nullptr;     // device int32[cap]
   void* sell_val = nullptr;       // device val_dtype[cap]
-  // 16-bit column deltas: for chunk k (slots a = off[k] .. off[k+1] per lane),
+  // column deltas: for chunk k (slots a = off[k] .. off[k+1] per lane),
   // base[a + j] is the smallest column of slot j and dl the column minus that
-  // base (0xFFFF for padding); flag[k] = 1 where every slot of the chunk fits
+  // base in flag[k] = 8 or 16 bits (all ones for padding; 8-bit deltas in the
+  // first half of the chunk's region), flag[k] = 0 for 4-byte columns
   int32_t* sell_base = nullptr;   // device int32[cap / 64]
   uint16_t* sell_dl = nullptr;    // device uint16[cap]
   int32_t* sell_flag = nullptr;   // device int32[nch]

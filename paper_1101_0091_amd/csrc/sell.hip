@@ -14,12 +14,12 @@
 //
 // Column deltas: within a chunk, slot j of the 64 rows often points at 64
 // nearby columns (a band, a diagonal, a stencil). Each slot j then gets a
-// 4-byte base (the smallest of its columns) and every entry a 2-byte delta
-// from it (0xFFFF for padding). A chunk whose every slot spans at most 0xFFFE
-// columns is read through the deltas, 10 instead of 12 bytes per float64 slot
-// (6 instead of 8 for float32); other chunks read the 4-byte columns. The
-// column, and hence every product and the order of the sum, is the same
-// either way.
+// 4-byte base (the smallest of its columns) and every entry a delta from it
+// of 8 bits when every slot of the chunk spans at most 0xFE columns, else of
+// 16 bits when every slot spans at most 0xFFFE (the all-ones delta marks
+// padding): 9 or 10 instead of 12 bytes per float64 slot (5 or 6 instead of
+// 8 for float32). Other chunks read the 4-byte columns. The column, and hence
+// every product and the order of the sum, is the same either way.
 //
 // The copy is built on the device at plan creation in four passes: chunk
 // widths, an exclusive scan of the widths, the fill, and the deltas. Its
@@ -42,7 +42,8 @@ typedef float f32x4 __attribute__((ext_vector_type(4)));
 typedef int32_t i32x4 __attribute__((ext_vector_type(4)));
 typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
 
-constexpr uint32_t kPadDelta = 0xFFFFu;  // delta of a padding slot
+// Delta bits of a chunk (its flag): 0 = 4-byte columns, 8 or 16.
+template <int DB> constexpr uint32_t kPad = (1u << DB) - 1;  // delta of a padding slot
 
 // Slots per lane-interleaved group for a value type (see the layout above).
 template <typename VT> constexpr int kGroup = sizeof(VT) == 8 ? 2 : 4;
@@ -129,11 +130,22 @@ __global__ __launch_bounds__(kWG) void k_sell_fill(
 }
 
 // Column deltas of the filled copy (one wavefront per chunk): for each slot j
-// the smallest column over the chunk's rows becomes base[off + j], every entry
-// stores its column minus that base (kPadDelta for padding), and flag[k] = 1
-// when every slot of chunk k spans at most kPadDelta - 1 columns (the deltas
-// of a chunk with flag 0 are never read). Nothing is written unless the copy
-// fit its reserve.
+// the smallest column over the chunk's rows becomes base[off + j]; the largest
+// span over the slots picks the chunk's delta width (flag[k] = 8, 16, or 0 when
+// some slot spans more than 0xFFFE columns), and every entry stores its column
+// minus the slot's base in that width (all ones for padding). 8-bit deltas fill
+// the first half of the chunk's 16-bit delta region, at the same slot
+// positions. Nothing is written unless the copy fit its reserve.
+__device__ __forceinline__ void slot_min_max(int32_t c, int32_t& mn, int32_t& mx) {
+  mn = c >= 0 ? c : INT32_MAX;  // padding: c = -1
+  mx = c;
+  for (int m = 32; m >= 1; m >>= 1) {
+    const int32_t x = __shfl_xor(mn, m), y = __shfl_xor(mx, m);
+    mn = x < mn ? x : mn;
+    mx = y > mx ? y : mx;
+  }
+}
+
 template <int G>
 __global__ __launch_bounds__(kWG) void k_sell_narrow(int64_t nch, const int32_t* __restrict__ off,
                                                      int64_t cap64,
@@ -148,36 +160,54 @@ __global__ __launch_bounds__(kWG) void k_sell_narrow(int64_t nch, const int32_t*
   if (a < 0 || b < a || b > total) return;
   const int lane = threadIdx.x % kChunk;
   const int64_t w = b - a;
-  bool ok = true;
+  int64_t span = 0;  // largest over the slots; uniform over the wavefront
   for (int64_t j = 0; j < w; ++j) {
-    const int64_t o = a * kChunk + slot_offset<G>(j, lane, w);
-    const int32_t c = sci[o];
-    int32_t mn = c >= 0 ? c : INT32_MAX, mx = c;  // padding: c = -1
-    for (int m = 32; m >= 1; m >>= 1) {
-      const int32_t x = __shfl_xor(mn, m), y = __shfl_xor(mx, m);
-      mn = x < mn ? x : mn;
-      mx = y > mx ? y : mx;
-    }
+    int32_t mn, mx;
+    slot_min_max(sci[a * kChunk + slot_offset<G>(j, lane, w)], mn, mx);
     // slot j < w of the chunk's longest row is a real entry, so mn <= mx
-    ok = ok && (int64_t)mx - (int64_t)mn < (int64_t)kPadDelta;
+    span = (int64_t)mx - mn > span ? (int64_t)mx - mn : span;
     if (lane == 0) sbase[a + j] = mn;
-    sdl[o] = c >= 0 ? (uint16_t)(uint32_t)(c - mn) : (uint16_t)kPadDelta;
   }
-  if (lane == 0) flag[chunk] = ok ? 1 : 0;
+  const int db = span < (int64_t)kPad<8> ? 8 : span < (int64_t)kPad<16> ? 16 : 0;
+  if (db != 0) {
+    uint8_t* d8 = reinterpret_cast<uint8_t*>(sdl + a * kChunk);
+    for (int64_t j = 0; j < w; ++j) {
+      const int64_t o = slot_offset<G>(j, lane, w);
+      const int32_t c = sci[a * kChunk + o];
+      int32_t mn, mx;
+      slot_min_max(c, mn, mx);
+      const uint32_t d = c >= 0 ? (uint32_t)(c - mn) : 0xFFFFFFFFu;
+      if (db == 8)
+        d8[o] = (uint8_t)d;
+      else
+        sdl[a * kChunk + o] = (uint16_t)d;
+    }
+  }
+  if (lane == 0) flag[chunk] = db;
 }
 
 // Column of a slot read through its delta (-1 for padding).
+template <int DB>
 __device__ __forceinline__ int32_t delta_col(uint32_t d, int32_t base) {
-  return d != kPadDelta ? base + (int32_t)d : -1;
+  return d != kPad<DB> ? base + (int32_t)d : -1;
+}
+
+// Field i of a lane's delta word (G deltas of DB bits, the first in the low bits).
+template <int DB, typename W>
+__device__ __forceinline__ uint32_t delta_field(W d, int i) {
+  if constexpr (std::is_same<W, u32x2>::value)  // four 16-bit deltas
+    return ((i < 2 ? d.x : d.y) >> (DB * (i & 1))) & kPad<DB>;
+  else
+    return ((uint32_t)d >> (DB * i)) & kPad<DB>;
 }
 
 // C = A*B from the chunked copy with float64 values: lane l of the wavefront
 // of chunk k owns row 64 k + l and sums its slots in order, kSellUP pairs per
 // round, the odd last slot after the rounds. The width is uniform over the
 // wavefront, so the loop and its masked last round are uniform branches.
-// NARROW reads the columns as base + 16-bit delta (a pair of deltas per
-// 4-byte load, the bases as wavefront-uniform loads).
-template <bool NARROW>
+// DB > 0 reads the columns as base + DB-bit delta (a lane's pair of deltas
+// per 4- or 2-byte load, the bases as wavefront-uniform loads).
+template <int DB>
 __device__ __forceinline__ double sell_pairs_row(int64_t a, int32_t w, int lane,
                                                  const int32_t* __restrict__ sci,
                                                  const uint16_t* __restrict__ sdl,
@@ -189,7 +219,9 @@ __device__ __forceinline__ double sell_pairs_row(int64_t a, int32_t w, int lane,
   const int32_t P = w >> 1;
   const V2* vp = reinterpret_cast<const V2*>(sval + a * kChunk) + lane;
   const i32x2* cp = reinterpret_cast<const i32x2*>(sci + a * kChunk) + lane;
-  const uint32_t* dp = reinterpret_cast<const uint32_t*>(sdl + a * kChunk) + lane;
+  using DW = typename std::conditional<DB == 16, uint32_t, uint16_t>::type;  // 2 deltas
+  using DT = typename std::conditional<DB == 16, uint16_t, uint8_t>::type;   // 1 delta
+  const DW* dp = reinterpret_cast<const DW*>(sdl + a * kChunk) + lane;
   const int32_t* bp = sbase + a;
   double acc = 0.0;
   // padded and masked slots contribute fma(0, 0, acc) = acc exactly: acc
@@ -199,8 +231,10 @@ __device__ __forceinline__ double sell_pairs_row(int64_t a, int32_t w, int lane,
     V2 v[kSellUP];
     i32x2 c[kSellUP];
     double x0[kSellUP], x1[kSellUP];
-    if constexpr (NARROW) {
-      // every load of the round is issued before any delta is decoded
+    if constexpr (DB > 0) {
+      // every load of the round is issued before any delta is decoded (each
+      // word widened to 32 bits: two 8-bit pairs packed into one register
+      // made every load wait for its predecessor)
       uint32_t d[kSellUP];
       i32x2 b[kSellUP];
 #pragma unroll
@@ -215,9 +249,14 @@ __device__ __forceinline__ double sell_pairs_row(int64_t a, int32_t w, int lane,
           b[u] = i32x2{0, 0};
         }
       }
+      if constexpr (DB == 8) {
+#pragma unroll
+        for (int u = 0; u < kSellUP; ++u) asm volatile("" : "+v"(d[u]));
+      }
 #pragma unroll
       for (int u = 0; u < kSellUP; ++u)
-        c[u] = i32x2{delta_col(d[u] & 0xFFFFu, b[u].x), delta_col(d[u] >> 16, b[u].y)};
+        c[u] = i32x2{delta_col<DB>(delta_field<DB>(d[u], 0), b[u].x),
+                     delta_col<DB>(delta_field<DB>(d[u], 1), b[u].y)};
     } else {
 #pragma unroll
       for (int u = 0; u < kSellUP; ++u) {
@@ -244,8 +283,10 @@ __device__ __forceinline__ double sell_pairs_row(int64_t a, int32_t w, int lane,
   if (w & 1) {
     const int64_t o = a * kChunk + 2 * (int64_t)P * kChunk + lane;
     int32_t c;
-    if constexpr (NARROW)
-      c = delta_col(dev::ld_stream(sdl + o), bp[2 * P]);
+    if constexpr (DB > 0)
+      c = delta_col<DB>(dev::ld_stream(reinterpret_cast<const DT*>(sdl + a * kChunk) +
+                                       2 * (int64_t)P * kChunk + lane),
+                        bp[2 * P]);
     else
       c = dev::ld_stream(sci + o);
     if (c >= 0) acc = fma(dev::widen(dev::ld_stream(sval + o)), (double)B[c], acc);
@@ -274,9 +315,10 @@ __global__ __launch_bounds__(kWG) void k_sell_pairs(int64_t nch, int64_t n,
   const int lane = threadIdx.x % kChunk;
   const int64_t a = off[chunk];
   const int32_t w = (int32_t)(off[chunk + 1] - a);
-  const double acc = flag && flag[chunk]
-                         ? sell_pairs_row<true>(a, w, lane, sci, sdl, sbase, sval, B)
-                         : sell_pairs_row<false>(a, w, lane, sci, sdl, sbase, sval, B);
+  const int db = flag ? flag[chunk] : 0;
+  const double acc = db == 8    ? sell_pairs_row<8>(a, w, lane, sci, sdl, sbase, sval, B)
+                     : db == 16 ? sell_pairs_row<16>(a, w, lane, sci, sdl, sbase, sval, B)
+                                : sell_pairs_row<0>(a, w, lane, sci, sdl, sbase, sval, B);
   const int64_t row = chunk * kChunk + lane;
   if (row < n) C[row] = acc;
 }
@@ -285,9 +327,9 @@ __global__ __launch_bounds__(kWG) void k_sell_pairs(int64_t nch, int64_t n,
 // three tail slots are loaded before the first round and summed in it.
 constexpr int kSellUQ = 2;
 
-// NARROW reads the columns as base + 16-bit delta (four deltas per 8-byte
-// load).
-template <bool NARROW, typename BT>
+// DB > 0 reads the columns as base + DB-bit delta (a lane's four deltas per
+// 8- or 4-byte load).
+template <int DB, typename BT>
 __device__ __forceinline__ double sell_quads_row(int64_t a, int32_t w, int lane,
                                                  const int32_t* __restrict__ sci,
                                                  const uint16_t* __restrict__ sdl,
@@ -297,7 +339,9 @@ __device__ __forceinline__ double sell_quads_row(int64_t a, int32_t w, int lane,
   const int32_t Q = w >> 2, T = w & 3;
   const f32x4* vp = reinterpret_cast<const f32x4*>(sval + a * kChunk) + lane;
   const i32x4* cp = reinterpret_cast<const i32x4*>(sci + a * kChunk) + lane;
-  const u32x2* dp = reinterpret_cast<const u32x2*>(sdl + a * kChunk) + lane;
+  using DW = typename std::conditional<DB == 16, u32x2, uint32_t>::type;   // 4 deltas
+  using DT = typename std::conditional<DB == 16, uint16_t, uint8_t>::type;  // 1 delta
+  const DW* dp = reinterpret_cast<const DW*>(sdl + a * kChunk) + lane;
   const int32_t* bp = sbase + a;
   // tail slots: raw column words now, decoded at their gather in the first
   // round, so no tail load is waited for before the round's loads are issued
@@ -310,15 +354,16 @@ __device__ __forceinline__ double sell_quads_row(int64_t a, int32_t w, int lane,
     if (t < T) {
       const int64_t o = a * kChunk + 4 * (int64_t)Q * kChunk + t * kChunk + lane;
       tv[t] = dev::ld_stream(sval + o);
-      if constexpr (NARROW) {
-        tr[t] = dev::ld_stream(sdl + o);
+      if constexpr (DB > 0) {
+        tr[t] = dev::ld_stream(reinterpret_cast<const DT*>(sdl + a * kChunk) +
+                               4 * (int64_t)Q * kChunk + t * kChunk + lane);
         tb[t] = bp[4 * Q + t];
       } else {
         tr[t] = (uint32_t)dev::ld_stream(sci + o);
       }
     } else {
       tv[t] = 0.0f;
-      tr[t] = NARROW ? kPadDelta : 0xFFFFFFFFu;
+      tr[t] = DB > 0 ? kPad<DB> : 0xFFFFFFFFu;
     }
   }
   double acc = 0.0;
@@ -328,9 +373,9 @@ __device__ __forceinline__ double sell_quads_row(int64_t a, int32_t w, int lane,
   do {
     f32x4 v[kSellUQ];
     i32x4 c[kSellUQ];
-    if constexpr (NARROW) {
+    if constexpr (DB > 0) {
       // every load of the round is issued before any delta is decoded
-      u32x2 d[kSellUQ];
+      DW d[kSellUQ];
       i32x4 b[kSellUQ];
 #pragma unroll
       for (int u = 0; u < kSellUQ; ++u) {
@@ -340,14 +385,19 @@ __device__ __forceinline__ double sell_quads_row(int64_t a, int32_t w, int lane,
           b[u] = *reinterpret_cast<const i32x4*>(bp + 4 * (q + u));
         } else {
           v[u] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
-          d[u] = u32x2{0xFFFFFFFFu, 0xFFFFFFFFu};
+          if constexpr (DB == 16)
+            d[u] = u32x2{0xFFFFFFFFu, 0xFFFFFFFFu};
+          else
+            d[u] = 0xFFFFFFFFu;
           b[u] = i32x4{0, 0, 0, 0};
         }
       }
 #pragma unroll
       for (int u = 0; u < kSellUQ; ++u)
-        c[u] = i32x4{delta_col(d[u].x & 0xFFFFu, b[u].x), delta_col(d[u].x >> 16, b[u].y),
-                     delta_col(d[u].y & 0xFFFFu, b[u].z), delta_col(d[u].y >> 16, b[u].w)};
+        c[u] = i32x4{delta_col<DB>(delta_field<DB>(d[u], 0), b[u].x),
+                     delta_col<DB>(delta_field<DB>(d[u], 1), b[u].y),
+                     delta_col<DB>(delta_field<DB>(d[u], 2), b[u].z),
+                     delta_col<DB>(delta_field<DB>(d[u], 3), b[u].w)};
     } else {
 #pragma unroll
       for (int u = 0; u < kSellUQ; ++u) {
@@ -367,7 +417,11 @@ __device__ __forceinline__ double sell_quads_row(int64_t a, int32_t w, int lane,
     BT tx[3];
 #pragma unroll
     for (int t = 0; t < 3; ++t) {
-      const int32_t tc = NARROW ? delta_col(tr[t], tb[t]) : (int32_t)tr[t];
+      int32_t tc;
+      if constexpr (DB > 0)
+        tc = delta_col<DB>(tr[t], tb[t]);
+      else
+        tc = (int32_t)tr[t];
       tx[t] = (first && tc >= 0) ? B[tc] : (BT)0;
     }
     BT x[kSellUQ][4];
@@ -416,9 +470,10 @@ __global__ __launch_bounds__(kWG) void k_sell_quads(int64_t nch, int64_t n,
   const int lane = threadIdx.x % kChunk;
   const int64_t a = off[chunk];
   const int32_t w = (int32_t)(off[chunk + 1] - a);
-  const double acc = flag && flag[chunk]
-                         ? sell_quads_row<true, BT>(a, w, lane, sci, sdl, sbase, sval, B)
-                         : sell_quads_row<false, BT>(a, w, lane, sci, sdl, sbase, sval, B);
+  const int db = flag ? flag[chunk] : 0;
+  const double acc = db == 8    ? sell_quads_row<8, BT>(a, w, lane, sci, sdl, sbase, sval, B)
+                     : db == 16 ? sell_quads_row<16, BT>(a, w, lane, sci, sdl, sbase, sval, B)
+                                : sell_quads_row<0, BT>(a, w, lane, sci, sdl, sbase, sval, B);
   const int64_t row = chunk * kChunk + lane;
   if (row < n) C[row] = acc;
 }

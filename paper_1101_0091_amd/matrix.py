@@ -6,7 +6,7 @@ from __future__ import annotations
 import numpy as np
 
 from . import (SPMV_ERR_STATE, SPMV_F32, SPMV_F64, SPMV_SELECT_DEFAULT, SPMV_SELECT_MLP,
-               SpmvError, dtype_code, spmv_get_sell_narrow, spmv_get_sell_slots, spmv_get_v4_staged,
+               SpmvError, dtype_code, spmv_get_sell_deltas, spmv_get_sell_slots, spmv_get_v4_staged,
                load_selector, spmv_selector_loaded, spmm_apply, spmv_apply, spmv_batch_apply,
                spmv_batch_apply_each, spmv_batch_create, spmv_batch_destroy, spmv_batch_set_mode,
                spmv_batch_get_num_tiles, spmv_batch_workspace_size, spmv_create, spmv_destroy,
@@ -89,11 +89,11 @@ class CRSMatrix:
             raise
 
     @property
-    def sell_narrow(self):
-        """(chunks read through 16-bit column deltas, all chunks), or None
-        if the plan has no V6 copy."""
+    def sell_deltas(self):
+        """(chunks read through 8-bit column deltas, through 16-bit ones, all
+        chunks), or None if the plan has no V6 copy."""
         try:
-            return spmv_get_sell_narrow(self.handle)
+            return spmv_get_sell_deltas(self.handle)
         except SpmvError as e:
             if e.status == SPMV_ERR_STATE:
                 return None

@@ -109,8 +109,8 @@ def test_null_handle_calls():
     slots = ctypes.c_int64(-7)
     assert L.spmv_get_sell_slots(None, ctypes.byref(slots)) == pkg.SPMV_ERR_INVALID_ARG
     assert slots.value == -7  # untouched on error
-    assert L.spmv_get_sell_narrow(None, ctypes.byref(slots), ctypes.byref(slots)) == \
-        pkg.SPMV_ERR_INVALID_ARG
+    assert L.spmv_get_sell_deltas(None, ctypes.byref(slots), ctypes.byref(slots),
+                                  ctypes.byref(slots)) == pkg.SPMV_ERR_INVALID_ARG
     assert L.spmv_set_variant(None, pkg.SPMV_V6_SELL64) == pkg.SPMV_ERR_INVALID_ARG
     times = (ctypes.c_double * pkg.SPMV_NUM_VARIANTS)()
     assert L.spmv_get_autotune_times(None, times) == pkg.SPMV_ERR_INVALID_ARG

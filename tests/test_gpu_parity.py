@@ -511,11 +511,12 @@ def _span_matrix(spans, n_cols):
 
 @pytest.mark.parametrize("dt", ["f64", "f32"])
 def test_sell_column_deltas_at_their_limit(dt):
-    """A chunk is read through 16-bit deltas exactly when each of its slots
-    spans at most 0xFFFE columns (0xFFFF marks padding); either way the
-    product is bitwise the one read through the 4-byte columns, and within the
-    bound of the oracle."""
-    spans = [0, 1, 63, 0xFFFE, 0xFFFF, 0x10000, 1_000_000]
+    """A chunk is read through 8-bit deltas exactly when each of its slots
+    spans at most 0xFE columns, else through 16-bit deltas when each spans at
+    most 0xFFFE (the all-ones delta marks padding); either way the product is
+    bitwise the one read through the 4-byte columns, and within the bound of
+    the oracle."""
+    spans = [0, 1, 63, 0xFE, 0xFF, 0xFFFE, 0xFFFF, 0x10000, 1_000_000]
     A = _span_matrix(spans, 2_000_000)
     B = crsgen.uniform_vec(A.n_cols, 12)
     tdt = torch.float32 if dt == "f32" else torch.float64
@@ -523,11 +524,11 @@ def test_sell_column_deltas_at_their_limit(dt):
     Bh = B.astype(np.float32) if dt == "f32" else B
     Cref, S = oracle.spmv(A.n_rows, A.row_ptr, A.col_idx, val, Bh)
     outs = []
-    for wide, expect in ((False, 4), (True, 0)):
+    for wide, expect in ((False, (4, 2)), (True, (0, 0))):
         fl = pkg.SPMV_FLAG_VARIANT(6) | SELL | (pkg.SPMV_FLAG_SELL_WIDE if wide else 0)
         M = pkg.CRSMatrix(A.n_rows, A.n_cols, A.row_ptr, A.col_idx, val, val_dtype=tdt,
                           flags=fl, device=DEV)
-        assert M.sell_narrow == (expect, len(spans))
+        assert M.sell_deltas == expect + (len(spans),)
         C = M.apply(_gpu(Bh)).cpu().numpy()
         ok, worst = oracle.bound_ok(C, Cref, A.row_ptr, S)
         assert ok, (wide, worst)
@@ -551,13 +552,14 @@ def test_sell_deltas_bitwise_equal_wide(name, dt):
         M = pkg.CRSMatrix(A.n_rows, A.n_cols, A.row_ptr, A.col_idx, val, val_dtype=tdt,
                           flags=fl, device=DEV)
         M.variant = 6
-        narrow.append(M.sell_narrow)
+        narrow.append(M.sell_deltas)
         outs.append(M.apply(Bd).cpu().numpy())
-    assert narrow[1][0] == 0
+    assert narrow[1][:2] == (0, 0)
+    n8, n16, nch = narrow[0]
     if name in ("laplace2d_256", "banded_40k"):
-        assert narrow[0][0] == narrow[0][1]  # a band: every chunk narrow
-    if name == "hamiltonian_200k":  # narrow except near the ends of the long diagonals
-        assert narrow[0][0] >= 0.9 * narrow[0][1]
+        assert n8 + n16 == nch  # a band: every chunk on deltas
+    if name == "hamiltonian_200k":  # 8-bit except near the ends of the long diagonals
+        assert n8 >= 0.9 * nch
     assert np.array_equal(outs[0], outs[1])
 
 
