@@ -482,26 +482,21 @@ __global__ __launch_bounds__(kWG) void k_sell_quads(int64_t nch, int64_t n,
 // for t < kc = min(KB, k - c0). Lane l of chunk k owns row 64 k + l and keeps
 // KB accumulators; every slot gathers the row segment B[col, c0 .. c0 + KB)
 // (16-byte loads when VEC: float64 B, 16-byte aligned rows and segments).
-// Slots per round shrink with KB to bound the registers in flight.
-template <typename VT, typename BT, int KB, bool VEC>
-__global__ __launch_bounds__(kWG) void k_sell_spmm(int64_t nch, int64_t n,
-                                                   const int32_t* __restrict__ off,
-                                                   const int32_t* __restrict__ sci,
-                                                   const VT* __restrict__ sval,
-                                                   const BT* __restrict__ B, int64_t ldb,
-                                                   double* __restrict__ C, int64_t ldc,
-                                                   int32_t k, int32_t c0) {
+// Slots per round shrink with KB to bound the registers in flight. DB > 0
+// reads the columns through the chunk's DB-bit deltas.
+template <typename VT, typename BT, int KB, bool VEC, int DB>
+__device__ __forceinline__ void sell_spmm_rows(int64_t a, int32_t w, int lane, int32_t kc,
+                                               int32_t c0, const int32_t* __restrict__ sci,
+                                               const uint16_t* __restrict__ sdl,
+                                               const int32_t* __restrict__ sbase,
+                                               const VT* __restrict__ sval,
+                                               const BT* __restrict__ B, int64_t ldb,
+                                               double* acc) {
   constexpr int G = kGroup<VT>;
   constexpr int U = KB <= 4 ? 8 : 4;
-  const int64_t chunk = ((int64_t)blockIdx.x * kWG + threadIdx.x) / kChunk;
-  if (chunk >= nch) return;
-  const int lane = threadIdx.x % kChunk;
-  const int64_t a = off[chunk];
-  const int32_t w = (int32_t)(off[chunk + 1] - a);
-  const int32_t kc = k - c0 < KB ? k - c0 : KB;
-  double acc[KB];
-#pragma unroll
-  for (int t = 0; t < KB; ++t) acc[t] = 0.0;
+  using DT = typename std::conditional<DB == 16, uint16_t, uint8_t>::type;
+  const DT* dp = reinterpret_cast<const DT*>(sdl + a * kChunk);
+  const int32_t* bp = sbase + a;
   // narrower value or B types are loaded and gathered in their own type and
   // widened only after every load of the round is issued (empty asm pins
   // keep the compiler from moving a widening next to its load, which then
@@ -511,24 +506,47 @@ __global__ __launch_bounds__(kWG) void k_sell_spmm(int64_t nch, int64_t n,
   for (int32_t j = 0; j < w; j += U) {
     VT vr[U];
     int32_t c[U];
+    if constexpr (DB > 0) {
+      // deltas held as 32-bit words and decoded after every load is issued
+      uint32_t d[U];
+      int32_t b[U];
 #pragma unroll
-    for (int u = 0; u < U; ++u) {
-      if (j + u < w) {
-        const int64_t o = a * kChunk + slot_offset<G>(j + u, lane, w);
-        vr[u] = dev::ld_stream(sval + o);
-        c[u] = dev::ld_stream(sci + o);
-      } else {
-        vr[u] = (VT)0;
-        c[u] = -1;
+      for (int u = 0; u < U; ++u) {
+        if (j + u < w) {
+          const int64_t o = slot_offset<G>(j + u, lane, w);
+          vr[u] = dev::ld_stream(sval + a * kChunk + o);
+          d[u] = dev::ld_stream(dp + o);
+          b[u] = bp[j + u];
+        } else {
+          vr[u] = (VT)0;
+          d[u] = kPad<DB>;
+          b[u] = 0;
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < U; ++u) asm volatile("" : "+v"(d[u]));
+#pragma unroll
+      for (int u = 0; u < U; ++u) c[u] = delta_col<DB>(d[u], b[u]);
+    } else {
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        if (j + u < w) {
+          const int64_t o = a * kChunk + slot_offset<G>(j + u, lane, w);
+          vr[u] = dev::ld_stream(sval + o);
+          c[u] = dev::ld_stream(sci + o);
+        } else {
+          vr[u] = (VT)0;
+          c[u] = -1;
+        }
       }
     }
     if constexpr (kPinB) {
       BT xb[U][KB];
 #pragma unroll
       for (int u = 0; u < U; ++u) {
-        const BT* bp = B + (int64_t)(c[u] >= 0 ? c[u] : 0) * ldb + c0;
+        const BT* bq = B + (int64_t)(c[u] >= 0 ? c[u] : 0) * ldb + c0;
 #pragma unroll
-        for (int t = 0; t < KB; ++t) xb[u][t] = (c[u] >= 0 && t < kc) ? bp[t] : (BT)0;
+        for (int t = 0; t < KB; ++t) xb[u][t] = (c[u] >= 0 && t < kc) ? bq[t] : (BT)0;
       }
 #pragma unroll
       for (int u = 0; u < U; ++u) {
@@ -550,12 +568,12 @@ __global__ __launch_bounds__(kWG) void k_sell_spmm(int64_t nch, int64_t n,
     double x[U][KB];
 #pragma unroll
     for (int u = 0; u < U; ++u) {
-      const BT* bp = B + (int64_t)(c[u] >= 0 ? c[u] : 0) * ldb + c0;
+      const BT* bq = B + (int64_t)(c[u] >= 0 ? c[u] : 0) * ldb + c0;
       if constexpr (VEC && KB >= 2 && std::is_same<BT, double>::value) {
         if (c[u] >= 0) {
 #pragma unroll
           for (int t = 0; t < KB; t += 2) {
-            const f64x2 q = *reinterpret_cast<const f64x2*>(bp + t);
+            const f64x2 q = *reinterpret_cast<const f64x2*>(bq + t);
             x[u][t] = q.x;
             x[u][t + 1] = q.y;
           }
@@ -565,7 +583,7 @@ __global__ __launch_bounds__(kWG) void k_sell_spmm(int64_t nch, int64_t n,
         }
       } else {
 #pragma unroll
-        for (int t = 0; t < KB; ++t) x[u][t] = (c[u] >= 0 && t < kc) ? (double)bp[t] : 0.0;
+        for (int t = 0; t < KB; ++t) x[u][t] = (c[u] >= 0 && t < kc) ? (double)bq[t] : 0.0;
       }
     }
     // masked slots add fma(0, 0, acc) = acc exactly (acc is never -0)
@@ -574,6 +592,36 @@ __global__ __launch_bounds__(kWG) void k_sell_spmm(int64_t nch, int64_t n,
 #pragma unroll
       for (int t = 0; t < KB; ++t) acc[t] = fma(v[u], x[u][t], acc[t]);
   }
+}
+
+// flag is null when the plan keeps 4-byte columns only.
+template <typename VT, typename BT, int KB, bool VEC>
+__global__ __launch_bounds__(kWG) void k_sell_spmm(int64_t nch, int64_t n,
+                                                   const int32_t* __restrict__ off,
+                                                   const int32_t* __restrict__ sci,
+                                                   const int32_t* __restrict__ flag,
+                                                   const int32_t* __restrict__ sbase,
+                                                   const uint16_t* __restrict__ sdl,
+                                                   const VT* __restrict__ sval,
+                                                   const BT* __restrict__ B, int64_t ldb,
+                                                   double* __restrict__ C, int64_t ldc,
+                                                   int32_t k, int32_t c0) {
+  const int64_t chunk = chunk_of_wave();
+  if (chunk >= nch) return;
+  const int lane = threadIdx.x % kChunk;
+  const int64_t a = off[chunk];
+  const int32_t w = (int32_t)(off[chunk + 1] - a);
+  const int32_t kc = k - c0 < KB ? k - c0 : KB;
+  double acc[KB];
+#pragma unroll
+  for (int t = 0; t < KB; ++t) acc[t] = 0.0;
+  const int db = flag ? flag[chunk] : 0;
+  if (db == 8)
+    sell_spmm_rows<VT, BT, KB, VEC, 8>(a, w, lane, kc, c0, sci, sdl, sbase, sval, B, ldb, acc);
+  else if (db == 16)
+    sell_spmm_rows<VT, BT, KB, VEC, 16>(a, w, lane, kc, c0, sci, sdl, sbase, sval, B, ldb, acc);
+  else
+    sell_spmm_rows<VT, BT, KB, VEC, 0>(a, w, lane, kc, c0, sci, sdl, sbase, sval, B, ldb, acc);
   const int64_t row = chunk * kChunk + lane;
   if (row < n) {
     double* out = C + row * ldc + c0;
@@ -630,8 +678,8 @@ template <typename VT, typename BT, int KB, bool VEC>
 int sell_spmm_pass(const Plan& p, int k, int c0, const BT* B, int64_t ldb, double* C, int64_t ldc,
                    hipStream_t s) {
   k_sell_spmm<VT, BT, KB, VEC><<<grid_chunks(p.sell_nch), kWG, 0, s>>>(
-      p.sell_nch, p.n_rows, p.sell_off, p.sell_ci, static_cast<const VT*>(p.sell_val), B, ldb, C,
-      ldc, k, c0);
+      p.sell_nch, p.n_rows, p.sell_off, p.sell_ci, p.sell_wide ? nullptr : p.sell_flag,
+      p.sell_base, p.sell_dl, static_cast<const VT*>(p.sell_val), B, ldb, C, ldc, k, c0);
   SPMV_HIP(hipGetLastError());
   return SPMV_OK;
 }

@@ -541,12 +541,16 @@ def test_sell_column_deltas_at_their_limit(dt):
                                   "nnz0", "rows0"])  # the cases whose copy fits its reserve
 def test_sell_deltas_bitwise_equal_wide(name, dt):
     """Every case read through the deltas where they fit gives bitwise the
-    product of the copy read through its 4-byte columns."""
+    product (and the multi-RHS product) of the copy read through its 4-byte
+    columns."""
     A, B = case(name)
     tdt = torch.float32 if dt == "f32" else torch.float64
     val = A.val.astype(np.float32) if dt == "f32" else A.val
     Bd = _gpu(B.astype(np.float32) if dt == "f32" else B)
-    outs, narrow = [], []
+    tdB = torch.float32 if dt == "f32" else torch.float64
+    Bk = {k: torch.from_numpy(crsgen.uniform_vec(A.n_cols * k, 40 + k)).to(DEV, tdB).reshape(
+        A.n_cols, k) for k in (3, 8)}
+    outs, narrow, mm = [], [], []
     for wide in (False, True):
         fl = pkg.SPMV_FLAG_VARIANT(4) | SELL | (pkg.SPMV_FLAG_SELL_WIDE if wide else 0)
         M = pkg.CRSMatrix(A.n_rows, A.n_cols, A.row_ptr, A.col_idx, val, val_dtype=tdt,
@@ -554,7 +558,10 @@ def test_sell_deltas_bitwise_equal_wide(name, dt):
         M.variant = 6
         narrow.append(M.sell_deltas)
         outs.append(M.apply(Bd).cpu().numpy())
+        mm.append([M.spmm(Bk[k]).cpu().numpy() for k in (3, 8)])  # from the copy (k <= 8)
     assert narrow[1][:2] == (0, 0)
+    for x, y in zip(mm[0], mm[1]):
+        assert np.array_equal(x, y)
     n8, n16, nch = narrow[0]
     if name in ("laplace2d_256", "banded_40k"):
         assert n8 + n16 == nch  # a band: every chunk on deltas
