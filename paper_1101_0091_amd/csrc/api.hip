@@ -522,7 +522,7 @@ int spmv_destroy(spmv_handle h) {
 
 namespace {
 struct BatchLayout {
-  size_t err = 0, tiles = 0, toff = 0, nr = 0, nc = 0, nz = 0, total = 0;
+  size_t err = 0, tiles = 0, deltas = 0, toff = 0, nr = 0, nc = 0, nz = 0, total = 0;
 };
 BatchLayout batch_layout(int32_t count, int64_t max_tiles) {
   BatchLayout L;
@@ -531,6 +531,8 @@ BatchLayout batch_layout(int32_t count, int64_t max_tiles) {
   o += 256;  // err[2] at 0, tile counters[2] at 128
   L.tiles = o;
   o += align256(sizeof(int32_t) * kTileInts * (size_t)std::max<int64_t>(max_tiles, 1));
+  L.deltas = o;
+  o += align256((size_t)2 * kBlockBudget * (size_t)std::max<int64_t>(max_tiles, 1));
   L.toff = o;
   o += align256(sizeof(int64_t) * (size_t)(count + 1));
   L.nr = o;
@@ -591,6 +593,7 @@ int spmv_batch_create(spmv_batch_handle* h, int32_t count, const int64_t* n_rows
   b.col_idxs = col_idxs;
   b.vals = vals;
   b.tiles = reinterpret_cast<int32_t*>(ws + L.tiles);
+  b.deltas = reinterpret_cast<uint8_t*>(ws + L.deltas);
   b.ntiles = ntiles;
   b.err = reinterpret_cast<int32_t*>(ws + L.err);
   b.counters = reinterpret_cast<unsigned int*>(ws + L.err + 128);

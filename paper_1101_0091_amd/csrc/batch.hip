@@ -73,20 +73,27 @@ __global__ __launch_bounds__(kWG) void k_batch_tiles(int32_t count,
     t[5] = 0;
     t[6] = -1;
     t[7] = 0;
+    t[8] = 0;
+    t[9] = 0;
   }
 }
 
 // Staging range of every tile (one workgroup per tile): the column bounds of
 // its chunk [S, min(E, S + budget)) when they span at most the LDS array, else
 // the budget-wide window of columns centred on the tile's rows (clamped to
-// the matrix's columns). S and E are clamped to [0, nnz] so an invalid
-// pattern (reported by validation in the same pass) reads nothing out of
-// bounds.
+// the matrix's columns). The chunk's columns are also stored as deltas from
+// their smallest value, in 8 bits when they span at most 0xFF columns, else
+// in 16 bits when they span at most 0xFFFF (tile fields 7 and 8: bits and
+// base; 0 bits keeps the 4-byte columns); the product then reads 1 or 2
+// bytes per column instead of 4. S and E are clamped to [0, nnz] so an
+// invalid pattern (reported by validation in the same pass) reads nothing
+// out of bounds.
 __global__ __launch_bounds__(kWG) void k_batch_spans(int64_t ntiles,
                                                      const int64_t* __restrict__ nz,
                                                      const int64_t* __restrict__ nc,
                                                      const int32_t* const* __restrict__ cis,
-                                                     int32_t* __restrict__ tiles) {
+                                                     int32_t* __restrict__ tiles,
+                                                     uint8_t* __restrict__ deltas) {
   __shared__ int32_t lo[kWG / 64], hi[kWG / 64];
   const int64_t t = blockIdx.x;
   if (t >= ntiles) return;
@@ -121,6 +128,8 @@ __global__ __launch_bounds__(kWG) void k_batch_spans(int64_t ntiles,
     }
     a = lo[0] < a ? lo[0] : a;
     z = hi[0] > z ? hi[0] : z;
+    lo[0] = a;  // block-wide bounds for the delta pass
+    hi[0] = z;
     if (a > z) {  // empty chunk: nothing staged
       tl[5] = 0;
       tl[6] = -1;
@@ -138,6 +147,21 @@ __global__ __launch_bounds__(kWG) void k_batch_spans(int64_t ntiles,
       tl[6] = w0 < w1 ? (int32_t)(w1 - 1) : -1;
     }
   }
+  __syncthreads();
+  a = lo[0];
+  z = hi[0];
+  const int64_t span = (int64_t)z - a;
+  const int bits = a > z ? 0 : span <= 0xFF ? 8 : span <= 0xFFFF ? 16 : 0;
+  uint8_t* d = deltas + (int64_t)2 * kBlockBudget * t;
+  for (int64_t j = S + threadIdx.x; j < E; j += kWG) {
+    const uint32_t x = (uint32_t)(ci[j] - a);
+    if (bits == 8) d[j - S] = (uint8_t)x;
+    if (bits == 16) reinterpret_cast<uint16_t*>(d)[j - S] = (uint16_t)x;
+  }
+  if (threadIdx.x == 0) {
+    tl[7] = bits;
+    tl[8] = bits ? a : 0;
+  }
 }
 
 // B is staged in the LDS product array itself (2048 doubles): a 4096-entry
@@ -150,17 +174,18 @@ __device__ __forceinline__ void batch_tile(dev::BlockLds& L, const int32_t* __re
                                            const void* const* __restrict__ vals,
                                            const void* const* __restrict__ Bs,
                                            double* const* __restrict__ Cs,
-                                           const BT* __restrict__ B1, double* __restrict__ C1) {
+                                           const BT* __restrict__ B1, double* __restrict__ C1,
+                                           const uint8_t* __restrict__ deltas) {
   const int32_t* tl = tiles + kTileInts * t;
   const int32_t m = tl[0], r0 = tl[1], r1 = tl[2], S = tl[3], E = tl[4], cmin = tl[5],
-                cmax = tl[6];
+                cmax = tl[6], dbits = tl[7], dbase = tl[8];
   if (r0 >= r1) return;
   const BT* B = static_cast<const BT*>(dev::global_ptr_or(Bs, m, static_cast<const void*>(B1)));
   double* C = dev::global_ptr_or(Cs, m, C1);
-  dev::lds_block<VT, BT, false, true>(
+  dev::lds_block<VT, BT, false, true, true>(
       L, dev::global_ptr_at(rps, m), dev::global_ptr_at(cis, m),
       static_cast<const VT*>(dev::global_ptr_at(vals, m)), B, C, r0, r1, S, E, cmin, cmax,
-      L.prod, kBlockBudget);
+      L.prod, kBlockBudget, dbits, dbase, deltas + (int64_t)2 * kBlockBudget * t);
 }
 
 // Persistent, static: workgroup w owns one contiguous range of tiles.
@@ -169,14 +194,15 @@ __global__ __launch_bounds__(kWG) void k_batch_static(
     int64_t t0, int64_t t1, const int32_t* __restrict__ tiles,
     const int32_t* const* __restrict__ rps, const int32_t* const* __restrict__ cis,
     const void* const* __restrict__ vals, const void* const* __restrict__ Bs,
-    double* const* __restrict__ Cs, const BT* __restrict__ B1, double* __restrict__ C1) {
+    double* const* __restrict__ Cs, const BT* __restrict__ B1, double* __restrict__ C1,
+    const uint8_t* __restrict__ deltas) {
   __shared__ dev::BlockLds L;
   const int64_t w = dev::xcd_remap(blockIdx.x, gridDim.x);
   const int64_t n = t1 - t0, g = gridDim.x;
   const int64_t lo = t0 + (n * w) / g, hi = t0 + (n * (w + 1)) / g;
   for (int64_t t = lo; t < hi; ++t) {
     __syncthreads();  // LDS of the previous tile is no longer read
-    batch_tile<VT, BT>(L, tiles, t, rps, cis, vals, Bs, Cs, B1, C1);
+    batch_tile<VT, BT>(L, tiles, t, rps, cis, vals, Bs, Cs, B1, C1, deltas);
   }
 }
 
@@ -191,7 +217,7 @@ __global__ __launch_bounds__(kWG) void k_batch_dynamic(
     const int32_t* const* __restrict__ rps, const int32_t* const* __restrict__ cis,
     const void* const* __restrict__ vals, const void* const* __restrict__ Bs,
     double* const* __restrict__ Cs, const BT* __restrict__ B1, double* __restrict__ C1,
-    unsigned int* __restrict__ counters) {
+    const uint8_t* __restrict__ deltas, unsigned int* __restrict__ counters) {
   __shared__ dev::BlockLds L;
   __shared__ int64_t claim;
   for (;;) {
@@ -203,7 +229,7 @@ __global__ __launch_bounds__(kWG) void k_batch_dynamic(
     const int64_t ce = c + kClaim < t1 ? c + kClaim : t1;
     for (int64_t t = c; t < ce; ++t) {  // same trip count in every lane
       if (t > c) __syncthreads();       // previous tile done with LDS
-      batch_tile<VT, BT>(L, tiles, t, rps, cis, vals, Bs, Cs, B1, C1);
+      batch_tile<VT, BT>(L, tiles, t, rps, cis, vals, Bs, Cs, B1, C1, deltas);
     }
   }
   if (threadIdx.x == 0) {
@@ -221,10 +247,11 @@ __global__ __launch_bounds__(kWG) void k_batch_tilegrid(
     int64_t t0, int64_t t1, const int32_t* __restrict__ tiles,
     const int32_t* const* __restrict__ rps, const int32_t* const* __restrict__ cis,
     const void* const* __restrict__ vals, const void* const* __restrict__ Bs,
-    double* const* __restrict__ Cs, const BT* __restrict__ B1, double* __restrict__ C1) {
+    double* const* __restrict__ Cs, const BT* __restrict__ B1, double* __restrict__ C1,
+    const uint8_t* __restrict__ deltas) {
   __shared__ dev::BlockLds L;
   const int64_t t = t0 + dev::xcd_remap(blockIdx.x, t1 - t0);
-  batch_tile<VT, BT>(L, tiles, t, rps, cis, vals, Bs, Cs, B1, C1);
+  batch_tile<VT, BT>(L, tiles, t, rps, cis, vals, Bs, Cs, B1, C1, deltas);
 }
 
 template <typename VT, typename BT>
@@ -235,16 +262,16 @@ int batch_launch(const Batch& b, int64_t t0, int64_t t1, const void* const* Bs,
   const int64_t pgrid = std::min<int64_t>(b.grid, n);
   switch (b.mode) {
     case SPMV_BATCH_STATIC:
-      k_batch_static<VT, BT><<<(unsigned)pgrid, kWG, 0, s>>>(t0, t1, b.tiles, b.row_ptrs,
-                                                             b.col_idxs, b.vals, Bs, Cs, B1, C1);
+      k_batch_static<VT, BT><<<(unsigned)pgrid, kWG, 0, s>>>(
+          t0, t1, b.tiles, b.row_ptrs, b.col_idxs, b.vals, Bs, Cs, B1, C1, b.deltas);
       break;
     case SPMV_BATCH_TILE_GRID:
-      k_batch_tilegrid<VT, BT><<<(unsigned)n, kWG, 0, s>>>(t0, t1, b.tiles, b.row_ptrs,
-                                                           b.col_idxs, b.vals, Bs, Cs, B1, C1);
+      k_batch_tilegrid<VT, BT><<<(unsigned)n, kWG, 0, s>>>(
+          t0, t1, b.tiles, b.row_ptrs, b.col_idxs, b.vals, Bs, Cs, B1, C1, b.deltas);
       break;
     default:
       k_batch_dynamic<VT, BT><<<(unsigned)pgrid, kWG, 0, s>>>(
-          t0, t1, b.tiles, b.row_ptrs, b.col_idxs, b.vals, Bs, Cs, B1, C1, b.counters);
+          t0, t1, b.tiles, b.row_ptrs, b.col_idxs, b.vals, Bs, Cs, B1, C1, b.deltas, b.counters);
   }
   SPMV_HIP(hipGetLastError());
   return SPMV_OK;
@@ -267,7 +294,8 @@ int launch_batch_build(Batch& b, const int64_t* toff, const int64_t* nr, const i
   k_batch_tiles<<<b.count, kWG, 0, s>>>(b.count, nr, toff, b.row_ptrs, b.tiles);
   SPMV_HIP(hipGetLastError());
   if (b.ntiles > 0) {
-    k_batch_spans<<<(unsigned)b.ntiles, kWG, 0, s>>>(b.ntiles, nz, nc, b.col_idxs, b.tiles);
+    k_batch_spans<<<(unsigned)b.ntiles, kWG, 0, s>>>(b.ntiles, nz, nc, b.col_idxs, b.tiles,
+                                                     b.deltas);
     SPMV_HIP(hipGetLastError());
   }
   return SPMV_OK;

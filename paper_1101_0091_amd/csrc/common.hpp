@@ -18,7 +18,9 @@ constexpr int kWG = 256;          // threads per workgroup for the streaming ker
 constexpr int kBlockBudget = 2048;  // rows + in-chunk nonzeros of one LDS row block
 constexpr int kNumXCD = 8;        // MI355X: 8 accelerator complex dies, one L2 each
 constexpr int kNumBins = 5;       // row-length bins of the binned variant
-constexpr int kTileInts = 8;      // batch tile record: matrix, r0, r1, S, E, cmin, cmax, pad
+// batch tile record: matrix, r0, r1, S, E, staging cmin, cmax, column-delta bits (0, 8 or 16),
+// delta base, pad
+constexpr int kTileInts = 10;
 constexpr int kCounters = 32;     // u64 analysis counters in the workspace header
 constexpr int kStatsGrid = 1024;  // most workgroups of the row-statistics pass
 constexpr int kPartSlots = 18;    // u64 partial counters per statistics workgroup
@@ -104,6 +106,7 @@ struct Batch {
   const int32_t* const* col_idxs = nullptr;
   const void* const* vals = nullptr;
   int32_t* tiles = nullptr;   // device int32[kTileInts * ntiles]
+  uint8_t* deltas = nullptr;  // device [ntiles][2 * kBlockBudget]: column deltas per tile chunk
   int64_t ntiles = 0;
   int32_t* err = nullptr;     // device
   unsigned int* counters = nullptr;  // device [2]: next tile, finished workgroups

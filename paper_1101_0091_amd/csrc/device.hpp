@@ -223,37 +223,85 @@ __device__ __forceinline__ void block_rows(const BlockLds& L, const int32_t* __r
 // exact column span of the chunk [S, min(E, S + budget)) or, for blocks whose
 // span is wider, a window around the block's rows.
 // STAGE = false compiles the path out (callers without a range).
-template <typename VT, typename BT, bool ACC = false, bool STAGE = false>
+// DELTA: the chunk's columns may come from dptr as dbits-bit deltas from
+// dbase (8 or 16; 0 reads ci).
+template <typename VT, typename BT, bool ACC = false, bool STAGE = false, bool DELTA = false>
 __device__ __forceinline__ void lds_block(BlockLds& L, const int32_t* __restrict__ rp,
                                           const int32_t* __restrict__ ci,
                                           const VT* __restrict__ val, const BT* __restrict__ B,
                                           double* __restrict__ C, int32_t r0, int32_t r1,
                                           int32_t S, int32_t E, int32_t cmin = 0,
                                           int32_t cmax = -1, double* stage = nullptr,
-                                          int32_t stage_cap = 0) {
+                                          int32_t stage_cap = 0, int32_t dbits = 0,
+                                          int32_t dbase = 0,
+                                          const uint8_t* __restrict__ dptr = nullptr) {
   const int tid = threadIdx.x;
   const int32_t cend = (E - S > kBlockBudget) ? S + kBlockBudget : E;
   const int32_t nin = cend - S;
   const bool tail = E > cend;
   const int32_t span = cmax - cmin + 1;
-  const bool staged = STAGE && stage && cmin <= cmax && span <= stage_cap;
+  const bool staged = STAGE && stage && cmin <= cmax && span <= stage_cap &&
+                      span <= kBlockBudget;
 
   // phase 1: products of the chunk into LDS; all loads issued before use
   constexpr int kPer = kBlockBudget / kWG;
   VT v[kPer];
   int32_t c[kPer];
+  if (DELTA && dbits != 0) {
+    // raw deltas held as 32-bit words and the base added after every load
+    // is issued
+    uint32_t d[kPer];
 #pragma unroll
-  for (int u = 0; u < kPer; ++u) {
-    const int k = tid + u * kWG;
-    if (k < nin) {
-      v[u] = ld_stream(val + S + k);
-      c[u] = ld_stream(ci + S + k);
+    for (int u = 0; u < kPer; ++u) {
+      const int k = tid + u * kWG;
+      d[u] = 0;
+      if (k < nin) {
+        v[u] = ld_stream(val + S + k);
+        d[u] = dbits == 8 ? (uint32_t)ld_stream(dptr + k)
+                          : (uint32_t)ld_stream(reinterpret_cast<const uint16_t*>(dptr) + k);
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < kPer; ++u) asm volatile("" : "+v"(d[u]));
+#pragma unroll
+    for (int u = 0; u < kPer; ++u) c[u] = dbase + (int32_t)d[u];
+  } else {
+#pragma unroll
+    for (int u = 0; u < kPer; ++u) {
+      const int k = tid + u * kWG;
+      if (k < nin) {
+        v[u] = ld_stream(val + S + k);
+        c[u] = ld_stream(ci + S + k);
+      }
     }
   }
   double b[kPer];
   if constexpr (STAGE) {
     if (staged) {
-      for (int32_t k = tid; k < span; k += kWG) stage[k] = widen(B[cmin + k]);
+      if constexpr (!DELTA) {
+        for (int32_t k = tid; k < span; k += kWG) stage[k] = widen(B[cmin + k]);
+      } else {
+        // the batch's tiles: span <= stage_cap <= kPer * kWG, every load
+        // issued before the first LDS write (the loop above waits for each
+        // load before its write; unrolled, it costs the single-matrix kernel
+        // more through registers than it saves)
+        BT sv[kPer];
+#pragma unroll
+        for (int u = 0; u < kPer; ++u) {
+          const int k = tid + u * kWG;
+          sv[u] = (BT)0;
+          if (k < span) sv[u] = B[cmin + k];
+        }
+        if constexpr (!std::is_same<BT, double>::value) {
+#pragma unroll
+          for (int u = 0; u < kPer; ++u) asm volatile("" : "+v"(sv[u]));
+        }
+#pragma unroll
+        for (int u = 0; u < kPer; ++u) {
+          const int k = tid + u * kWG;
+          if (k < span) stage[k] = widen(sv[u]);
+        }
+      }
       __syncthreads();
 #pragma unroll
       for (int u = 0; u < kPer; ++u) {

@@ -570,6 +570,49 @@ def test_sell_deltas_bitwise_equal_wide(name, dt):
     assert np.array_equal(outs[0], outs[1])
 
 
+def _two_col(n, ncols, far, seed):
+    """n rows: even rows hold columns 0 and `far`, odd rows column 1, so the
+    one tile of the matrix spans exactly `far` columns."""
+    rng = np.random.default_rng(seed)
+    cols = [[0, far] if i % 2 == 0 else [1] for i in range(n)]
+    lens = np.array([len(c) for c in cols])
+    rp = np.concatenate([[0], np.cumsum(lens)]).astype(np.int32)
+    ci = np.concatenate(cols).astype(np.int32)
+    return crsgen.CRS(n, ncols, rp, ci, rng.standard_normal(ci.shape[0]))
+
+
+@pytest.mark.parametrize("dt", ["f64", "f32"])
+def test_batch_column_delta_widths(dt):
+    """Tile columns are read as 8-bit deltas up to a span of 0xFF, 16-bit up to
+    0xFFFF and as the 4-byte columns beyond: every width against the oracle,
+    and bitwise equal to the single-matrix staged row-block product (the same
+    blocks, products and sums)."""
+    mats = [_two_col(64, 300, 0xFF, 1), _two_col(64, 300, 0x100, 2),
+            _two_col(64, 70_000, 0xFFFF, 3), _two_col(64, 70_000, 0x10000, 4),
+            crsgen.random_crs(1000, 200_000, seed=5, max_len=40), _banded_ragged(3000, 9, 6, 2)]
+    tdt = torch.float32 if dt == "f32" else torch.float64
+    if dt == "f32":
+        mats = [crsgen.CRS(m.n_rows, m.n_cols, m.row_ptr, m.col_idx, m.val.astype(np.float32))
+                for m in mats]
+    Bt = pkg.Batch(mats, val_dtype=tdt, device=DEV)
+    Bh = crsgen.uniform_vec(int(Bt.n_cols.sum()), 7)
+    if dt == "f32":
+        Bh = Bh.astype(np.float32)
+    B_all = _gpu(Bh)
+    C_all = torch.full((int(Bt.n_rows.sum()),), float("nan"), dtype=torch.float64, device=DEV)
+    Bd, Cd, bh, ch = Bt.pointers(B_all, C_all)
+    Bt.apply(Bd, Cd)
+    for m, A in enumerate(mats):
+        b = Bh[Bt.col_off[m]:Bt.col_off[m + 1]]
+        Cref, S = oracle.spmv(A.n_rows, A.row_ptr, A.col_idx, A.val, b)
+        got = C_all[Bt.row_off[m]:Bt.row_off[m + 1]]
+        ok, worst = oracle.bound_ok(got.cpu().numpy(), Cref, A.row_ptr, S)
+        assert ok, (m, worst)
+        M = pkg.CRSMatrix(A.n_rows, A.n_cols, A.row_ptr, A.col_idx, A.val, val_dtype=tdt,
+                          flags=pkg.SPMV_FLAG_VARIANT(4) | pkg.SPMV_FLAG_V4_STAGE_ON, device=DEV)
+        assert torch.equal(M.apply(_gpu(b)), got), m
+
+
 def test_batch_full_size_4096():
     """The batch the benchmark times (4096 matrices, seed 6, N log-uniform in
     [100, 5000]) in its launch mode (one tile-grid launch): every row of every
