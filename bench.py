@@ -422,15 +422,17 @@ def run_solvers(pkg, dev):
     import crsgen
     L = crsgen.laplace2d(256)
     n = L.n_rows
-    M64 = pkg.CRSMatrix.from_crs(L, flags=pkg.SPMV_FLAG_VARIANT(4), device=dev)
+    # the solvers use whatever product the plan picked: autotuned over V0-V6
+    fl = pkg.SPMV_SELECT_AUTOTUNE | pkg.SPMV_FLAG_SELL
+    M64 = pkg.CRSMatrix.from_crs(L, flags=fl, device=dev)
     M32 = pkg.CRSMatrix(n, n, L.row_ptr, L.col_idx, L.val.astype(np.float32),
-                        val_dtype=torch.float32, flags=pkg.SPMV_FLAG_VARIANT(4), device=dev)
+                        val_dtype=torch.float32, flags=fl, device=dev)
     xs = torch.from_numpy(crsgen.uniform_vec(n, 8)).to(dev)
     b = M64.apply(xs)
     wsb = pkg.spmv_cg_workspace_size(n)
     ws = torch.empty(wsb, dtype=torch.uint8, device=dev)
     s = torch.cuda.Stream()
-    res = {}
+    res = {"variant_fp64": pkg.VARIANTS[M64.variant], "variant_fp32": pkg.VARIANTS[M32.variant]}
     for tag, M, tol in (("cg_fp64", M64, 1e-10), ("cg_fp32_storage", M32, 1e-5)):
         for graph in (False, True):
             x = torch.zeros(n, dtype=torch.float64, device=dev)
