@@ -11,7 +11,9 @@
  *
  * Conventions for every entry point:
  *  - Indices are 0-based. row_ptr and col_idx are int32 (the paper's 4-byte
- *    index), so nnz < 2^31; larger inputs return SPMV_ERR_UNSUPPORTED.
+ *    index). n_rows, n_cols and nnz may each be at most 2^31 - 4097 (the
+ *    kernels step through rows and nonzeros in int32 with strides of up to
+ *    4096); larger inputs return SPMV_ERR_UNSUPPORTED.
  *  - Every array argument is a DEVICE pointer owned by the caller unless the
  *    comment says "host". A handle BORROWS the matrix arrays and the
  *    workspace: they must stay alive and unchanged until the handle is
@@ -134,7 +136,7 @@ int spmv_workspace_size(int64_t n_rows, int64_t n_cols, int64_t nnz, uint32_t fl
  * Analyse a CRS matrix and build a plan (the paper's point that the
  * bookkeeping of a sparsity pattern is done once and reused, Sect. 3.1).
  *  h        host out: the new handle
- *  n_rows, n_cols >= 0; nnz = row_ptr[n_rows] >= 0, nnz < 2^31
+ *  n_rows, n_cols >= 0; nnz = row_ptr[n_rows] >= 0; each at most 2^31 - 4097
  *  row_ptr  int32[n_rows+1], col_idx int32[nnz], val float64 or float32 [nnz]
  *  val_dtype SPMV_F64 or SPMV_F32
  *  workspace device, >= spmv_workspace_size() bytes, 256-byte aligned

@@ -85,8 +85,8 @@ PlanLayout plan_layout(int64_t n_rows, int64_t n_cols, int64_t nnz, uint32_t fla
 
 int check_shape(int64_t n_rows, int64_t n_cols, int64_t nnz) {
   if (n_rows < 0 || n_cols < 0 || nnz < 0) return fail(SPMV_ERR_INVALID_ARG, "negative size");
-  if (nnz > INT32_MAX - 1 || n_rows > INT32_MAX - 1 || n_cols > INT32_MAX)
-    return fail(SPMV_ERR_UNSUPPORTED, "sizes must fit int32 indices (nnz < 2^31)");
+  if (nnz > kMaxDim || n_rows > kMaxDim || n_cols > kMaxDim)
+    return fail(SPMV_ERR_UNSUPPORTED, "n_rows, n_cols and nnz must each be at most 2^31 - 4097");
   return SPMV_OK;
 }
 

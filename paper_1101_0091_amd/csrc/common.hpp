@@ -21,6 +21,9 @@ constexpr int kNumBins = 5;       // row-length bins of the binned variant
 // batch tile record: matrix, r0, r1, S, E, staging cmin, cmax, column-delta bits (0, 8 or 16),
 // delta base, pad
 constexpr int kTileInts = 10;
+// Largest n_rows, n_cols and nnz: every int32 row, nonzero and column index
+// plus a kernel's stride (at most 4096) stays below 2^31.
+constexpr int64_t kMaxDim = 2147483647LL - 4096;
 constexpr int kCounters = 32;     // u64 analysis counters in the workspace header
 constexpr int kStatsGrid = 1024;  // most workgroups of the row-statistics pass
 constexpr int kPartSlots = 18;    // u64 partial counters per statistics workgroup

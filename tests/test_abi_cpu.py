@@ -55,9 +55,12 @@ def test_workspace_size_is_stable_and_checked():
     with pytest.raises(pkg.SpmvError) as e:
         pkg.spmv_workspace_size(-1, 5, 5)
     assert e.value.status == pkg.SPMV_ERR_INVALID_ARG
-    with pytest.raises(pkg.SpmvError) as e:
-        pkg.spmv_workspace_size(10, 10, 2**31)
-    assert e.value.status == pkg.SPMV_ERR_UNSUPPORTED
+    for big in (2**31, 2**31 - 4096):  # the largest accepted size is 2^31 - 4097
+        for shape in ((10, 10, big), (big, 10, 10), (10, big, 10)):
+            with pytest.raises(pkg.SpmvError) as e:
+                pkg.spmv_workspace_size(*shape)
+            assert e.value.status == pkg.SPMV_ERR_UNSUPPORTED
+    assert pkg.spmv_workspace_size(2**31 - 4097, 2**31 - 4097, 2**31 - 4097) > 0
     assert pkg.spmv_batch_workspace_size(4096, 5_000_000, 90_000_000) > 0
     with pytest.raises(pkg.SpmvError):
         pkg.spmv_batch_workspace_size(0, 1, 1)

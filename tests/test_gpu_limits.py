@@ -1,0 +1,97 @@
+"""The largest plan the library accepts: n_cols and nnz within 102 of the
+limit 2^31 - 4097 (every int32 row, nonzero and column index plus a kernel's
+stride stays below 2^31). Integer values keep every sum exact, so sampled
+rows of every variant, in both storage precisions, must equal the oracle bit
+for bit. About 90 GB of device memory at a time."""
+import numpy as np
+import pytest
+
+import oracle
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+import paper_1101_0091_amd as pkg  # noqa: E402
+
+DEV = "cuda:0"
+KMAX = 2**31 - 4097   # largest accepted n_rows, n_cols and nnz
+L = 127               # nonzeros per row
+N = KMAX // L         # 16,909,287 rows
+NNZ = N * L           # 2,147,479,449 nonzeros, 102 below the limit
+# row i holds columns j N + i (j < L): up to 2,147,479,448, sorted and distinct
+
+
+def _val(i, j):
+    return ((i + 3 * j) % 17) - 8
+
+
+def _bval(c):
+    return ((c * 7) % 13) - 6
+
+
+@pytest.fixture(scope="module")
+def big():
+    if torch.cuda.get_device_properties(0).total_memory < 160 * 2**30:
+        pytest.skip("needs 160 GB of device memory")
+    rp = (torch.arange(N + 1, device=DEV, dtype=torch.int64) * L).to(torch.int32)
+    ci = torch.empty(NNZ, dtype=torch.int32, device=DEV)
+    val = torch.empty(NNZ, dtype=torch.float64, device=DEV)
+    j = torch.arange(L, device=DEV, dtype=torch.int64)[None, :]
+    step = 1 << 22  # rows per generation chunk
+    for r0 in range(0, N, step):
+        r1 = min(N, r0 + step)
+        i = torch.arange(r0, r1, device=DEV, dtype=torch.int64)[:, None]
+        ci[r0 * L:r1 * L] = (j * N + i).reshape(-1).to(torch.int32)
+        val[r0 * L:r1 * L] = _val(i, j).reshape(-1).to(torch.float64)
+        del i
+    B = torch.empty(KMAX, dtype=torch.float64, device=DEV)
+    for c0 in range(0, KMAX, 1 << 28):
+        c1 = min(KMAX, c0 + (1 << 28))
+        B[c0:c1] = _bval(torch.arange(c0, c1, device=DEV, dtype=torch.int64)).to(torch.float64)
+    torch.cuda.synchronize()
+    # sampled rows and their exact products from the oracle on a compacted CRS
+    rng = np.random.default_rng(31)
+    rows = np.unique(np.concatenate([rng.choice(N, 2000, replace=False),
+                                     [0, 1, 63, 64, N - 65, N - 64, N - 2, N - 1]]))
+    cols = np.arange(L, dtype=np.int64)[None, :] * N + rows[:, None]
+    vs = _val(rows[:, None], np.arange(L)[None, :]).astype(np.float64).reshape(-1)
+    bs = _bval(cols).astype(np.float64).reshape(-1)
+    rp_s = (np.arange(len(rows) + 1) * L).astype(np.int32)
+    ci_s = np.arange(len(rows) * L, dtype=np.int32)
+    expect, _ = oracle.spmv(len(rows), rp_s, ci_s, vs, bs)
+    yield rp, ci, val, B, torch.from_numpy(rows).to(DEV), expect
+    del rp, ci, val, B
+    torch.cuda.empty_cache()
+
+
+def _check(M, B, rows_d, expect, variants):
+    C = torch.empty(N, dtype=torch.float64, device=DEV)
+    for v in variants:
+        M.variant = v
+        C.fill_(float("nan"))
+        M.apply(B, C)
+        got = C[rows_d].cpu().numpy()
+        assert np.array_equal(got, expect), (v, np.flatnonzero(got != expect)[:5])
+    del C
+
+
+def test_largest_plan_fp64_every_variant(big):
+    rp, ci, val, B, rows_d, expect = big
+    M = pkg.CRSMatrix(N, KMAX, rp, ci, val, flags=pkg.SPMV_FLAG_VARIANT(4) | pkg.SPMV_FLAG_SELL,
+                      device=DEV)
+    nch = (N + 63) // 64
+    assert M.sell_slots == 64 * L * nch
+    # slot j of a chunk holds columns j N + i of 64 consecutive rows: 8-bit deltas
+    assert M.sell_deltas == (nch, 0, nch)
+    _check(M, B, rows_d, expect, range(pkg.SPMV_NUM_VARIANTS))
+    del M
+    torch.cuda.empty_cache()
+
+
+def test_largest_plan_fp32_storage(big):
+    rp, ci, val, B, rows_d, expect = big
+    v32, B32 = val.float(), B.float()  # small integers: exact in float32
+    M = pkg.CRSMatrix(N, KMAX, rp, ci, v32, val_dtype=torch.float32,
+                      flags=pkg.SPMV_FLAG_VARIANT(4) | pkg.SPMV_FLAG_SELL, device=DEV)
+    _check(M, B32, rows_d, expect, (4, 6))
+    del M, v32, B32
+    torch.cuda.empty_cache()
