@@ -97,11 +97,22 @@ __global__ __launch_bounds__(kWG) void k_stats(int64_t n, int64_t nnz,
     v[P_VB0 + variant_bin(l)] += 1;
     if (l > 64) v[P_LONGNNZ] += ul;
     unsigned long long dl = 0, nr = 0;
-    for (int64_t j = s; j < e; ++j) {
-      int64_t d = (int64_t)ci[j] - i;
-      d = d < 0 ? -d : d;
-      dl += (unsigned long long)(63 - __clzll((unsigned long long)d + 1));
-      nr += d <= 64;
+    // eight columns loaded before any is used (integer sums: order-free); one
+    // load at a time left every lane waiting on each load of its row
+    constexpr int kU = 8;
+    for (int64_t j0 = s; j0 < e; j0 += kU) {
+      int32_t c[kU];
+#pragma unroll
+      for (int u = 0; u < kU; ++u) c[u] = j0 + u < e ? ci[j0 + u] : (int32_t)i;
+#pragma unroll
+      for (int u = 0; u < kU; ++u) {
+        int64_t d = (int64_t)c[u] - i;
+        d = d < 0 ? -d : d;
+        if (j0 + u < e) {
+          dl += (unsigned long long)(63 - __clzll((unsigned long long)d + 1));
+          nr += d <= 64;
+        }
+      }
     }
     v[P_DISTLOG] += dl;
     v[P_NEAR] += nr;
