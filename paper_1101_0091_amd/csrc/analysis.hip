@@ -345,11 +345,22 @@ __global__ __launch_bounds__(kWG) void k_block_spans(int64_t nblocks, int64_t nn
   S = S < 0 ? 0 : S > nnz ? nnz : S;
   E = E < S ? S : E > nnz ? nnz : E;
   if (E - S > kBlockBudget) E = S + kBlockBudget;
+  // the chunk's <= kBlockBudget columns, kPer per lane, loaded at once and
+  // kept for the window count below
+  constexpr int kPer = kBlockBudget / kWG;
+  int32_t cc[kPer];
   int32_t a = INT32_MAX, z = INT32_MIN;
-  for (int64_t j = S + threadIdx.x; j < E; j += kWG) {
-    const int32_t c = ci[j];
-    a = c < a ? c : a;
-    z = c > z ? c : z;
+#pragma unroll
+  for (int u = 0; u < kPer; ++u) {
+    const int64_t j = S + threadIdx.x + (int64_t)u * kWG;
+    cc[u] = j < E ? ci[j] : -1;
+  }
+#pragma unroll
+  for (int u = 0; u < kPer; ++u) {
+    if (S + threadIdx.x + (int64_t)u * kWG < E) {
+      a = cc[u] < a ? cc[u] : a;
+      z = cc[u] > z ? cc[u] : z;
+    }
   }
   for (int o = 32; o >= 1; o >>= 1) {
     const int32_t x = __shfl_xor(a, o), y = __shfl_xor(z, o);
@@ -388,9 +399,12 @@ __global__ __launch_bounds__(kWG) void k_block_spans(int64_t nblocks, int64_t nn
     w0c[q] = w0 < 0 ? 0 : w0;
     cnt[q] = 0;
   }
-  for (int64_t j = S + threadIdx.x; j < E; j += kWG) {
-    const int64_t c = ci[j];
-    for (int q = 0; q < kWinCand; ++q) cnt[q] += c >= w0c[q] && c < w0c[q] + kBlockBudget;
+#pragma unroll
+  for (int u = 0; u < kPer; ++u) {
+    if (S + threadIdx.x + (int64_t)u * kWG < E) {
+      const int64_t c = cc[u];
+      for (int q = 0; q < kWinCand; ++q) cnt[q] += c >= w0c[q] && c < w0c[q] + kBlockBudget;
+    }
   }
   __shared__ int32_t wc[kWG / 64][kWinCand];
   for (int q = 0; q < kWinCand; ++q) {

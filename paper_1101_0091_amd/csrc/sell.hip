@@ -117,13 +117,33 @@ __global__ __launch_bounds__(kWG) void k_sell_fill(
       c[u] = j < len ? ci[s + j] : -1;
       v[u] = j < len ? val[s + j] : (VT)0;
     }
+    // a whole group of G slots of the row goes out as one vector store of
+    // columns and one of values (the group is G-aligned: kU and j0 are
+    // multiples of G); the tail slots one at a time
+    constexpr int G = kGroup<VT>;
+    const int64_t GQ = G * (w / G);
 #pragma unroll
-    for (int u = 0; u < kU; ++u) {
+    for (int u = 0; u < kU; u += G) {
       const int64_t j = j0 + u;
-      if (j < w) {
-        const int64_t o = slot_offset<kGroup<VT>>(j, lane, w);
-        dc[o] = c[u];
-        dv[o] = v[u];
+      if (j + G <= GQ) {
+        const int64_t o = slot_offset<G>(j, lane, w);
+        if constexpr (G == 2) {
+          *reinterpret_cast<i32x2*>(dc + o) = i32x2{c[u], c[u + 1]};
+          *reinterpret_cast<f64x2*>(dv + o) = f64x2{(double)v[u], (double)v[u + 1]};
+        } else {
+          *reinterpret_cast<i32x4*>(dc + o) = i32x4{c[u], c[u + 1], c[u + 2], c[u + 3]};
+          *reinterpret_cast<f32x4*>(dv + o) = f32x4{(float)v[u], (float)v[u + 1],
+                                                    (float)v[u + 2], (float)v[u + 3]};
+        }
+      } else {
+#pragma unroll
+        for (int t = 0; t < G; ++t) {
+          if (j + t < w) {
+            const int64_t o = slot_offset<G>(j + t, lane, w);
+            dc[o] = c[u + t];
+            dv[o] = v[u + t];
+          }
+        }
       }
     }
   }
@@ -161,12 +181,22 @@ __global__ __launch_bounds__(kWG) void k_sell_narrow(int64_t nch, const int32_t*
   const int lane = threadIdx.x % kChunk;
   const int64_t w = b - a;
   int64_t span = 0;  // largest over the slots; uniform over the wavefront
-  for (int64_t j = 0; j < w; ++j) {
-    int32_t mn, mx;
-    slot_min_max(sci[a * kChunk + slot_offset<G>(j, lane, w)], mn, mx);
-    // slot j < w of the chunk's longest row is a real entry, so mn <= mx
-    span = (int64_t)mx - mn > span ? (int64_t)mx - mn : span;
-    if (lane == 0) sbase[a + j] = mn;
+  constexpr int kU = 8;  // slots loaded before any is reduced
+  for (int64_t j0 = 0; j0 < w; j0 += kU) {
+    int32_t c[kU];
+#pragma unroll
+    for (int u = 0; u < kU; ++u)
+      c[u] = j0 + u < w ? sci[a * kChunk + slot_offset<G>(j0 + u, lane, w)] : -1;
+#pragma unroll
+    for (int u = 0; u < kU; ++u) {
+      if (j0 + u < w) {  // uniform
+        int32_t mn, mx;
+        slot_min_max(c[u], mn, mx);
+        // slot j < w of the chunk's longest row is a real entry, so mn <= mx
+        span = (int64_t)mx - mn > span ? (int64_t)mx - mn : span;
+        if (lane == 0) sbase[a + j0 + u] = mn;
+      }
+    }
   }
   const int db = span < (int64_t)kPad<8> ? 8 : span < (int64_t)kPad<16> ? 16 : 0;
   if (db != 0) {
