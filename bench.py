@@ -314,8 +314,13 @@ def run_extra(A, B, M, pkg, pm, dev, stream, args):
         per, _ = time_launches(lambda: pkg.spmm_apply(ML32.handle, k, Bk32, k, pkg.SPMV_F32, Ck,
                                                       k), 50, 5, stream)
         t32 = float(np.median(per)) / 1000
+        c64 = cold_time(lambda: pkg.spmm_apply(ML.handle, k, Bk, k, pkg.SPMV_F64, Ck, k), stream)
+        c32 = cold_time(lambda: pkg.spmm_apply(ML32.handle, k, Bk32, k, pkg.SPMV_F32, Ck, k),
+                        stream)
         spmm[str(k)] = {"fp64_gflops": round(pm.gflops(L.nnz, t64, k), 1),
-                        "mixed_gflops": round(pm.gflops(L.nnz, t32, k), 1)}
+                        "mixed_gflops": round(pm.gflops(L.nnz, t32, k), 1),
+                        "fp64_cold_gflops": round(pm.gflops(L.nnz, c64, k), 1),
+                        "mixed_cold_gflops": round(pm.gflops(L.nnz, c32, k), 1)}
     ex["spmm_laplace2d_256"] = spmm
     log(f"spmm: {spmm}")
     # multi-RHS on the headline matrix with its own plan (V6 copy: one pass for k <= 8)
@@ -465,6 +470,25 @@ def run_solvers(pkg, dev):
     return res
 
 
+def cold_time(fn, stream, reps=20):
+    """Median duration (s) of fn with every cache cold: a 1 GiB buffer is
+    written before each timed call."""
+    import numpy as np
+    import torch
+    flush = torch.empty(1 << 27, dtype=torch.float64, device=stream.device)
+    ts = []
+    for _ in range(reps):
+        flush.fill_(1.0)
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record(stream)
+        fn()
+        b.record(stream)
+        torch.cuda.synchronize()
+        ts.append(a.elapsed_time(b))
+    del flush
+    return float(np.median(ts)) / 1000
+
+
 def run_small(pkg, pm, dev, stream):
     """The 2D Laplacian (256^2): fits in cache, so report warm (back to back)
     and cold (a 1 GiB buffer written between products evicts it)."""
@@ -479,17 +503,7 @@ def run_small(pkg, pm, dev, stream):
     comp = pm.compulsory_bytes(L.n_rows, L.n_cols, L.nnz)
     per, _ = time_launches(lambda: pkg.spmv_apply(M.handle, Bd, pkg.SPMV_F64, C), 50, 5, stream)
     warm = float(np.median(per)) / 1000
-    flush = torch.empty(1 << 27, dtype=torch.float64, device=dev)
-    cold = []
-    for _ in range(20):
-        flush.fill_(1.0)
-        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        a.record(stream)
-        pkg.spmv_apply(M.handle, Bd, pkg.SPMV_F64, C)
-        b.record(stream)
-        torch.cuda.synchronize()
-        cold.append(a.elapsed_time(b))
-    cold_t = float(np.median(cold)) / 1000
+    cold_t = cold_time(lambda: pkg.spmv_apply(M.handle, Bd, pkg.SPMV_F64, C), stream)
     res = {"variant": variant_name(pkg, M), "warm_us": round(warm * 1e6, 2),
            "cold_us": round(cold_t * 1e6, 2), "warm_gflops": round(pm.gflops(L.nnz, warm), 1),
            "cold_gflops": round(pm.gflops(L.nnz, cold_t), 1),
@@ -555,6 +569,12 @@ def run_batch(pkg, pm, dev, stream):
         Bt.set_mode(mode)
         rec(name, lambda: Bt.apply(Bd, Cd))
     Bt.set_mode(pkg.SPMV_BATCH_TILE_GRID)
+    # the batch (1.1 GB) exceeds the caches; cold timing shows what the
+    # memory-side cache held from the previous launch
+    t = cold_time(lambda: Bt.apply(Bd, Cd), stream)
+    res["one_launch_tile_grid_cold"] = {"us": round(t * 1e6, 1),
+                                        "eff_gbs": round(comp / t / 1e9, 1),
+                                        "gflops": round(pm.gflops(nnz, t), 1)}
     rec("separate_launches_4096", lambda: Bt.apply_each(bh, ch), steps=5)
     s = torch.cuda.Stream()
     torch.cuda.synchronize()
