@@ -156,14 +156,37 @@ __global__ __launch_bounds__(kWG) void k_sell_fill(
 // minus the slot's base in that width (all ones for padding). 8-bit deltas fill
 // the first half of the chunk's 16-bit delta region, at the same slot
 // positions. Nothing is written unless the copy fit its reserve.
+// One step of the wavefront min/max: combine with the partner lane that
+// STEP (a DPP pattern inside rows, then the 16- and 32-lane swaps) names.
+template <int STEP>
+__device__ __forceinline__ int32_t partner(int32_t x) {
+  if constexpr (STEP == 0) return __builtin_amdgcn_update_dpp(0, x, dev::kQuadXor1, 0xF, 0xF, false);
+  if constexpr (STEP == 1) return __builtin_amdgcn_update_dpp(0, x, dev::kQuadXor2, 0xF, 0xF, false);
+  if constexpr (STEP == 2)
+    return __builtin_amdgcn_update_dpp(0, x, dev::kRowHalfMirror, 0xF, 0xF, false);
+  if constexpr (STEP == 3) return __builtin_amdgcn_update_dpp(0, x, dev::kRowMirror, 0xF, 0xF, false);
+  if constexpr (STEP == 4) return __builtin_amdgcn_ds_swizzle(x, 0x401F);  // lane ^ 16
+  return __builtin_amdgcn_ds_bpermute((int)((__lane_id() ^ 32u) << 2), x);
+}
+
+template <int STEP>
+__device__ __forceinline__ void min_max_step(int32_t& mn, int32_t& mx) {
+  const int32_t x = partner<STEP>(mn), y = partner<STEP>(mx);
+  mn = x < mn ? x : mn;
+  mx = y > mx ? y : mx;
+}
+
+// Smallest and largest real column of a slot over the wavefront's 64 lanes
+// (every lane of the wavefront is active here).
 __device__ __forceinline__ void slot_min_max(int32_t c, int32_t& mn, int32_t& mx) {
   mn = c >= 0 ? c : INT32_MAX;  // padding: c = -1
   mx = c;
-  for (int m = 32; m >= 1; m >>= 1) {
-    const int32_t x = __shfl_xor(mn, m), y = __shfl_xor(mx, m);
-    mn = x < mn ? x : mn;
-    mx = y > mx ? y : mx;
-  }
+  min_max_step<0>(mn, mx);
+  min_max_step<1>(mn, mx);
+  min_max_step<2>(mn, mx);
+  min_max_step<3>(mn, mx);
+  min_max_step<4>(mn, mx);
+  min_max_step<5>(mn, mx);
 }
 
 template <int G>
