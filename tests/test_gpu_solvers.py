@@ -165,3 +165,22 @@ def test_lanczos_first_steps_match_cpu():
         assert abs(al[j] - a) <= 1e-12 * 8
         assert abs(be[j] - bn) <= 1e-12 * 8
         v, vp, bprev = w / bn, v, bn
+
+
+@pytest.mark.parametrize("dt", ["f64", "f32"])
+def test_cg_on_the_chunked_copy(lap128, dt):
+    """CG whose product is V6 read through its column deltas: eager and
+    graph-replayed iterations bitwise equal, and the solution converged."""
+    A, xs, b = lap128
+    tdt = torch.float32 if dt == "f32" else torch.float64
+    val = A.val.astype(np.float32) if dt == "f32" else A.val
+    M = pkg.CRSMatrix(A.n_rows, A.n_cols, A.row_ptr, A.col_idx, val, val_dtype=tdt,
+                      flags=pkg.SPMV_FLAG_VARIANT(6) | pkg.SPMV_FLAG_SELL, device=DEV)
+    n8, n16, nch = M.sell_deltas
+    assert n8 + n16 == nch
+    tol = 1e-5 if dt == "f32" else 1e-10
+    x1, it1, r1 = _cg(M, b, tol)
+    x2, it2, r2 = _cg(M, b, tol, graph=True)
+    assert it1 == it2 and r1 == r2 and np.array_equal(x1, x2)
+    Ax, _ = oracle.spmv(A.n_rows, A.row_ptr, A.col_idx, A.val, x1)
+    assert np.linalg.norm(b - Ax) / np.linalg.norm(b) <= (1e-4 if dt == "f32" else 1e-9)
