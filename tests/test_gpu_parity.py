@@ -613,6 +613,47 @@ def test_batch_column_delta_widths(dt):
         assert torch.equal(M.apply(_gpu(b)), got), m
 
 
+@pytest.mark.parametrize("dt", ["f64", "f32"])
+@pytest.mark.parametrize("shape", ["empty_chunks", "one_column", "ragged_last"])
+def test_sell_deltas_degenerate_chunks(shape, dt):
+    """Chunks of width 0 next to full ones, a single column (every span 0),
+    and a last chunk of 1 row: V6 through its deltas against the oracle and
+    bitwise against its 4-byte columns."""
+    rng = np.random.default_rng(17)
+    if shape == "empty_chunks":  # every other chunk empty, the rest 1..3 entries per row
+        n, nc = 64 * 9, 500
+        lens = np.array([0 if (i // 64) % 2 == 0 else 1 + i % 3 for i in range(n)])
+    elif shape == "one_column":
+        n, nc = 300, 1
+        lens = (np.arange(n) % 2).astype(np.int64)
+    else:  # 64 k + 1 rows: the last chunk holds one row
+        n, nc = 64 * 5 + 1, 2000
+        lens = rng.integers(1, 9, size=n)
+    rp = np.concatenate([[0], np.cumsum(lens)]).astype(np.int32)
+    ci = np.concatenate([np.sort(rng.choice(nc, size=l, replace=False)) for l in lens]
+                        ).astype(np.int32)
+    va = rng.standard_normal(ci.shape[0])
+    B = crsgen.uniform_vec(nc, 19)
+    tdt = torch.float32 if dt == "f32" else torch.float64
+    if dt == "f32":
+        va, B = va.astype(np.float32), B.astype(np.float32)
+    Cref, S = oracle.spmv(n, rp, ci, va, B)
+    outs = []
+    for wide in (False, True):
+        fl = pkg.SPMV_FLAG_VARIANT(6) | SELL | (pkg.SPMV_FLAG_SELL_WIDE if wide else 0)
+        M = pkg.CRSMatrix(n, nc, rp, ci, va, val_dtype=tdt, flags=fl, device=DEV)
+        C = torch.full((n,), float("nan"), dtype=torch.float64, device=DEV)
+        M.apply(_gpu(B), C)
+        got = C.cpu().numpy()
+        ok, worst = oracle.bound_ok(got, Cref, rp, S)
+        assert ok, (wide, worst)
+        outs.append(got)
+        if not wide:
+            n8, n16, nch = M.sell_deltas
+            assert n8 + n16 == nch  # every span here is below 0xFF or 0xFFFF
+    assert np.array_equal(outs[0], outs[1])
+
+
 def test_batch_full_size_4096():
     """The batch the benchmark times (4096 matrices, seed 6, N log-uniform in
     [100, 5000]) in its launch mode (one tile-grid launch): every row of every
