@@ -373,7 +373,9 @@ __global__ __launch_bounds__(kWG) void k_sell_pairs(int64_t nch, int64_t n,
                      : db == 16 ? sell_pairs_row<16>(a, w, lane, sci, sdl, sbase, sval, B)
                                 : sell_pairs_row<0>(a, w, lane, sci, sdl, sbase, sval, B);
   const int64_t row = chunk * kChunk + lane;
-  if (row < n) C[row] = acc;
+  // nontemporal: C is written once and not read again in this launch
+  // (1.6% faster on a 6M-row product; the float32 kernel lost 0.6% with it)
+  if (row < n) __builtin_nontemporal_store(acc, C + row);
 }
 
 // float32 values: groups of four slots, kSellUQ groups per round; the up to
