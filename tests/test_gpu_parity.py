@@ -227,6 +227,25 @@ def test_full_size_hamiltonian_and_mesh():
         torch.cuda.empty_cache()
 
 
+def test_full_size_spmm_hamiltonian():
+    """Multi-RHS on the full N = 6.0M Hamiltonian-like matrix with the plan the
+    benchmark times (autotuned, V6 copy requested): k = 2 and 8 run from the
+    chunked copy through its 8-bit deltas, k = 16 on the CRS row-group
+    kernel; every entry checked against the oracle."""
+    A = crsgen.hamiltonian(6_000_000, seed=2)
+    M = pkg.CRSMatrix.from_crs(A, flags=pkg.SPMV_SELECT_AUTOTUNE | SELL, device=DEV)
+    assert M.variant == pkg.SPMV_V6_SELL64
+    for k in (2, 8, 16):
+        Bh = crsgen.uniform_vec(A.n_cols * k, 4).reshape(A.n_cols, k)
+        Cref, S = oracle.spmm(A.n_rows, A.row_ptr, A.col_idx, A.val, Bh)
+        C = M.spmm(_gpu(Bh)).cpu().numpy()
+        ok, worst = oracle.bound_ok(C, Cref, A.row_ptr, S)
+        assert ok, (k, worst)
+        del Cref, S, C
+    del M
+    torch.cuda.empty_cache()
+
+
 @pytest.mark.parametrize("name", ["laplace2d_256", "powerlaw_60k", "mostly_empty", "hand",
                                   "rect_wide", "nnz0", "rows0"])
 def test_features_vs_oracle(name):
