@@ -15,6 +15,17 @@ from . import (SPMV_ERR_STATE, SPMV_F32, SPMV_F64, SPMV_SELECT_DEFAULT, SPMV_SEL
                spmv_split_workspace_size, spmv_workspace_size)
 
 
+def _keep(stream, *tensors):
+    """Tell PyTorch's caching allocator that work queued on a side stream
+    reads these tensors (the plan's own arrays and workspace), so their memory
+    is not handed out again before that work has run, even if the wrapper is
+    dropped first. The caller's B and C are the caller's to guard."""
+    import torch
+    if isinstance(stream, torch.cuda.Stream):
+        for t in tensors:
+            t.record_stream(stream)
+
+
 def _dev(x, dtype, device):
     import torch
     if isinstance(x, torch.Tensor):
@@ -104,6 +115,7 @@ class CRSMatrix:
         if C is None:
             C = torch.empty(self.n_rows, dtype=torch.float64, device=B.device)
         spmv_apply(self.handle, B, dtype_code(B), C, stream)
+        _keep(stream, self.row_ptr, self.col_idx, self.val, self.workspace)
         return C
 
     def spmm(self, B, C=None, stream=None):
@@ -114,6 +126,7 @@ class CRSMatrix:
             C = torch.empty((self.n_rows, k), dtype=torch.float64, device=B.device)
         spmm_apply(self.handle, k, B, int(B.stride(0)), dtype_code(B), C, int(C.stride(0)),
                    stream)
+        _keep(stream, self.row_ptr, self.col_idx, self.val, self.workspace)
         return C
 
     def close(self):
@@ -176,10 +189,14 @@ class Batch:
     def apply(self, Bs_dev, Cs_dev, b_code=None, stream=None):
         spmv_batch_apply(self.handle, Bs_dev, Cs_dev, self.code if b_code is None else b_code,
                          stream)
+        _keep(stream, self.rp_all, self.ci_all, self.val_all, self.rp_ptrs, self.ci_ptrs,
+              self.val_ptrs, self.workspace)
 
     def apply_each(self, Bs_host, Cs_host, b_code=None, stream=None):
         spmv_batch_apply_each(self.handle, Bs_host, Cs_host,
                               self.code if b_code is None else b_code, stream)
+        _keep(stream, self.rp_all, self.ci_all, self.val_all, self.rp_ptrs, self.ci_ptrs,
+              self.val_ptrs, self.workspace)
 
     def close(self):
         if getattr(self, "handle", None) is not None:
@@ -218,6 +235,7 @@ class SplitMatrix:
         if C is None:
             C = torch.empty(self.n_rows, dtype=torch.float64, device=B.device)
         spmv_split_apply(self.handle, pass_, B, self.code, C, stream)
+        _keep(stream, self.row_ptr, self.col_idx, self.val, self.workspace)
         return C
 
     def close(self):

@@ -125,6 +125,41 @@ def test_diagonal_bit_exact():
         assert np.array_equal(M.apply(_gpu(B)).cpu().numpy(), d * B), v
 
 
+@pytest.mark.parametrize("v", [0, 4, 5, 6])
+def test_concurrent_applies_on_two_streams(v):
+    """A plan is const under apply: two streams multiplying the same plan by
+    different B into different C at the same time give bitwise the results
+    of the sequential products (V4 in its B-staging form, V6 through its
+    8-bit deltas, and multi-RHS from the copy)."""
+    A, _ = case("hamiltonian_200k")
+    flags = pkg.SPMV_FLAG_VARIANT(v) | SELL | (pkg.SPMV_FLAG_V4_STAGE_ON if v == 4 else 0)
+    M = pkg.CRSMatrix.from_crs(A, flags=flags, device=DEV)
+    if v == 6:
+        assert M.sell_deltas[0] > 0
+    B1, B2 = _gpu(crsgen.uniform_vec(A.n_cols, 11)), _gpu(crsgen.uniform_vec(A.n_cols, 12))
+    Bk = _gpu(crsgen.uniform_vec(A.n_cols * 4, 13).reshape(A.n_cols, 4))
+    ref1, ref2, refk = M.apply(B1), M.apply(B2), M.spmm(Bk)
+    torch.cuda.synchronize()
+    reps = 16
+    C1 = torch.empty((reps, A.n_rows), dtype=torch.float64, device=DEV)
+    C2 = torch.empty_like(C1)
+    Ck = torch.empty((reps, A.n_rows, 4), dtype=torch.float64, device=DEV)
+    s1, s2 = torch.cuda.Stream(), torch.cuda.Stream()
+    s1.wait_stream(torch.cuda.current_stream())
+    s2.wait_stream(torch.cuda.current_stream())
+    for i in range(reps):
+        M.apply(B1, C1[i], stream=s1)
+        M.apply(B2, C2[i], stream=s2)
+        M.spmm(Bk, Ck[i], stream=s1 if i % 2 else s2)
+    torch.cuda.synchronize()
+    for i in range(reps):
+        assert torch.equal(C1[i], ref1) and torch.equal(C2[i], ref2), (v, i)
+        assert torch.equal(Ck[i], refk), (v, i)
+    Cref, S = oracle.spmv(A.n_rows, A.row_ptr, A.col_idx, A.val, B1.cpu().numpy())
+    ok, worst = oracle.bound_ok(ref1.cpu().numpy(), Cref, A.row_ptr, S)
+    assert ok, worst
+
+
 def test_deterministic_repeats():
     A, B = case("powerlaw_60k")
     M = pkg.CRSMatrix.from_crs(A, device=DEV)
