@@ -38,6 +38,7 @@ constexpr int kSellUP = 8;  // slot pairs of one row loaded before the first is 
 
 typedef double f64x2 __attribute__((ext_vector_type(2)));
 typedef int32_t i32x2 __attribute__((ext_vector_type(2)));
+typedef float f32x2 __attribute__((ext_vector_type(2)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 typedef int32_t i32x4 __attribute__((ext_vector_type(4)));
 typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
@@ -380,7 +381,10 @@ __global__ __launch_bounds__(kWG) void k_sell_pairs(int64_t nch, int64_t n,
 
 // float32 values: groups of four slots, kSellUQ groups per round; the up to
 // three tail slots are loaded before the first round and summed in it.
-constexpr int kSellUQ = 2;
+// Three groups (62 VGPRs, 8 waves per SIMD) put a row of up to 15 entries in
+// one round: 4.9% faster than two groups on a 6M-row matrix of width 15,
+// four groups (66 VGPRs, 7 waves) 4%.
+constexpr int kSellUQ = 3;
 
 // DB > 0 reads the columns as base + DB-bit delta (a lane's four deltas per
 // 8- or 4-byte load).
@@ -536,8 +540,10 @@ __global__ __launch_bounds__(kWG) void k_sell_quads(int64_t nch, int64_t n,
 // Multi-RHS form from the chunked copy: C[i, c0 + t] = sum_j val(j) B[col(j), c0 + t]
 // for t < kc = min(KB, k - c0). Lane l of chunk k owns row 64 k + l and keeps
 // KB accumulators; every slot gathers the row segment B[col, c0 .. c0 + KB)
-// (16-byte loads when VEC: float64 B, 16-byte aligned rows and segments).
-// Slots per round shrink with KB to bound the registers in flight. DB > 0
+// (vector loads when VEC: 16-byte for float64 pairs and float32 quads, 8-byte
+// for float32 pairs, on rows and segments aligned to them). Slots per round
+// shrink with KB to bound the registers in flight (16 up to KB = 4, 8 for
+// KB = 8: a round of 15 entries or fewer is one round of loads). DB > 0
 // reads the columns through the chunk's DB-bit deltas.
 template <typename VT, typename BT, int KB, bool VEC, int DB>
 __device__ __forceinline__ void sell_spmm_rows(int64_t a, int32_t w, int lane, int32_t kc,
@@ -548,7 +554,7 @@ __device__ __forceinline__ void sell_spmm_rows(int64_t a, int32_t w, int lane, i
                                                const BT* __restrict__ B, int64_t ldb,
                                                double* acc) {
   constexpr int G = kGroup<VT>;
-  constexpr int U = KB <= 4 ? 8 : 4;
+  constexpr int U = KB <= 4 ? 16 : 8;
   using DT = typename std::conditional<DB == 16, uint16_t, uint8_t>::type;
   const DT* dp = reinterpret_cast<const DT*>(sdl + a * kChunk);
   const int32_t* bp = sbase + a;
@@ -600,8 +606,31 @@ __device__ __forceinline__ void sell_spmm_rows(int64_t a, int32_t w, int lane, i
 #pragma unroll
       for (int u = 0; u < U; ++u) {
         const BT* bq = B + (int64_t)(c[u] >= 0 ? c[u] : 0) * ldb + c0;
+        if constexpr (VEC && KB >= 2) {
+          // one 8-byte (KB = 2) or 16-byte load per 4 columns of the segment
+          if (c[u] >= 0) {
+            if constexpr (KB == 2) {
+              const f32x2 q = *reinterpret_cast<const f32x2*>(bq);
+              xb[u][0] = q.x;
+              xb[u][1] = q.y;
+            } else {
 #pragma unroll
-        for (int t = 0; t < KB; ++t) xb[u][t] = (c[u] >= 0 && t < kc) ? bq[t] : (BT)0;
+              for (int t = 0; t < KB; t += 4) {
+                const f32x4 q = *reinterpret_cast<const f32x4*>(bq + t);
+                xb[u][t] = q.x;
+                xb[u][t + 1] = q.y;
+                xb[u][t + 2] = q.z;
+                xb[u][t + 3] = q.w;
+              }
+            }
+          } else {
+#pragma unroll
+            for (int t = 0; t < KB; ++t) xb[u][t] = (BT)0;
+          }
+        } else {
+#pragma unroll
+          for (int t = 0; t < KB; ++t) xb[u][t] = (c[u] >= 0 && t < kc) ? bq[t] : (BT)0;
+        }
       }
 #pragma unroll
       for (int u = 0; u < U; ++u) {
@@ -744,8 +773,13 @@ int sell_spmm_typed(const Plan& p, int k, const BT* B, int64_t ldb, double* C, i
                     hipStream_t s) {
   // columns in blocks of KB = the smallest of 1, 2, 4, 8 covering min(k, 8)
   const int KB = k >= 5 ? 8 : k >= 3 ? 4 : k == 2 ? 2 : 1;
-  const bool vec = std::is_same<BT, double>::value && KB >= 2 &&
-                   reinterpret_cast<uintptr_t>(B) % 16 == 0 && ldb % 2 == 0;
+  // vector loads of B row segments need them aligned to the load width:
+  // 16 bytes for float64 pairs and float32 quads, 8 for float32 pairs
+  // (c0 is a multiple of KB)
+  const uintptr_t ba = reinterpret_cast<uintptr_t>(B);
+  const bool vec = KB >= 2 && (std::is_same<BT, double>::value ? ba % 16 == 0 && ldb % 2 == 0
+                               : KB == 2 ? ba % 8 == 0 && ldb % 2 == 0
+                                         : ba % 16 == 0 && ldb % 4 == 0);
   for (int c0 = 0; c0 < k; c0 += KB) {
     // a full-width block takes the vector path; a partial last block the scalar one
     const bool full = c0 + KB <= k;

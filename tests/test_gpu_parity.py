@@ -225,6 +225,34 @@ def test_spmm_from_v6_copy(name, k, dt):
     assert np.all(Cp[:, k] == 7.0)
 
 
+@pytest.mark.parametrize("dt", ["f64", "f32"])
+@pytest.mark.parametrize("k", [2, 4, 8, 16])
+def test_spmm_from_v6_copy_misaligned_B(k, dt):
+    """B starting 1 or 2 elements past an aligned address: the vector loads of
+    B row segments need 16 bytes of alignment (8 for float32 pairs), and a B
+    that lacks it takes the scalar path with the same products."""
+    A, _ = case("hamiltonian_200k")
+    tdt = torch.float32 if dt == "f32" else torch.float64
+    val = A.val.astype(np.float32) if dt == "f32" else A.val
+    Bh = crsgen.uniform_vec(A.n_cols * k, 6).reshape(A.n_cols, k)
+    if dt == "f32":
+        Bh = Bh.astype(np.float32)
+    Cref, S = oracle.spmm(A.n_rows, A.row_ptr, A.col_idx, val, Bh)
+    M = pkg.CRSMatrix(A.n_rows, A.n_cols, A.row_ptr, A.col_idx, val, val_dtype=tdt,
+                      flags=pkg.SPMV_FLAG_VARIANT(6) | SELL, device=DEV)
+    aligned = M.spmm(_gpu(Bh))
+    for off in (1, 2):
+        flat = torch.zeros(A.n_cols * k + off, dtype=tdt, device=DEV)
+        Bv = flat[off:].view(A.n_cols, k)
+        Bv.copy_(_gpu(Bh))
+        C = torch.empty((A.n_rows, k), dtype=torch.float64, device=DEV)
+        pkg.spmm_apply(M.handle, k, Bv, k, M.code, C, k)
+        ok, worst = oracle.bound_ok(C.cpu().numpy(), Cref, A.row_ptr, S)
+        assert ok, (off, worst)
+        # the same slots summed in the same order: bitwise equal to the aligned B
+        assert torch.equal(C, aligned), off
+
+
 def test_full_size_hamiltonian_and_mesh():
     """Workloads at full size (N = 6.0M and 21.95M), every row checked, with
     the plans the benchmark builds (V6 copy requested; it fits the
