@@ -5,7 +5,7 @@ matrices) and the committed weights (trained on the GPU with the library's
 own kernels). The held-out choices are recomputed with the float64 oracle
 network, so this test needs no GPU. Selector accuracy itself is not pinned by
 the paper (it has no learned component): the exhaustive autotuner's timings
-are the judge."""
+decide which choice was right."""
 import json
 import os
 
