@@ -161,6 +161,8 @@ struct Vec<double, 2> { using type = double2; };
 template <>
 struct Vec<float, 1> { using type = float; };
 template <>
+struct Vec<float, 2> { using type = float2; };
+template <>
 struct Vec<float, 4> { using type = float4; };
 
 template <typename BT, int CPL>
@@ -229,9 +231,13 @@ __global__ __launch_bounds__(kWG) void k_spmm(int32_t nrows, int32_t k,
           for (int u = 0; u < kSpmmU; ++u) {
             V x{};
             if (c[u] >= 0) x = *reinterpret_cast<const V*>(B + (int64_t)c[u] * ldb + c0);
-            static_assert(CPL == 1 || CPL == 4, "float column groups are 1 or 4 wide");
+            static_assert(CPL == 1 || CPL == 2 || CPL == 4,
+                          "float column groups are 1, 2 or 4 wide");
             if constexpr (CPL == 1) {
               b[u][0] = x;
+            } else if constexpr (CPL == 2) {
+              b[u][0] = x.x;
+              b[u][1] = x.y;
             } else {
               b[u][0] = x.x;
               b[u][1] = x.y;
@@ -284,17 +290,45 @@ __global__ __launch_bounds__(kWG) void k_spmm(int32_t nrows, int32_t k,
         for (int t = 0; t < CPL; ++t) out[t] = acc[t];
       }
     } else {
-      // last, partial column group (k not a multiple of CPL): scalar loads
-      for (int32_t j = s; j < e; ++j) {
-        const double v = widen(val[j]);
-        const int64_t o = (int64_t)ci[j] * ldb + c0;
+      // last, partial column group (k not a multiple of CPL): the same rounds
+      // of kSpmmU entries with the B elements loaded one by one (an entry at
+      // a time made each entry's loads wait for the previous entry's FMAs:
+      // k = 6 took twice as long as k = 8)
+      const int32_t kc = k - c0;
+      for (int32_t j = s; j < e; j += kSpmmU) {
+        VT vr[kSpmmU];
+        int32_t c[kSpmmU];
 #pragma unroll
-        for (int t = 0; t < CPL; ++t)
-          if (c0 + t < k) acc[t] = fma(v, (double)B[o + t], acc[t]);
+        for (int u = 0; u < kSpmmU; ++u) {
+          const bool in = j + u < e;
+          vr[u] = in ? val[j + u] : (VT)0;
+          c[u] = in ? ci[j + u] : -1;
+        }
+        BT b[kSpmmU][CPL];
+#pragma unroll
+        for (int u = 0; u < kSpmmU; ++u) {
+          const BT* bq = B + (int64_t)(c[u] >= 0 ? c[u] : 0) * ldb + c0;
+#pragma unroll
+          for (int t = 0; t < CPL; ++t) b[u][t] = (c[u] >= 0 && t < kc) ? bq[t] : (BT)0;
+        }
+        if constexpr (!std::is_same<VT, double>::value || !std::is_same<BT, double>::value) {
+#pragma unroll
+          for (int u = 0; u < kSpmmU; ++u) {
+            asm volatile("" : "+v"(vr[u]));
+#pragma unroll
+            for (int t = 0; t < CPL; ++t) asm volatile("" : "+v"(b[u][t]));
+          }
+        }
+        // masked entries add fma(0, 0, acc) = acc exactly (acc is never -0)
+#pragma unroll
+        for (int u = 0; u < kSpmmU; ++u)
+#pragma unroll
+          for (int t = 0; t < CPL; ++t)
+            acc[t] = fma(widen(vr[u]), (double)b[u][t], acc[t]);
       }
 #pragma unroll
       for (int t = 0; t < CPL; ++t)
-        if (c0 + t < k) out[t] = acc[t];
+        if (t < kc) out[t] = acc[t];
     }
   }
 }
@@ -426,17 +460,21 @@ int launch_spmm(const Plan& p, int k, const void* B, int64_t ldb, double* C, int
                 hipStream_t s) {
   if (p.n_rows == 0) return SPMV_OK;
   const uintptr_t a = reinterpret_cast<uintptr_t>(B);
+  // column groups of 4 unless k = 2 mod 4, where groups of 2 leave no
+  // partial group (k = 6 and 10 took twice as long with a partial group of 2)
   if (p.vdt == SPMV_F64) {
     const double* b = static_cast<const double*>(B);
-    if (k >= 4 && a % 16 == 0 && ldb % 2 == 0)
+    if (k >= 4 && k % 4 != 2 && a % 16 == 0 && ldb % 2 == 0)
       return spmm_store<double, double, 4>(p, k, b, ldb, C, ldc, s);
     if (k >= 2 && a % 16 == 0 && ldb % 2 == 0)
       return spmm_store<double, double, 2>(p, k, b, ldb, C, ldc, s);
     return spmm_store<double, double, 1>(p, k, b, ldb, C, ldc, s);
   }
   const float* b = static_cast<const float*>(B);
-  if (k >= 4 && a % 16 == 0 && ldb % 4 == 0)
+  if (k >= 4 && k % 4 != 2 && a % 16 == 0 && ldb % 4 == 0)
     return spmm_store<float, float, 4>(p, k, b, ldb, C, ldc, s);
+  if (k >= 2 && a % 8 == 0 && ldb % 2 == 0)
+    return spmm_store<float, float, 2>(p, k, b, ldb, C, ldc, s);
   return spmm_store<float, float, 1>(p, k, b, ldb, C, ldc, s);
 }
 

@@ -172,7 +172,7 @@ def test_deterministic_repeats():
 
 
 @pytest.mark.parametrize("dt", ["f64", "f32"])
-@pytest.mark.parametrize("k", [1, 2, 3, 4, 5, 8, 16, 32, 33, 64, 100])
+@pytest.mark.parametrize("k", [1, 2, 3, 4, 5, 6, 8, 10, 16, 32, 33, 64, 100])
 def test_spmm_vs_oracle(k, dt):
     A = crsgen.laplace2d(256) if k <= 32 else crsgen.random_crs(3000, 2000, seed=k, max_len=50)
     Bh = crsgen.uniform_vec(A.n_cols * k, 4).reshape(A.n_cols, k)
@@ -187,14 +187,17 @@ def test_spmm_vs_oracle(k, dt):
     C = M.spmm(_gpu(Bh)).cpu().numpy()
     ok, worst = oracle.bound_ok(C, Cref, A.row_ptr, S)
     assert ok, worst
-    # padded leading dimensions (ldb, ldc > k) take the scalar path
-    Bp = torch.zeros((A.n_cols, k + 3), dtype=tdt, device=DEV)
-    Bp[:, :k] = _gpu(Bh)
-    Cp = torch.full((A.n_rows, k + 1), 7.0, dtype=torch.float64, device=DEV)
-    pkg.spmm_apply(M.handle, k, Bp, k + 3, M.code, Cp, k + 1)
-    Cp = Cp.cpu().numpy()
-    assert oracle.bound_ok(Cp[:, :k], Cref, A.row_ptr, S)[0]
-    assert np.all(Cp[:, k] == 7.0)  # untouched padding column
+    # padded leading dimensions: ldb = k + 3 takes the scalar path, ldb = k + 2
+    # the column groups its parity allows (with a partial group where k is odd)
+    for pad in (3, 2):
+        Bp = torch.zeros((A.n_cols, k + pad), dtype=tdt, device=DEV)
+        Bp[:, :k] = _gpu(Bh)
+        Cp = torch.full((A.n_rows, k + 1), 7.0, dtype=torch.float64, device=DEV)
+        pkg.spmm_apply(M.handle, k, Bp, k + pad, M.code, Cp, k + 1)
+        Cp = Cp.cpu().numpy()
+        ok, worst = oracle.bound_ok(Cp[:, :k], Cref, A.row_ptr, S)
+        assert ok, (pad, worst)
+        assert np.all(Cp[:, k] == 7.0)  # untouched padding column
 
 
 @pytest.mark.parametrize("dt", ["f64", "f32"])
