@@ -194,7 +194,9 @@ __device__ __forceinline__ void store_vec(double* p, const double* x) {
 }
 
 // VST: C rows are 16-byte aligned (vector stores of full column groups).
-template <typename VT, typename BT, int LPR, int CPL, bool VST>
+// SB: B rows are not aligned for vector loads (odd ldb, or an offset B):
+// every column group takes the scalar-load path.
+template <typename VT, typename BT, int LPR, int CPL, bool VST, bool SB>
 __global__ __launch_bounds__(kWG) void k_spmm(int32_t nrows, int32_t k,
                                               const int32_t* __restrict__ rp,
                                               const int32_t* __restrict__ ci,
@@ -210,7 +212,7 @@ __global__ __launch_bounds__(kWG) void k_spmm(int32_t nrows, int32_t k,
 #pragma unroll
     for (int t = 0; t < CPL; ++t) acc[t] = 0.0;
     double* out = C + row * ldc + c0;
-    if (c0 + CPL <= k) {
+    if (!SB && c0 + CPL <= k) {
       // full column group: vector loads of B, masked entries read nothing
       if constexpr (!std::is_same<VT, double>::value || !std::is_same<BT, double>::value) {
         // narrower types: loaded in their own type and widened only after
@@ -283,17 +285,17 @@ __global__ __launch_bounds__(kWG) void k_spmm(int32_t nrows, int32_t k,
 #pragma unroll
           for (int t = 0; t < CPL; ++t) acc[t] = fma(v[u], b[u][t], acc[t]);
       }
-      if (VST) {
+      if constexpr (VST) {
         store_vec<CPL>(out, acc);
       } else {
 #pragma unroll
         for (int t = 0; t < CPL; ++t) out[t] = acc[t];
       }
     } else {
-      // last, partial column group (k not a multiple of CPL): the same rounds
-      // of kSpmmU entries with the B elements loaded one by one (an entry at
-      // a time made each entry's loads wait for the previous entry's FMAs:
-      // k = 6 took twice as long as k = 8)
+      // last, partial column group (k not a multiple of CPL), or any group of
+      // an unaligned B: the same rounds of kSpmmU entries with the B elements
+      // loaded one by one (an entry at a time made each entry's loads wait
+      // for the previous entry's FMAs: k = 6 took twice as long as k = 8)
       const int32_t kc = k - c0;
       for (int32_t j = s; j < e; j += kSpmmU) {
         VT vr[kSpmmU];
@@ -400,7 +402,7 @@ int spmv_typed(const Plan& p, int variant, const BT* B, double* C, hipStream_t s
   return SPMV_OK;
 }
 
-template <typename VT, typename BT, int CPL, bool VST>
+template <typename VT, typename BT, int CPL, bool VST, bool SB>
 int spmm_lpr(const Plan& p, int k, const BT* B, int64_t ldb, double* C, int64_t ldc,
              hipStream_t s) {
   const VT* val = static_cast<const VT*>(p.val);
@@ -410,7 +412,7 @@ int spmm_lpr(const Plan& p, int k, const BT* B, int64_t ldb, double* C, int64_t 
   while (lpr < need && lpr < 64) lpr *= 2;
 #define SPMM_CASE(L)                                                                        \
   case L:                                                                                   \
-    k_spmm<VT, BT, L, CPL, VST><<<grid_for((int64_t)n * L), kWG, 0, s>>>(                   \
+    k_spmm<VT, BT, L, CPL, VST, SB><<<grid_for((int64_t)n * L), kWG, 0, s>>>(               \
         n, k, p.row_ptr, p.col_idx, val, B, ldb, C, ldc);                                   \
     break;
   switch (lpr) {
@@ -427,12 +429,12 @@ int spmm_lpr(const Plan& p, int k, const BT* B, int64_t ldb, double* C, int64_t 
   return SPMV_OK;
 }
 
-template <typename VT, typename BT, int CPL>
+template <typename VT, typename BT, int CPL, bool SB = false>
 int spmm_store(const Plan& p, int k, const BT* B, int64_t ldb, double* C, int64_t ldc,
                hipStream_t s) {
   const bool vst = CPL > 1 && reinterpret_cast<uintptr_t>(C) % 16 == 0 && ldc % 2 == 0;
-  return vst ? spmm_lpr<VT, BT, CPL, (CPL > 1)>(p, k, B, ldb, C, ldc, s)
-             : spmm_lpr<VT, BT, CPL, false>(p, k, B, ldb, C, ldc, s);
+  return vst ? spmm_lpr<VT, BT, CPL, (CPL > 1), SB>(p, k, B, ldb, C, ldc, s)
+             : spmm_lpr<VT, BT, CPL, false, SB>(p, k, B, ldb, C, ldc, s);
 }
 
 template <typename VT, typename BT>
@@ -468,6 +470,11 @@ int launch_spmm(const Plan& p, int k, const void* B, int64_t ldb, double* C, int
       return spmm_store<double, double, 4>(p, k, b, ldb, C, ldc, s);
     if (k >= 2 && a % 16 == 0 && ldb % 2 == 0)
       return spmm_store<double, double, 2>(p, k, b, ldb, C, ldc, s);
+    // B rows not aligned for vector loads (odd ldb): from k = 5 on, groups
+    // of 4 columns with scalar loads (one column per lane re-reads every
+    // row's entries in each of up to 16 lanes: k = 9 took 1.5x as long on a
+    // 3M-row matrix; for k = 3 one column per lane was 14% faster)
+    if (k >= 5) return spmm_store<double, double, 4, true>(p, k, b, ldb, C, ldc, s);
     return spmm_store<double, double, 1>(p, k, b, ldb, C, ldc, s);
   }
   const float* b = static_cast<const float*>(B);
@@ -475,6 +482,9 @@ int launch_spmm(const Plan& p, int k, const void* B, int64_t ldb, double* C, int
     return spmm_store<float, float, 4>(p, k, b, ldb, C, ldc, s);
   if (k >= 2 && a % 8 == 0 && ldb % 2 == 0)
     return spmm_store<float, float, 2>(p, k, b, ldb, C, ldc, s);
+  // unaligned float32 rows: scalar groups of 4 from k = 9 on (k = 5 and 7
+  // ran 15-18% faster with one column per lane)
+  if (k >= 9) return spmm_store<float, float, 4, true>(p, k, b, ldb, C, ldc, s);
   return spmm_store<float, float, 1>(p, k, b, ldb, C, ldc, s);
 }
 
