@@ -432,9 +432,13 @@ int spmm_apply(spmv_handle h, int32_t k, const void* B, int64_t ldb, int b_dtype
     return fail(SPMV_ERR_INVALID_ARG, "B or C is null");
   if ((int64_t)p.n_rows * ldc > INT64_MAX / 2) return fail(SPMV_ERR_UNSUPPORTED, "C too large");
   // a plan running V6 multiplies up to 8 right-hand sides from its chunked copy
-  // (one pass over it); wider blocks use the row-group kernel, which reads
-  // the matrix once for any k
-  if (p.variant == SPMV_V6_SELL64 && p.sell_ok && k <= 8)
+  // (one pass over it) when its rows average at least 8 entries; wider blocks
+  // use the row-group kernel, which reads the matrix once for any k, and so
+  // do short rows, where its lane groups keep more rows in flight than one
+  // lane per row (5-point Laplacians, 262k and 1M rows: the copy took 1.1-1.3x
+  // as long at k = 4 and 1.5-1.8x at k = 8; a 15-entry-per-row matrix ran
+  // 1.1-2x faster from the copy)
+  if (p.variant == SPMV_V6_SELL64 && p.sell_ok && k <= 8 && p.nnz >= 8 * p.n_rows)
     return launch_sell_spmm(p, k, B, ldb, C, ldc, as_stream(stream));
   return launch_spmm(p, k, B, ldb, C, ldc, as_stream(stream));
 }

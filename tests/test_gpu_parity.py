@@ -205,8 +205,10 @@ def test_spmm_vs_oracle(k, dt):
 @pytest.mark.parametrize("name", ["hamiltonian_200k", "laplace2d_256"])
 def test_spmm_from_v6_copy(name, k, dt):
     """A plan running V6 multiplies blocks of right-hand sides from its chunked
-    copy (column blocks of up to 8, vector loads of B row segments, a scalar
-    partial last block); also with padded leading dimensions."""
+    copy when its rows average at least 8 entries (column blocks of up to 8,
+    vector loads of B row segments, a scalar partial last block), else with
+    the row-group kernel (the 5-point Laplacian); also with padded leading
+    dimensions."""
     A, _ = case(name)
     Bh = crsgen.uniform_vec(A.n_cols * k, 5).reshape(A.n_cols, k)
     tdt = torch.float32 if dt == "f32" else torch.float64
@@ -643,7 +645,8 @@ def test_sell_deltas_bitwise_equal_wide(name, dt):
         M.variant = 6
         narrow.append(M.sell_deltas)
         outs.append(M.apply(Bd).cpu().numpy())
-        mm.append([M.spmm(Bk[k]).cpu().numpy() for k in (3, 8)])  # from the copy (k <= 8)
+        # from the copy where rows average at least 8 entries (k <= 8)
+        mm.append([M.spmm(Bk[k]).cpu().numpy() for k in (3, 8)])
     assert narrow[1][:2] == (0, 0)
     for x, y in zip(mm[0], mm[1]):
         assert np.array_equal(x, y)
