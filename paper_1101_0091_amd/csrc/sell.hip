@@ -545,7 +545,7 @@ __global__ __launch_bounds__(kWG) void k_sell_quads(int64_t nch, int64_t n,
 // shrink with KB to bound the registers in flight (16 up to KB = 4, 8 for
 // KB = 8: a round of 15 entries or fewer is one round of loads). DB > 0
 // reads the columns through the chunk's DB-bit deltas.
-template <typename VT, typename BT, int KB, bool VEC, int DB>
+template <typename VT, typename BT, int KB, int VEC, int DB>
 __device__ __forceinline__ void sell_spmm_rows(int64_t a, int32_t w, int lane, int32_t kc,
                                                int32_t c0, const int32_t* __restrict__ sci,
                                                const uint16_t* __restrict__ sdl,
@@ -606,7 +606,7 @@ __device__ __forceinline__ void sell_spmm_rows(int64_t a, int32_t w, int lane, i
 #pragma unroll
       for (int u = 0; u < U; ++u) {
         const BT* bq = B + (int64_t)(c[u] >= 0 ? c[u] : 0) * ldb + c0;
-        if constexpr (VEC && KB >= 2) {
+        if constexpr (VEC == 1 && KB >= 2) {
           // one 8-byte (KB = 2) or 16-byte load per 4 columns of the segment
           if (c[u] >= 0) {
             if constexpr (KB == 2) {
@@ -626,6 +626,19 @@ __device__ __forceinline__ void sell_spmm_rows(int64_t a, int32_t w, int lane, i
           } else {
 #pragma unroll
             for (int t = 0; t < KB; ++t) xb[u][t] = (BT)0;
+          }
+        } else if constexpr (VEC == 2) {
+          // partial block: 8-byte pairs of the kc columns, the odd last one alone
+#pragma unroll
+          for (int t = 0; t < KB; t += 2) {
+            if (c[u] >= 0 && t + 1 < kc) {
+              const f32x2 q = *reinterpret_cast<const f32x2*>(bq + t);
+              xb[u][t] = q.x;
+              xb[u][t + 1] = q.y;
+            } else {
+              xb[u][t] = (c[u] >= 0 && t < kc) ? bq[t] : (BT)0;
+              xb[u][t + 1] = (BT)0;
+            }
           }
         } else {
 #pragma unroll
@@ -653,7 +666,7 @@ __device__ __forceinline__ void sell_spmm_rows(int64_t a, int32_t w, int lane, i
 #pragma unroll
     for (int u = 0; u < U; ++u) {
       const BT* bq = B + (int64_t)(c[u] >= 0 ? c[u] : 0) * ldb + c0;
-      if constexpr (VEC && KB >= 2 && std::is_same<BT, double>::value) {
+      if constexpr (VEC == 1 && KB >= 2 && std::is_same<BT, double>::value) {
         if (c[u] >= 0) {
 #pragma unroll
           for (int t = 0; t < KB; t += 2) {
@@ -664,6 +677,19 @@ __device__ __forceinline__ void sell_spmm_rows(int64_t a, int32_t w, int lane, i
         } else {
 #pragma unroll
           for (int t = 0; t < KB; ++t) x[u][t] = 0.0;
+        }
+      } else if constexpr (VEC == 2) {
+        // partial block: 16-byte pairs of the kc columns, the odd last one alone
+#pragma unroll
+        for (int t = 0; t < KB; t += 2) {
+          if (c[u] >= 0 && t + 1 < kc) {
+            const f64x2 q = *reinterpret_cast<const f64x2*>(bq + t);
+            x[u][t] = q.x;
+            x[u][t + 1] = q.y;
+          } else {
+            x[u][t] = (c[u] >= 0 && t < kc) ? (double)bq[t] : 0.0;
+            x[u][t + 1] = 0.0;
+          }
         }
       } else {
 #pragma unroll
@@ -679,7 +705,7 @@ __device__ __forceinline__ void sell_spmm_rows(int64_t a, int32_t w, int lane, i
 }
 
 // flag is null when the plan keeps 4-byte columns only.
-template <typename VT, typename BT, int KB, bool VEC>
+template <typename VT, typename BT, int KB, int VEC>
 __global__ __launch_bounds__(kWG) void k_sell_spmm(int64_t nch, int64_t n,
                                                    const int32_t* __restrict__ off,
                                                    const int32_t* __restrict__ sci,
@@ -758,7 +784,7 @@ int launch_sell_build(Plan& p, hipStream_t s) {
 }
 
 namespace {
-template <typename VT, typename BT, int KB, bool VEC>
+template <typename VT, typename BT, int KB, int VEC>
 int sell_spmm_pass(const Plan& p, int k, int c0, const BT* B, int64_t ldb, double* C, int64_t ldc,
                    hipStream_t s) {
   k_sell_spmm<VT, BT, KB, VEC><<<grid_chunks(p.sell_nch), kWG, 0, s>>>(
@@ -780,23 +806,28 @@ int sell_spmm_typed(const Plan& p, int k, const BT* B, int64_t ldb, double* C, i
   const bool vec = KB >= 2 && (std::is_same<BT, double>::value ? ba % 16 == 0 && ldb % 2 == 0
                                : KB == 2 ? ba % 8 == 0 && ldb % 2 == 0
                                          : ba % 16 == 0 && ldb % 4 == 0);
+  // a partial block of 8 (k = 5..7) loads pairs where rows are aligned to them
+  const bool pairs = std::is_same<BT, double>::value ? ba % 16 == 0 && ldb % 2 == 0
+                                                     : ba % 8 == 0 && ldb % 2 == 0;
   for (int c0 = 0; c0 < k; c0 += KB) {
-    // a full-width block takes the vector path; a partial last block the scalar one
+    // a full-width block takes the vector path; a partial last block of 8
+    // pairs and a scalar last column, other partial blocks scalar loads
     const bool full = c0 + KB <= k;
     int st = SPMV_OK;
     switch (KB) {
-      case 1: st = sell_spmm_pass<VT, BT, 1, false>(p, k, c0, B, ldb, C, ldc, s); break;
+      case 1: st = sell_spmm_pass<VT, BT, 1, 0>(p, k, c0, B, ldb, C, ldc, s); break;
       case 2:
-        st = vec && full ? sell_spmm_pass<VT, BT, 2, true>(p, k, c0, B, ldb, C, ldc, s)
-                         : sell_spmm_pass<VT, BT, 2, false>(p, k, c0, B, ldb, C, ldc, s);
+        st = vec && full ? sell_spmm_pass<VT, BT, 2, 1>(p, k, c0, B, ldb, C, ldc, s)
+                         : sell_spmm_pass<VT, BT, 2, 0>(p, k, c0, B, ldb, C, ldc, s);
         break;
       case 4:
-        st = vec && full ? sell_spmm_pass<VT, BT, 4, true>(p, k, c0, B, ldb, C, ldc, s)
-                         : sell_spmm_pass<VT, BT, 4, false>(p, k, c0, B, ldb, C, ldc, s);
+        st = vec && full ? sell_spmm_pass<VT, BT, 4, 1>(p, k, c0, B, ldb, C, ldc, s)
+                         : sell_spmm_pass<VT, BT, 4, 0>(p, k, c0, B, ldb, C, ldc, s);
         break;
       default:
-        st = vec && full ? sell_spmm_pass<VT, BT, 8, true>(p, k, c0, B, ldb, C, ldc, s)
-                         : sell_spmm_pass<VT, BT, 8, false>(p, k, c0, B, ldb, C, ldc, s);
+        st = vec && full    ? sell_spmm_pass<VT, BT, 8, 1>(p, k, c0, B, ldb, C, ldc, s)
+             : pairs && !full ? sell_spmm_pass<VT, BT, 8, 2>(p, k, c0, B, ldb, C, ldc, s)
+                              : sell_spmm_pass<VT, BT, 8, 0>(p, k, c0, B, ldb, C, ldc, s);
     }
     if (st) return st;
   }

@@ -201,7 +201,7 @@ def test_spmm_vs_oracle(k, dt):
 
 
 @pytest.mark.parametrize("dt", ["f64", "f32"])
-@pytest.mark.parametrize("k", [1, 2, 3, 4, 5, 8, 9, 16, 17])
+@pytest.mark.parametrize("k", [1, 2, 3, 4, 5, 6, 7, 8, 9, 16, 17])
 @pytest.mark.parametrize("name", ["hamiltonian_200k", "laplace2d_256"])
 def test_spmm_from_v6_copy(name, k, dt):
     """A plan running V6 multiplies blocks of right-hand sides from its chunked
@@ -231,7 +231,7 @@ def test_spmm_from_v6_copy(name, k, dt):
 
 
 @pytest.mark.parametrize("dt", ["f64", "f32"])
-@pytest.mark.parametrize("k", [2, 4, 8, 16])
+@pytest.mark.parametrize("k", [2, 4, 6, 8, 16])
 def test_spmm_from_v6_copy_misaligned_B(k, dt):
     """B starting 1 or 2 elements past an aligned address: the vector loads of
     B row segments need 16 bytes of alignment (8 for float32 pairs), and a B
