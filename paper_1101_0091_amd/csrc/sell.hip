@@ -806,12 +806,12 @@ int sell_spmm_typed(const Plan& p, int k, const BT* B, int64_t ldb, double* C, i
   const bool vec = KB >= 2 && (std::is_same<BT, double>::value ? ba % 16 == 0 && ldb % 2 == 0
                                : KB == 2 ? ba % 8 == 0 && ldb % 2 == 0
                                          : ba % 16 == 0 && ldb % 4 == 0);
-  // a partial block of 8 (k = 5..7) loads pairs where rows are aligned to them
+  // a partial block (k = 3, 5..7) loads pairs where rows are aligned to them
   const bool pairs = std::is_same<BT, double>::value ? ba % 16 == 0 && ldb % 2 == 0
                                                      : ba % 8 == 0 && ldb % 2 == 0;
   for (int c0 = 0; c0 < k; c0 += KB) {
-    // a full-width block takes the vector path; a partial last block of 8
-    // pairs and a scalar last column, other partial blocks scalar loads
+    // a full-width block takes the vector path; a partial last block pairs
+    // and a scalar last column (scalar loads where rows are not aligned)
     const bool full = c0 + KB <= k;
     int st = SPMV_OK;
     switch (KB) {
@@ -821,8 +821,9 @@ int sell_spmm_typed(const Plan& p, int k, const BT* B, int64_t ldb, double* C, i
                          : sell_spmm_pass<VT, BT, 2, 0>(p, k, c0, B, ldb, C, ldc, s);
         break;
       case 4:
-        st = vec && full ? sell_spmm_pass<VT, BT, 4, 1>(p, k, c0, B, ldb, C, ldc, s)
-                         : sell_spmm_pass<VT, BT, 4, 0>(p, k, c0, B, ldb, C, ldc, s);
+        st = vec && full    ? sell_spmm_pass<VT, BT, 4, 1>(p, k, c0, B, ldb, C, ldc, s)
+             : pairs && !full ? sell_spmm_pass<VT, BT, 4, 2>(p, k, c0, B, ldb, C, ldc, s)
+                              : sell_spmm_pass<VT, BT, 4, 0>(p, k, c0, B, ldb, C, ldc, s);
         break;
       default:
         st = vec && full    ? sell_spmm_pass<VT, BT, 8, 1>(p, k, c0, B, ldb, C, ldc, s)
