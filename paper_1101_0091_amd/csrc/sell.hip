@@ -539,12 +539,14 @@ __global__ __launch_bounds__(kWG) void k_sell_quads(int64_t nch, int64_t n,
 
 // Multi-RHS form from the chunked copy: C[i, c0 + t] = sum_j val(j) B[col(j), c0 + t]
 // for t < kc = min(KB, k - c0). Lane l of chunk k owns row 64 k + l and keeps
-// KB accumulators; every slot gathers the row segment B[col, c0 .. c0 + KB)
-// (vector loads when VEC: 16-byte for float64 pairs and float32 quads, 8-byte
-// for float32 pairs, on rows and segments aligned to them). Slots per round
-// shrink with KB to bound the registers in flight (16 up to KB = 4, 8 for
-// KB = 8: a round of 15 entries or fewer is one round of loads). DB > 0
-// reads the columns through the chunk's DB-bit deltas.
+// KB accumulators; every slot gathers the row segment B[col, c0 .. c0 + KB).
+// VEC = 1: vector loads of a full segment (16-byte for float64 pairs and
+// float32 quads, 8-byte for float32 pairs); VEC = 2: a partial segment
+// (kc < KB) in pairs with its odd last column alone; VEC = 0: scalar loads.
+// Both vector forms need rows and segments aligned to the load. Slots per
+// round shrink with KB to bound the registers in flight (16 up to KB = 4, 8
+// for KB = 8, so a row of up to 16 or 8 entries is one round of loads).
+// DB > 0 reads the columns through the chunk's DB-bit deltas.
 template <typename VT, typename BT, int KB, int VEC, int DB>
 __device__ __forceinline__ void sell_spmm_rows(int64_t a, int32_t w, int lane, int32_t kc,
                                                int32_t c0, const int32_t* __restrict__ sci,
