@@ -105,8 +105,8 @@ typedef enum {
  * with the others. */
 #define SPMV_FLAG_SELL 0x20000u
 /* V4 in its B-staging form: each row block copies a range of B into LDS (its
- * exact column span when that fits 2048 entries, else the 2048 columns around
- * its rows) and gathers from it where it can. By default a plan stages when at
+ * exact column span when that fits 2048 entries, 4096 for float32 plans, else
+ * that many columns around its rows) and gathers from it where it can. By default a plan stages when at
  * least a quarter of its blocks fit exactly, and autotune times both forms;
  * these flags force one form (setting both is SPMV_ERR_INVALID_ARG). */
 #define SPMV_FLAG_V4_STAGE_ON 0x40000u

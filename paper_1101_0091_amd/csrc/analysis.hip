@@ -326,8 +326,8 @@ __global__ void k_blocks(int64_t n, int64_t nblocks, const int32_t* __restrict__
 
 // Staging range of every row block (one workgroup per block): the exact
 // column bounds of its chunk [S, min(E, S + budget)) when they span at most
-// the LDS array (counted in staged_blocks), else a budget-wide window of
-// columns: of kWinCand windows starting at the one centred on the block's
+// W, the B entries the LDS array holds (counted in staged_blocks), else a
+// W-wide window of columns: of kWinCand windows starting at the one centred on the block's
 // rows shifted by multiples of kWinStep columns (clamped to [0, n_cols)), the
 // one holding most of the chunk's entries (ties to the least shift). S and E
 // are clamped to [0, nnz] so an invalid pattern (reported by validation in
@@ -337,7 +337,8 @@ constexpr int kWinStep = 256;   // shift between candidates, in columns
 __global__ __launch_bounds__(kWG) void k_block_spans(int64_t nblocks, int64_t nnz, int64_t n_cols,
                                                      const int2* __restrict__ blocks,
                                                      const int32_t* __restrict__ ci,
-                                                     int2* __restrict__ spans, WsHeader* h) {
+                                                     int2* __restrict__ spans, WsHeader* h,
+                                                     int32_t W) {
   __shared__ int32_t lo[kWG / 64], hi[kWG / 64];
   const int64_t b = blockIdx.x;
   if (b >= nblocks) return;
@@ -381,7 +382,7 @@ __global__ __launch_bounds__(kWG) void k_block_spans(int64_t nblocks, int64_t nn
     hi[0] = z;
     if (a > z) {
       spans[b] = make_int2(0, -1);  // empty chunk: nothing staged
-    } else if ((int64_t)z - a < kBlockBudget) {
+    } else if ((int64_t)z - a < W) {
       spans[b] = make_int2(a, z);
       atomicAdd(&h->staged_blocks, 1);
     }
@@ -389,13 +390,13 @@ __global__ __launch_bounds__(kWG) void k_block_spans(int64_t nblocks, int64_t nn
   // wide chunk: every lane counts its entries inside each candidate window
   __syncthreads();
   const int32_t a0 = lo[0], z0 = hi[0];
-  if (!(a0 <= z0) || (int64_t)z0 - a0 < kBlockBudget) return;  // block-uniform
+  if (!(a0 <= z0) || (int64_t)z0 - a0 < W) return;  // block-uniform
   const int64_t mid = ((int64_t)blocks[b].x + blocks[b + 1].x) / 2;
   int64_t w0c[kWinCand];
   int32_t cnt[kWinCand];
   for (int q = 0; q < kWinCand; ++q) {
-    int64_t w0 = mid - kBlockBudget / 2 + (int64_t)(q - kWinCand / 2) * kWinStep;
-    w0 = w0 + kBlockBudget > n_cols ? n_cols - kBlockBudget : w0;
+    int64_t w0 = mid - W / 2 + (int64_t)(q - kWinCand / 2) * kWinStep;
+    w0 = w0 + W > n_cols ? n_cols - W : w0;
     w0c[q] = w0 < 0 ? 0 : w0;
     cnt[q] = 0;
   }
@@ -403,7 +404,7 @@ __global__ __launch_bounds__(kWG) void k_block_spans(int64_t nblocks, int64_t nn
   for (int u = 0; u < kPer; ++u) {
     if (S + threadIdx.x + (int64_t)u * kWG < E) {
       const int64_t c = cc[u];
-      for (int q = 0; q < kWinCand; ++q) cnt[q] += c >= w0c[q] && c < w0c[q] + kBlockBudget;
+      for (int q = 0; q < kWinCand; ++q) cnt[q] += c >= w0c[q] && c < w0c[q] + W;
     }
   }
   __shared__ int32_t wc[kWG / 64][kWinCand];
@@ -425,7 +426,7 @@ __global__ __launch_bounds__(kWG) void k_block_spans(int64_t nblocks, int64_t nn
         best = q;
       }
     }
-    const int64_t w1 = w0c[best] + kBlockBudget < n_cols ? w0c[best] + kBlockBudget : n_cols;
+    const int64_t w1 = w0c[best] + W < n_cols ? w0c[best] + W : n_cols;
     spans[b] = w0c[best] < w1 ? make_int2((int32_t)w0c[best], (int32_t)(w1 - 1))
                               : make_int2(0, -1);
   }
@@ -470,8 +471,10 @@ int launch_analysis(Plan& p, const float* mu, const float* sigma, hipStream_t s)
                                                                p.blocks);
     SPMV_HIP(hipGetLastError());
     if (p.nblocks > 0) {
-      k_block_spans<<<(unsigned)p.nblocks, kWG, 0, s>>>(p.nblocks, p.nnz, p.n_cols, p.blocks,
-                                                        p.col_idx, p.spans, p.hdr);
+      // W: the B entries a block stages (twice as many for float32 values)
+      k_block_spans<<<(unsigned)p.nblocks, kWG, 0, s>>>(
+          p.nblocks, p.nnz, p.n_cols, p.blocks, p.col_idx, p.spans, p.hdr,
+          p.vdt == SPMV_F64 ? kStageEntries<double> : kStageEntries<float>);
       SPMV_HIP(hipGetLastError());
     }
   }

@@ -16,6 +16,10 @@ namespace spmv {
 
 constexpr int kWG = 256;          // threads per workgroup for the streaming kernels
 constexpr int kBlockBudget = 2048;  // rows + in-chunk nonzeros of one LDS row block
+// B entries a V4 row block stages in its kBlockBudget doubles of LDS: float32
+// B is staged as float32, so twice as many.
+template <typename BT>
+constexpr int kStageEntries = sizeof(BT) == 4 ? 2 * kBlockBudget : kBlockBudget;
 constexpr int kNumXCD = 8;        // MI355X: 8 accelerator complex dies, one L2 each
 constexpr int kNumBins = 5;       // row-length bins of the binned variant
 // batch tile record: matrix, r0, r1, S, E, staging cmin, cmax, column-delta bits (0, 8 or 16),

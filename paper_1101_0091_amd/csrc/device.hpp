@@ -240,8 +240,11 @@ __device__ __forceinline__ void lds_block(BlockLds& L, const int32_t* __restrict
   const int32_t nin = cend - S;
   const bool tail = E > cend;
   const int32_t span = cmax - cmin + 1;
+  // float32 B is staged as float32 (stage_cap up to 2 kBlockBudget entries
+  // in the same LDS); the batch's unrolled staging holds kBlockBudget
+  constexpr bool kStageF = std::is_same<BT, float>::value && !DELTA;
   const bool staged = STAGE && stage && cmin <= cmax && span <= stage_cap &&
-                      span <= kBlockBudget;
+                      span <= (kStageF ? 2 : 1) * kBlockBudget;
 
   // phase 1: products of the chunk into LDS; all loads issued before use
   constexpr int kPer = kBlockBudget / kWG;
@@ -278,7 +281,10 @@ __device__ __forceinline__ void lds_block(BlockLds& L, const int32_t* __restrict
   double b[kPer];
   if constexpr (STAGE) {
     if (staged) {
-      if constexpr (!DELTA) {
+      if constexpr (kStageF) {
+        float* sf = reinterpret_cast<float*>(stage);
+        for (int32_t k = tid; k < span; k += kWG) sf[k] = B[cmin + k];
+      } else if constexpr (!DELTA) {
         for (int32_t k = tid; k < span; k += kWG) stage[k] = widen(B[cmin + k]);
       } else {
         // the batch's tiles: span <= stage_cap <= kPer * kWG, every load
@@ -312,8 +318,15 @@ __device__ __forceinline__ void lds_block(BlockLds& L, const int32_t* __restrict
           // fold it and the global load into one flat load from a selected
           // address (flat loads also wait on the LDS counter)
           const bool in = c[u] >= cmin && c[u] <= cmax;
-          double xs = stage[in ? c[u] - cmin : 0];
-          asm volatile("" : "+v"(xs));
+          double xs;
+          if constexpr (kStageF) {
+            float xf = reinterpret_cast<const float*>(stage)[in ? c[u] - cmin : 0];
+            asm volatile("" : "+v"(xf));
+            xs = (double)xf;
+          } else {
+            xs = stage[in ? c[u] - cmin : 0];
+            asm volatile("" : "+v"(xs));
+          }
           double xg = 0.0;
           if (!in) xg = widen(B[c[u]]);
           b[u] = in ? xs : xg;

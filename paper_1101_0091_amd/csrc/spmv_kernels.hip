@@ -129,8 +129,9 @@ __global__ __launch_bounds__(kWG) void k_lds_block_staged(int64_t nblocks,
   const int64_t b = dev::xcd_remap(blockIdx.x, nblocks);
   const int2 m0 = blocks[b], m1 = blocks[b + 1], sp = spans[b];
   if (m0.x >= m1.x) return;
+  // float32 B: twice the entries in the same LDS (the spans were chosen for it)
   dev::lds_block<VT, BT, ACC, true>(L, rp, ci, val, B, C, m0.x, m1.x, m0.y, m1.y, sp.x, sp.y,
-                                    L.prod, kBlockBudget);
+                                    L.prod, kStageEntries<BT>);
 }
 
 template <typename VT, typename BT, bool ACC>
