@@ -111,6 +111,16 @@ typedef enum {
  * these flags force one form (setting both is SPMV_ERR_INVALID_ARG). */
 #define SPMV_FLAG_V4_STAGE_ON 0x40000u
 #define SPMV_FLAG_V4_STAGE_OFF 0x80000u
+/* V4 in its window form: super-blocks of 4096 rows, one 1024-lane workgroup
+ * each, that copy the three (float32 plans: six) most used aligned 4096-column
+ * windows of B into LDS and gather from them where they can; each wavefront
+ * streams 256 rows on its own and adds every row's products in CRS order (a
+ * row with more than 64 entries in one 512-entry chunk is summed by its
+ * wavefront as a tree). The windows are chosen at create from the columns of
+ * each super-block. By default a plan takes this form when the windows hold
+ * at least three quarters of the nonzeros and fewer than a quarter of the
+ * row blocks fit the staging form exactly. Exclusive with the two flags above. */
+#define SPMV_FLAG_V4_WINDOWS 0x200000u
 /* With SPMV_FLAG_SELL: read every chunk of the V6 copy through its 4-byte
  * columns (the deltas are not built). Without SPMV_FLAG_SELL it is
  * SPMV_ERR_INVALID_ARG. */
@@ -195,6 +205,13 @@ int spmv_get_sell_deltas(spmv_handle h, int64_t* chunks8, int64_t* chunks16, int
 /* Whether V4 runs in its B-staging form (host out: 1 or 0; see
  * SPMV_FLAG_V4_STAGE_ON). */
 int spmv_get_v4_staged(spmv_handle h, int* staged);
+/* The three forms of V4: the same row blocks and sums, different B access. */
+typedef enum { SPMV_V4_PLAIN = 0, SPMV_V4_STAGED = 1, SPMV_V4_WINDOWS = 2 } spmv_v4_form;
+/* The V4 form in use (host out), and the nonzeros whose column lies in their
+ * super-block's windows (host out, may be null). */
+int spmv_get_v4_form(spmv_handle h, int* form, int64_t* win_covered);
+/* Switch the V4 form of a plan (every table is built at create). */
+int spmv_set_v4_form(spmv_handle h, int form);
 /* Number of row blocks of the LDS-block variant (host out). */
 int spmv_get_num_blocks(spmv_handle h, int64_t* nblocks);
 int spmv_destroy(spmv_handle h);

@@ -33,6 +33,9 @@ SPMV_FLAG_SELL = 0x20000
 SPMV_FLAG_V4_STAGE_ON = 0x40000
 SPMV_FLAG_V4_STAGE_OFF = 0x80000
 SPMV_FLAG_SELL_WIDE = 0x100000
+SPMV_FLAG_V4_WINDOWS = 0x200000
+SPMV_V4_PLAIN, SPMV_V4_STAGED, SPMV_V4_WINDOWS = 0, 1, 2
+V4_FORMS = ("plain", "staged", "windows")
 SPMV_BATCH_DYNAMIC, SPMV_BATCH_STATIC, SPMV_BATCH_TILE_GRID = 0, 1, 2
 SPMV_NUM_FEATURES = 16
 SPMV_MLP_PARAMS = 5638
@@ -40,7 +43,7 @@ SPMV_MLP_PARAMS = 5638
 EXPORTS = (
     "spmv_workspace_size", "spmv_create", "spmv_apply", "spmm_apply", "spmv_get_variant",
     "spmv_set_variant", "spmv_get_features", "spmv_get_predictions", "spmv_get_autotune_times",
-    "spmv_get_num_blocks", "spmv_get_sell_slots", "spmv_get_sell_deltas", "spmv_get_v4_staged", "spmv_destroy", "spmv_batch_workspace_size", "spmv_batch_create",
+    "spmv_get_num_blocks", "spmv_get_sell_slots", "spmv_get_sell_deltas", "spmv_get_v4_staged", "spmv_get_v4_form", "spmv_set_v4_form", "spmv_destroy", "spmv_batch_workspace_size", "spmv_batch_create",
     "spmv_batch_apply", "spmv_batch_apply_each", "spmv_batch_get_num_tiles", "spmv_batch_set_mode",
     "spmv_batch_destroy", "spmv_graph_begin", "spmv_graph_end", "spmv_graph_launch",
     "spmv_graph_destroy", "spmv_selector_load", "spmv_selector_loaded",
@@ -91,6 +94,8 @@ def lib():
             "spmv_get_sell_slots": [P, P],
             "spmv_get_sell_deltas": [P, P, P, P],
             "spmv_get_v4_staged": [P, P],
+            "spmv_get_v4_form": [P, P, P],
+            "spmv_set_v4_form": [P, ctypes.c_int],
             "spmv_destroy": [P],
             "spmv_batch_workspace_size": [i32, i64, i64, P],
             "spmv_batch_create": [P, i32, P, P, P, P, P, P, ctypes.c_int, P, sz, P],
@@ -261,6 +266,18 @@ def spmv_get_v4_staged(h) -> bool:
     v = ctypes.c_int(0)
     _check(lib().spmv_get_v4_staged(h, ctypes.byref(v)))
     return bool(v.value)
+
+
+def spmv_get_v4_form(h):
+    """(V4 form in use: SPMV_V4_PLAIN / _STAGED / _WINDOWS, nonzeros inside
+    the windows of their super-block)."""
+    f, n = ctypes.c_int(0), ctypes.c_int64(0)
+    _check(lib().spmv_get_v4_form(h, ctypes.byref(f), ctypes.byref(n)))
+    return int(f.value), int(n.value)
+
+
+def spmv_set_v4_form(h, form: int) -> None:
+    _check(lib().spmv_set_v4_form(h, int(form)))
 
 
 def spmv_destroy(h) -> None:

@@ -10,7 +10,7 @@ CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 SO = os.path.join(HERE, "libspmv.so")
 SOURCES = ["api.hip", "analysis.hip", "spmv_kernels.hip", "batch.hip", "mlp.hip", "stream.hip",
-           "split.hip", "reorder.hip", "solver.hip", "sell.hip"]
+           "split.hip", "reorder.hip", "solver.hip", "sell.hip", "window.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 FLAGS = [

@@ -29,7 +29,7 @@ int dtype_bytes(int dt) { return dt == SPMV_F64 ? 8 : 4; }
 bool dtype_ok(int dt) { return dt == SPMV_F64 || dt == SPMV_F32; }
 
 struct PlanLayout {
-  size_t header = 0, blocks = 0, spans = 0, bins = 0, stats = 0, bin_base = 0, at_B = 0, at_C = 0;
+  size_t header = 0, blocks = 0, spans = 0, win = 0, bins = 0, stats = 0, bin_base = 0, at_B = 0, at_C = 0;
   size_t sell_width = 0, sell_off = 0, sell_partials = 0, sell_ci = 0, sell_val = 0;
   size_t sell_base = 0, sell_dl = 0, sell_flag = 0;
   size_t total = 0;
@@ -45,6 +45,8 @@ PlanLayout plan_layout(int64_t n_rows, int64_t n_cols, int64_t nnz, uint32_t fla
   o += align256(sizeof(int2) * (size_t)(nb + 1));
   L.spans = o;
   o += align256(sizeof(int2) * (size_t)std::max<int64_t>(nb, 1));
+  L.win = o;
+  o += align256(sizeof(int32_t) * kWinMax * (size_t)std::max<int64_t>(super_block_count(n_rows), 1));
   L.bins = o;
   o += align256(sizeof(int32_t) * (size_t)std::max<int64_t>(n_rows, 1));
   L.stats = o;
@@ -116,12 +118,13 @@ int autotune(Plan& p, hipStream_t s) {
       p.at_us[v] = INFINITY;
       continue;
     }
-    // V4 is timed in both forms (with and without B staging); the faster stays
-    const int forms = v == SPMV_V4_LDS_BLOCK && p.nblocks > 0 && !p.v4_stage_forced ? 2 : 1;
-    const bool staged0 = p.v4_staged;
-    float form_med[2] = {INFINITY, INFINITY};
+    // V4 is timed in its three forms (plain, B staged per row block, B windows
+    // per super-block); the fastest stays
+    const int forms = v == SPMV_V4_LDS_BLOCK && p.nblocks > 0 && !p.v4_form_forced ? 3 : 1;
+    const int form0 = p.v4_form;
+    float form_med[3] = {INFINITY, INFINITY, INFINITY};
     for (int f = 0; f < forms && !st; ++f) {
-      if (forms == 2) p.v4_staged = f == 1;
+      if (forms == 3) p.v4_form = f;
       st = launch_spmv(p, v, p.at_B, p.at_C, s);
       if (st) break;
       float ms[kReps];
@@ -137,8 +140,8 @@ int autotune(Plan& p, hipStream_t s) {
       best = std::min(best, form_med[f]);
     }
     if (st) break;
-    p.v4_staged = forms == 2 ? form_med[1] < form_med[0] : staged0;
-    p.at_us[v] = 1000.0 * std::min(form_med[0], form_med[1]);
+    p.v4_form = forms == 3 ? (int)(std::min_element(form_med, form_med + 3) - form_med) : form0;
+    p.at_us[v] = 1000.0 * *std::min_element(form_med, form_med + 3);
   }
   hipEventDestroy(e0);
   hipEventDestroy(e1);
@@ -279,12 +282,16 @@ int plan_build(Plan& p, int64_t n_rows, int64_t n_cols, int64_t nnz, const int32
   if (mode == SPMV_SELECT_FIXED && fixed >= SPMV_NUM_VARIANTS)
     return fail(SPMV_ERR_INVALID_ARG, "variant out of range");
   if (flags & ~(0xFFFu | SPMV_FLAG_SKIP_VALIDATE | SPMV_FLAG_SELL | SPMV_FLAG_V4_STAGE_ON |
-                SPMV_FLAG_V4_STAGE_OFF | SPMV_FLAG_SELL_WIDE))
+                SPMV_FLAG_V4_STAGE_OFF | SPMV_FLAG_SELL_WIDE | SPMV_FLAG_V4_WINDOWS))
     return fail(SPMV_ERR_INVALID_ARG, "unknown flag bits");
   if ((flags & SPMV_FLAG_SELL_WIDE) && !(flags & SPMV_FLAG_SELL))
     return fail(SPMV_ERR_INVALID_ARG, "SPMV_FLAG_SELL_WIDE needs SPMV_FLAG_SELL");
-  if ((flags & SPMV_FLAG_V4_STAGE_ON) && (flags & SPMV_FLAG_V4_STAGE_OFF))
-    return fail(SPMV_ERR_INVALID_ARG, "SPMV_FLAG_V4_STAGE_ON and _OFF together");
+  {
+    const uint32_t fm = flags & (SPMV_FLAG_V4_STAGE_ON | SPMV_FLAG_V4_STAGE_OFF | SPMV_FLAG_V4_WINDOWS);
+    if (fm & (fm - 1))
+      return fail(SPMV_ERR_INVALID_ARG,
+                  "at most one of SPMV_FLAG_V4_STAGE_ON, _STAGE_OFF and _WINDOWS");
+  }
   if (mode == SPMV_SELECT_FIXED && fixed == SPMV_V6_SELL64 && !(flags & SPMV_FLAG_SELL))
     return fail(SPMV_ERR_INVALID_ARG, "variant V6 needs SPMV_FLAG_SELL");
   const PlanLayout L = plan_layout(n_rows, n_cols, nnz, flags);
@@ -306,6 +313,8 @@ int plan_build(Plan& p, int64_t n_rows, int64_t n_cols, int64_t nnz, const int32
   p.hdr = reinterpret_cast<WsHeader*>(p.ws + L.header);
   p.blocks = reinterpret_cast<int2*>(p.ws + L.blocks);
   p.spans = reinterpret_cast<int2*>(p.ws + L.spans);
+  p.win = reinterpret_cast<int32_t*>(p.ws + L.win);
+  p.nsb = super_block_count(n_rows);
   p.nblocks = lds_block_count(n_rows, nnz);
   p.bin_rows = reinterpret_cast<int32_t*>(p.ws + L.bins);
   p.stats_part = reinterpret_cast<unsigned long long*>(p.ws + L.stats);
@@ -337,6 +346,7 @@ int plan_build(Plan& p, int64_t n_rows, int64_t n_cols, int64_t nnz, const int32
   st = launch_zero_header(p.hdr, s);
   if (!st && !(flags & SPMV_FLAG_SKIP_VALIDATE)) st = launch_validate(p, s);
   if (!st) st = launch_analysis(p, run_mlp ? g_sel.mu : nullptr, run_mlp ? g_sel.sigma : nullptr, s);
+  if (!st) st = launch_win_build(p, s);
   if (!st && run_mlp)
     st = launch_mlp_forward(theta, p.hdr->x_std, 1, p.hdr->pred, p.hdr->z1, p.hdr->z2, s);
   if (!st && p.sell_reserved) st = launch_sell_build(p, s);
@@ -356,10 +366,21 @@ int plan_build(Plan& p, int64_t n_rows, int64_t n_cols, int64_t nnz, const int32
   if (st) return st;
   std::memcpy(p.features, hh.features, sizeof(p.features));
   p.staged_blocks = hh.staged_blocks;
-  p.v4_stage_forced = (flags & (SPMV_FLAG_V4_STAGE_ON | SPMV_FLAG_V4_STAGE_OFF)) != 0;
-  p.v4_staged = (flags & SPMV_FLAG_V4_STAGE_ON)    ? true
-                : (flags & SPMV_FLAG_V4_STAGE_OFF) ? false
-                                                   : p.staged_blocks * 4 >= p.nblocks;
+  p.win_covered = (int64_t)hh.win_covered;
+  p.v4_form_forced =
+      (flags & (SPMV_FLAG_V4_STAGE_ON | SPMV_FLAG_V4_STAGE_OFF | SPMV_FLAG_V4_WINDOWS)) != 0;
+  // without a flag: staging when a quarter of the row blocks fit exactly, else
+  // windows when they hold at least 65% of the nonzeros and there are enough
+  // super-blocks to fill the chip (permuted 3D stencil, 21.95M rows: 74%
+  // through two windows in float64, 85% through three in float32, both
+  // faster than the other forms; a 6M-row matrix of 7 diagonal pairs with
+  // 54-60% stays faster plain; below 512 super-blocks the grid leaves CUs idle)
+  p.v4_form = (flags & SPMV_FLAG_V4_STAGE_ON)    ? kV4Staged
+              : (flags & SPMV_FLAG_V4_STAGE_OFF) ? kV4Plain
+              : (flags & SPMV_FLAG_V4_WINDOWS)   ? kV4Window
+              : p.staged_blocks * 4 >= p.nblocks ? kV4Staged
+              : p.win_covered * 20 >= 13 * p.nnz && p.nnz > 0 && p.nsb >= 512 ? kV4Window
+                                                                              : kV4Plain;
   for (int b = 0; b < kNumBins; ++b) {
     p.bin_count[b] = hh.bin_count[b];
     p.bin_offset[b] = hh.bin_offset[b];
@@ -480,7 +501,22 @@ int spmv_get_autotune_times(spmv_handle h, double* us) {
 
 int spmv_get_v4_staged(spmv_handle h, int* staged) {
   if (!h || !staged) return fail(SPMV_ERR_INVALID_ARG, "null argument");
-  *staged = h->p.v4_staged ? 1 : 0;
+  *staged = h->p.v4_form == kV4Staged ? 1 : 0;
+  return SPMV_OK;
+}
+
+int spmv_get_v4_form(spmv_handle h, int* form, int64_t* win_covered) {
+  if (!h || !form) return fail(SPMV_ERR_INVALID_ARG, "null argument");
+  *form = h->p.v4_form;
+  if (win_covered) *win_covered = h->p.win_covered;
+  return SPMV_OK;
+}
+
+int spmv_set_v4_form(spmv_handle h, int form) {
+  if (!h) return fail(SPMV_ERR_INVALID_ARG, "handle is null");
+  if (form < SPMV_V4_PLAIN || form > SPMV_V4_WINDOWS)
+    return fail(SPMV_ERR_INVALID_ARG, "unknown V4 form");
+  h->p.v4_form = form;
   return SPMV_OK;
 }
 

@@ -20,6 +20,12 @@ constexpr int kBlockBudget = 2048;  // rows + in-chunk nonzeros of one LDS row b
 // B is staged as float32, so twice as many.
 template <typename BT>
 constexpr int kStageEntries = sizeof(BT) == 4 ? 2 * kBlockBudget : kBlockBudget;
+// V4 window form: a super-block of kSbRows rows per workgroup; windows of B
+// are kWinSize aligned columns, at most kWinMax per super-block
+constexpr int kSbRows = 4096;
+constexpr int kWinLog = 12;
+constexpr int kWinSize = 1 << kWinLog;
+constexpr int kWinMax = 6;
 constexpr int kNumXCD = 8;        // MI355X: 8 accelerator complex dies, one L2 each
 constexpr int kNumBins = 5;       // row-length bins of the binned variant
 // batch tile record: matrix, r0, r1, S, E, staging cmin, cmax, column-delta bits (0, 8 or 16),
@@ -45,6 +51,8 @@ struct alignas(256) WsHeader {
   int32_t bin_offset[8];
   int64_t sell_total;  // padded width sum of the V6 copy, in units of 64 slots
   int32_t staged_blocks;  // row blocks whose chunk's columns fit the LDS staging array
+  int32_t pad1;
+  unsigned long long win_covered;  // nonzeros inside the windows of their super-block
 };
 constexpr size_t kHeaderBytes = (sizeof(WsHeader) + 255) / 256 * 256;
 
@@ -55,6 +63,9 @@ enum : int {
 };
 
 // ---------------------------------------------------------------- plan
+
+// the three forms of V4 (the same rows and products, different B access)
+enum : int { kV4Plain = 0, kV4Staged = 1, kV4Window = 2 };
 
 struct Plan {
   int64_t n_rows = 0, n_cols = 0, nnz = 0;
@@ -68,8 +79,11 @@ struct Plan {
   int2* blocks = nullptr;         // device [nblocks+1]: (first row, row_ptr[first row])
   int2* spans = nullptr;          // device [nblocks]: (smallest, largest) column of the block's chunk
   int64_t staged_blocks = 0;      // blocks with a span that fits the LDS staging array
-  bool v4_staged = false;         // V4 runs the staging kernel (span rule, flag or autotune)
-  bool v4_stage_forced = false;   // the form was fixed by a plan flag
+  int v4_form = 0;                // V4 form: kV4Plain, kV4Staged or kV4Window
+  bool v4_form_forced = false;    // the form was fixed by a plan flag
+  int64_t nsb = 0;                // super-blocks of the window form
+  int32_t* win = nullptr;         // device int32[nsb][kWinMax]: window bins, -1 unused
+  int64_t win_covered = 0;        // nonzeros whose column lies in their super-block's windows
   int64_t nblocks = 0;
   int32_t* bin_rows = nullptr;    // device int32[n_rows]
   unsigned long long* stats_part = nullptr;  // device [kStatsGrid][kPartSlots]
@@ -139,6 +153,8 @@ int hip_fail(hipError_t e, const char* what);
 
 inline size_t align256(size_t x) { return (x + 255) / 256 * 256; }
 
+inline int64_t super_block_count(int64_t n_rows) { return (n_rows + kSbRows - 1) / kSbRows; }
+
 inline int64_t lds_block_count(int64_t n_rows, int64_t nnz) {
   if (n_rows <= 0) return 0;
   return (nnz + n_rows + kBlockBudget - 1) / kBlockBudget;
@@ -197,6 +213,10 @@ int launch_sell_build(Plan& p, hipStream_t s);
 int launch_sell(const Plan& p, const void* B, double* C, hipStream_t s);
 int launch_sell_spmm(const Plan& p, int k, const void* B, int64_t ldb, double* C, int64_t ldc,
                      hipStream_t s);
+// window.hip
+int win_count(int vdt);
+int launch_win_build(Plan& p, hipStream_t s);
+int launch_win(const Plan& p, const void* B, double* C, hipStream_t s);
 // stream.hip
 int launch_triad(double* a, const double* b, const double* c, double s, int64_t n,
                  hipStream_t st);

@@ -27,25 +27,26 @@ __global__ __launch_bounds__(kWG) void k_thread_row(int32_t nrows, const int32_t
                                                     const VT* __restrict__ val,
                                                     const BT* __restrict__ B,
                                                     double* __restrict__ C) {
-  const int64_t t = (int64_t)blockIdx.x * kWG + threadIdx.x;
-  if (t >= nrows) return;
-  const int32_t r = LIST ? list[t] : (int32_t)t;
-  const int32_t s = rp[r], e = rp[r + 1];
-  double acc = 0.0;
-  int32_t j = s;
-  for (; j + 4 <= e; j += 4) {
-    VT v0 = ld_stream(val + j), v1 = ld_stream(val + j + 1), v2 = ld_stream(val + j + 2),
-       v3 = ld_stream(val + j + 3);
-    int32_t c0 = ld_stream(ci + j), c1 = ld_stream(ci + j + 1), c2 = ld_stream(ci + j + 2),
-            c3 = ld_stream(ci + j + 3);
-    BT b0 = B[c0], b1 = B[c1], b2 = B[c2], b3 = B[c3];
-    acc = fma(widen(v0), widen(b0), acc);
-    acc = fma(widen(v1), widen(b1), acc);
-    acc = fma(widen(v2), widen(b2), acc);
-    acc = fma(widen(v3), widen(b3), acc);
+  for (int64_t t = (int64_t)blockIdx.x * kWG + threadIdx.x; t < nrows;
+       t += (int64_t)gridDim.x * kWG) {
+    const int32_t r = LIST ? list[t] : (int32_t)t;
+    const int32_t s = rp[r], e = rp[r + 1];
+    double acc = 0.0;
+    int32_t j = s;
+    for (; j + 4 <= e; j += 4) {
+      VT v0 = ld_stream(val + j), v1 = ld_stream(val + j + 1), v2 = ld_stream(val + j + 2),
+         v3 = ld_stream(val + j + 3);
+      int32_t c0 = ld_stream(ci + j), c1 = ld_stream(ci + j + 1), c2 = ld_stream(ci + j + 2),
+              c3 = ld_stream(ci + j + 3);
+      BT b0 = B[c0], b1 = B[c1], b2 = B[c2], b3 = B[c3];
+      acc = fma(widen(v0), widen(b0), acc);
+      acc = fma(widen(v1), widen(b1), acc);
+      acc = fma(widen(v2), widen(b2), acc);
+      acc = fma(widen(v3), widen(b3), acc);
+    }
+    for (; j < e; ++j) acc = fma(widen(ld_stream(val + j)), widen(B[ld_stream(ci + j)]), acc);
+    C[r] = acc;
   }
-  for (; j < e; ++j) acc = fma(widen(ld_stream(val + j)), widen(B[ld_stream(ci + j)]), acc);
-  C[r] = acc;
 }
 
 // ---------------------------------------------------------------- V1/V2/V3
@@ -58,23 +59,26 @@ __global__ __launch_bounds__(kWG) void k_group_row(int32_t nrows, const int32_t*
                                                    const VT* __restrict__ val,
                                                    const BT* __restrict__ B,
                                                    double* __restrict__ C) {
-  const int64_t g = ((int64_t)blockIdx.x * kWG + threadIdx.x) / G;
   const int lane = threadIdx.x & (G - 1);
-  if (g >= nrows) return;  // whole groups leave together
-  const int32_t r = LIST ? list[g] : (int32_t)g;
-  const int32_t s = rp[r], e = rp[r + 1];
-  double part = 0.0;
-  int32_t j = s + lane;
-  for (; j + G < e; j += 2 * G) {
-    VT v0 = ld_stream(val + j), v1 = ld_stream(val + j + G);
-    int32_t c0 = ld_stream(ci + j), c1 = ld_stream(ci + j + G);
-    BT b0 = B[c0], b1 = B[c1];
-    part = fma(widen(v0), widen(b0), part);
-    part = fma(widen(v1), widen(b1), part);
+  // grid-stride over groups: the grid is capped (rows x G lanes can exceed
+  // what one dispatch holds); whole groups leave together
+  const int64_t stride = (int64_t)gridDim.x * (kWG / G);
+  for (int64_t g = ((int64_t)blockIdx.x * kWG + threadIdx.x) / G; g < nrows; g += stride) {
+    const int32_t r = LIST ? list[g] : (int32_t)g;
+    const int32_t s = rp[r], e = rp[r + 1];
+    double part = 0.0;
+    int32_t j = s + lane;
+    for (; j + G < e; j += 2 * G) {
+      VT v0 = ld_stream(val + j), v1 = ld_stream(val + j + G);
+      int32_t c0 = ld_stream(ci + j), c1 = ld_stream(ci + j + G);
+      BT b0 = B[c0], b1 = B[c1];
+      part = fma(widen(v0), widen(b0), part);
+      part = fma(widen(v1), widen(b1), part);
+    }
+    if (j < e) part = fma(widen(ld_stream(val + j)), widen(B[ld_stream(ci + j)]), part);
+    const double sum = group_sum<G>(part);
+    if (lane == 0) C[r] = sum;
   }
-  if (j < e) part = fma(widen(ld_stream(val + j)), widen(B[ld_stream(ci + j)]), part);
-  const double sum = group_sum<G>(part);
-  if (lane == 0) C[r] = sum;
 }
 
 // Whole workgroup per row (very long rows of the binned variant).
@@ -137,7 +141,11 @@ __global__ __launch_bounds__(kWG) void k_lds_block_staged(int64_t nblocks,
 template <typename VT, typename BT, bool ACC>
 void launch_lds_block(const Plan& p, const VT* val, const BT* B, double* C, hipStream_t s) {
   if (p.nblocks <= 0) return;
-  if (p.v4_staged)
+  if (!ACC && p.v4_form == kV4Window) {
+    launch_win(p, B, C, s);
+    return;
+  }
+  if (p.v4_form == kV4Staged)
     k_lds_block_staged<VT, BT, ACC><<<(unsigned)p.nblocks, kWG, 0, s>>>(
         p.nblocks, p.blocks, p.spans, p.row_ptr, p.col_idx, val, B, C);
   else
@@ -204,9 +212,12 @@ __global__ __launch_bounds__(kWG) void k_spmm(int32_t nrows, int32_t k,
                                               const VT* __restrict__ val,
                                               const BT* __restrict__ B, int64_t ldb,
                                               double* __restrict__ C, int64_t ldc) {
-  const int64_t row = ((int64_t)blockIdx.x * kWG + threadIdx.x) / LPR;
   const int lane = threadIdx.x & (LPR - 1);
-  if (row >= nrows) return;
+  // grid-stride over rows (the grid is capped: rows x LPR lanes can exceed
+  // what one dispatch holds); the lanes of a row leave together
+  const int64_t row_stride = (int64_t)gridDim.x * (kWG / LPR);
+  for (int64_t row = ((int64_t)blockIdx.x * kWG + threadIdx.x) / LPR; row < nrows;
+       row += row_stride) {
   const int32_t s = rp[row], e = rp[row + 1];
   for (int32_t c0 = lane * CPL; c0 < k; c0 += LPR * CPL) {
     double acc[CPL];
@@ -334,6 +345,7 @@ __global__ __launch_bounds__(kWG) void k_spmm(int32_t nrows, int32_t k,
         if (t < kc) out[t] = acc[t];
     }
   }
+  }
 }
 
 // ---------------------------------------------------------------- fill
@@ -344,8 +356,12 @@ __global__ void k_fill(T* p, int64_t n, T v) {
     p[i] = v;
 }
 
+// Workgroups for `threads` lanes of a grid-stride kernel, at most kMaxGrid
+// (n_rows x 64 lanes can pass the 2^32 work-items of one dispatch).
+constexpr int64_t kMaxGrid = 1 << 20;
 inline unsigned grid_for(int64_t threads) {
-  return (unsigned)((threads + kWG - 1) / kWG);
+  const int64_t g = (threads + kWG - 1) / kWG;
+  return (unsigned)(g < kMaxGrid ? g : kMaxGrid);
 }
 
 template <typename VT, typename BT>

@@ -7,6 +7,7 @@ import numpy as np
 
 from . import (SPMV_ERR_STATE, SPMV_F32, SPMV_F64, SPMV_SELECT_DEFAULT, SPMV_SELECT_MLP,
                SpmvError, dtype_code, spmv_get_sell_deltas, spmv_get_sell_slots, spmv_get_v4_staged,
+               spmv_get_v4_form, spmv_set_v4_form,
                load_selector, spmv_selector_loaded, spmm_apply, spmv_apply, spmv_batch_apply,
                spmv_batch_apply_each, spmv_batch_create, spmv_batch_destroy, spmv_batch_set_mode,
                spmv_batch_get_num_tiles, spmv_batch_workspace_size, spmv_create, spmv_destroy,
@@ -88,6 +89,20 @@ class CRSMatrix:
     def v4_staged(self) -> bool:
         """Whether V4 runs in its B-staging form."""
         return spmv_get_v4_staged(self.handle)
+
+    @property
+    def v4_form(self) -> int:
+        """V4 form in use: 0 plain, 1 B staged per row block, 2 B windows."""
+        return spmv_get_v4_form(self.handle)[0]
+
+    @v4_form.setter
+    def v4_form(self, f: int) -> None:
+        spmv_set_v4_form(self.handle, f)
+
+    @property
+    def win_covered(self) -> int:
+        """Nonzeros whose column lies in their super-block's B windows."""
+        return spmv_get_v4_form(self.handle)[1]
 
     @property
     def sell_slots(self):

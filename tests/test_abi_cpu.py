@@ -84,9 +84,10 @@ def _create(**kw):
     (dict(flags=pkg.SPMV_FLAG_VARIANT(6)), pkg.SPMV_ERR_INVALID_ARG),  # V6 without its flag
     (dict(flags=pkg.SPMV_FLAG_VARIANT(6) | pkg.SPMV_FLAG_SELL, ws_bytes=1 << 12),
      pkg.SPMV_ERR_WORKSPACE),
-    (dict(flags=1 << 21), pkg.SPMV_ERR_INVALID_ARG),
+    (dict(flags=1 << 22), pkg.SPMV_ERR_INVALID_ARG),
     (dict(flags=pkg.SPMV_FLAG_SELL_WIDE), pkg.SPMV_ERR_INVALID_ARG),  # without SPMV_FLAG_SELL
     (dict(flags=pkg.SPMV_FLAG_V4_STAGE_ON | pkg.SPMV_FLAG_V4_STAGE_OFF), pkg.SPMV_ERR_INVALID_ARG),
+    (dict(flags=pkg.SPMV_FLAG_V4_STAGE_OFF | pkg.SPMV_FLAG_V4_WINDOWS), pkg.SPMV_ERR_INVALID_ARG),
     (dict(workspace=None), pkg.SPMV_ERR_WORKSPACE),
     (dict(workspace=0x10010), pkg.SPMV_ERR_WORKSPACE),
     (dict(ws_bytes=16), pkg.SPMV_ERR_WORKSPACE),
