@@ -1,12 +1,16 @@
-"""Benchmark: FP64 CRS spMVM on the Hamiltonian-like workload (N = 6.0M rows,
-diagonal + 7 symmetric offset pairs), one MI355X.
+"""Benchmark: FP64 CRS spMVM on the permuted 3D stencil with random extras
+(N = 21,952,000 rows, 170M nonzeros), one MI355X -- the largest workload, on
+which the headline is quoted.
 
-One step = one C = A*B product through spmv_apply with the plan's variant,
-inputs resident in HBM. Prints ONE JSON line (rank 0) with GFlop/s, the
-roofline of the product kernel (HBM-bound: compulsory bytes / kernel time
-against 8 TB/s), and the CPU oracle timed on the host as a baseline. Extra
-measurements (FP32 storage, the permuted-stencil workload, multi-RHS, the
-uneven batch, a triad) go into "extra".
+One step = one C = A*B product through spmv_apply with the plan's variant
+(autotuned), inputs resident in HBM. Prints ONE JSON line (rank 0) with
+GFlop/s, the roofline of the product kernel (HBM-bound: the bytes the
+kernel must read / kernel time, against 8 TB/s, with the HBM bytes the
+counters measured), and the CPU oracle timed on the host as a baseline next
+to the paper's node scheme on all host cores. Extra measurements (the
+Hamiltonian-like workload with the best kernel on the caller's CRS arrays and
+the chunked copy, FP32 storage, multi-RHS, the uneven batch, RCM, solvers, a
+triad) go into "extra".
 """
 from __future__ import annotations
 
@@ -25,7 +29,14 @@ METRIC = "CRS spMVM GFlop/s and effective HBM GB/s (% roofline) at 1 MI355X, FP6
 HBM_PEAK = 8000.0  # GB/s, MI355X nominal
 KERNEL_NAMES = {"V4_lds_block": "k_lds_block<double,double>",
                 "V4_lds_block_staged": "k_lds_block_staged<double,double>",
+                "V4_lds_block_windows": "k_win_rows<double,double,true>",
                 "V6_sell64": "k_sell_pairs"}
+# the paper's own CPU figures (Sect. 2, one Xeon X5550 socket, HMeP matrix):
+# context only, another machine and another matrix
+PAPER_CPU = {"hardware": "Intel Xeon X5550 (Nehalem EP, 4 cores, 2.66 GHz), one socket",
+             "matrix": "HMeP Holstein-Hubbard, N=6.2e6, N_nzr~15",
+             "spmv_gflops": 2.25, "spmv_gbs": 18.1, "stream_triad_gbs": 21.2,
+             "model_bound_gflops_at_18.1GBs": 2.66}
 SELL = 0  # plan flag requesting the V6 chunked copy; set in main()
 
 
@@ -38,7 +49,9 @@ def log(msg):
 KERNEL_SOURCES = {"V6_sell64": ("sell.hip", "device.hpp", "common.hpp"),
                   # the staged form's B ranges are chosen at create (analysis.hip)
                   "V4_lds_block_staged": ("spmv_kernels.hip", "device.hpp", "common.hpp",
-                                          "analysis.hip")}
+                                          "analysis.hip"),
+                  # the window form and its window choice
+                  "V4_lds_block_windows": ("window.hip", "device.hpp", "common.hpp")}
 DEFAULT_SOURCES = ("spmv_kernels.hip", "device.hpp", "common.hpp")
 
 
@@ -74,10 +87,22 @@ def stored_traffic(workload: str, variant_name: str):
     return None
 
 
+def kernel_name(vname: str, sv: int = 8) -> str:
+    """The product kernel of a variant (float32 storage: its float template
+    or, for V6, its quads kernel)."""
+    k = KERNEL_NAMES.get(vname, vname)
+    if sv == 4:
+        k = k.replace("<double,double", "<float,float").replace("k_sell_pairs", "k_sell_quads")
+    return k
+
+
 def variant_name(pkg, M) -> str:
-    """The plan's variant, with V4's B-staging form (its own kernel) named apart."""
+    """The plan's variant, with V4's B-staging and window forms (kernels of
+    their own) named apart."""
     v = pkg.VARIANTS[M.variant]
-    return "V4_lds_block_staged" if v == "V4_lds_block" and M.v4_staged else v
+    if v == "V4_lds_block":
+        return ("V4_lds_block", "V4_lds_block_staged", "V4_lds_block_windows")[M.v4_form]
+    return v
 
 
 def time_launches(fn, steps, warmup, stream, every=1):
@@ -115,7 +140,10 @@ def main():
     ap.add_argument("--no-extra", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--variant", type=int, default=-1, help="force a variant (default: autotune)")
-    ap.add_argument("--workload", default="hamiltonian", choices=["hamiltonian", "mesh"])
+    ap.add_argument("--v4-form", type=int, default=-1,
+                    help="with --variant 4: force the V4 form (0 plain, 1 staged, 2 windows)")
+    ap.add_argument("--workload", default="mesh", choices=["mesh", "hamiltonian"])
+    ap.add_argument("--f32", action="store_true", help="FP32 storage (profiling runs)")
     ap.add_argument("--no-sell", action="store_true",
                     help="build plans without the V6 chunked copy")
     ap.add_argument("--rcm", action="store_true",
@@ -140,7 +168,7 @@ def main():
     dev = torch.device("cuda:0")
     stream = torch.cuda.current_stream()
     if args.rcm:
-        print(json.dumps(run_rcm(pkg, pm, dev, stream)), flush=True)
+        print(json.dumps(run_rcm(pkg, pm, dev, stream, both=True)), flush=True)
         return
     if args.calib_copy:
         n = 1 << 27  # 1 GiB of float64 read, 1 GiB written per launch
@@ -161,17 +189,24 @@ def main():
         A = crsgen.mesh3d(280, seed=seed)[0]
     B = crsgen.uniform_vec(A.n_cols, seed)
     flags = pkg.SPMV_SELECT_AUTOTUNE if args.variant < 0 else pkg.SPMV_FLAG_VARIANT(args.variant)
+    if args.variant == 4 and args.v4_form >= 0:
+        flags |= (pkg.SPMV_FLAG_V4_STAGE_OFF, pkg.SPMV_FLAG_V4_STAGE_ON,
+                  pkg.SPMV_FLAG_V4_WINDOWS)[args.v4_form]
     flags |= SELL
-    M = pkg.CRSMatrix.from_crs(A, flags=flags, device=dev)
+    sv = 4 if args.f32 else 8
+    vdt, bdt = (torch.float32, np.float32) if args.f32 else (torch.float64, np.float64)
+    M = pkg.CRSMatrix(A.n_rows, A.n_cols, A.row_ptr, A.col_idx, A.val.astype(bdt),
+                      val_dtype=vdt, flags=flags, device=dev)
     vname = variant_name(pkg, M)
     log(f"plan ready: nnz={A.nnz} variant={vname} blocks={M.num_blocks} "
         f"sell_slots={M.sell_slots}")
-    Bd = torch.from_numpy(B).to(dev)
+    Bd = torch.from_numpy(B.astype(bdt)).to(dev)
     C = torch.empty(A.n_rows, dtype=torch.float64, device=dev)
     h = M.handle
+    code = pkg.SPMV_F32 if args.f32 else pkg.SPMV_F64
 
     def step():
-        pkg.spmv_apply(h, Bd, pkg.SPMV_F64, C)
+        pkg.spmv_apply(h, Bd, code, C)
 
     per, wall = time_launches(step, args.steps, args.warmup, stream,
                               every=8 if args.steps >= 64 else 1)
@@ -180,11 +215,12 @@ def main():
     secs = ms_per_step / 1000.0
     nnz = A.nnz
     value = pm.gflops(nnz, secs)
-    comp = pm.compulsory_bytes(A.n_rows, A.n_cols, nnz)
-    achieved = comp / (k_ms / 1000.0) / 1e9
-    log(f"fp64: {ms_per_step:.4f} ms/step, kernel {k_ms:.4f} ms, {value:.1f} GFlop/s, "
-        f"{achieved:.1f} GB/s")
-    traffic = stored_traffic(wname, vname)
+    comp = pm.compulsory_bytes(A.n_rows, A.n_cols, nnz, 1, sv, sv)
+    own = own_bytes(pkg, M, A, sv)
+    achieved = own / (k_ms / 1000.0) / 1e9
+    log(f"{'fp32' if args.f32 else 'fp64'}: {ms_per_step:.4f} ms/step, kernel {k_ms:.4f} ms, "
+        f"{value:.1f} GFlop/s, {achieved:.1f} GB/s of the kernel's own bytes")
+    traffic = None if args.f32 else stored_traffic(wname, vname)
     kappa = (None if traffic is None else
              round(pm.kappa_from_bytes(traffic, A.n_rows, A.n_cols, nnz), 3))
     out = {
@@ -198,20 +234,22 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64",
+        "dtype": "f32" if args.f32 else "f64",
         "data": "synthetic",
         "config": {"workload": wname, "n_rows": A.n_rows, "nnz": nnz, "seed": seed,
-                   "variant": vname, "rhs": "uniform[-1,1)"},
-        "eff_gbs": round(pm.effective_gbs(A.n_rows, A.n_cols, nnz, secs), 1),
-        "pct_hbm_roofline": round(100.0 * pm.effective_gbs(A.n_rows, A.n_cols, nnz, secs)
-                                  / HBM_PEAK, 2),
+                   "variant": vname, "reads_caller_crs_arrays": vname != "V6_sell64",
+                   "rhs": "uniform[-1,1)"},
+        "eff_gbs": round(comp / secs / 1e9, 1),
+        "pct_hbm_roofline": round(100.0 * comp / secs / 1e9 / HBM_PEAK, 2),
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK, 4),
-                     "traffic": traffic, "kernel": KERNEL_NAMES.get(vname, vname),
+                     "traffic": traffic, "kernel": kernel_name(vname, sv),
                      "kernel_ms": round(k_ms, 5),
                      "kernel_ms_median": round(float(np.median(per)), 5),
                      "kernel_ms_min": round(float(np.min(per)), 5),
-                     "algorithmic_bytes_per_launch": comp, "kappa_bytes_per_nnz": kappa},
+                     "algorithmic_bytes_per_launch": own,
+                     "crs_compulsory_bytes_per_launch": comp,
+                     "kappa_bytes_per_nnz": kappa},
     }
     extra = {}
     if not args.no_extra:
@@ -221,13 +259,25 @@ def main():
         # the paper's practice: performance against the measured STREAM triad
         out["pct_of_box_triad"] = round(100.0 * achieved / extra["triad_gbs"], 2)
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(A, B)
+        out["cpu_baseline"], out["host_node_scheme"] = cpu_baseline(A, B)
+        out["paper_cpu_context"] = PAPER_CPU
     print(json.dumps(out), flush=True)
 
 
-def time_create(A, pkg, dev):
+def own_bytes(pkg, M, A, sv, k=1):
+    """Bytes the plan's product kernel must read and write once: the CRS
+    compulsory bytes for kernels that read the caller's arrays, the chunked
+    copy's stream plus B and C for V6."""
+    from paper_1101_0091_amd import perfmodel as pm
+    if M.variant == pkg.SPMV_V6_SELL64:
+        return M.sell_stream_bytes + sv * A.n_cols * k + 8 * A.n_rows * k
+    return pm.compulsory_bytes(A.n_rows, A.n_cols, A.nnz, k, sv, sv)
+
+
+def time_create(A, pkg, dev, has_v6=True):
     """Plan creation cost: analysis only (fixed variant), analysis + selector
-    network, analysis + exhaustive autotune (the selector's alternative)."""
+    network, analysis + exhaustive autotune (the selector's alternative);
+    with the V6 copy where it fits the matrix."""
     import torch
     rp = torch.from_numpy(A.row_ptr).to(dev)
     ci = torch.from_numpy(A.col_idx).to(dev)
@@ -238,6 +288,8 @@ def time_create(A, pkg, dev):
                         ("fixed_v6_with_copy", pkg.SPMV_FLAG_VARIANT(6) | pkg.SPMV_FLAG_SELL),
                         ("selector_with_v6_copy", pkg.SPMV_SELECT_DEFAULT | pkg.SPMV_FLAG_SELL),
                         ("autotune_with_v6_copy", pkg.SPMV_SELECT_AUTOTUNE | pkg.SPMV_FLAG_SELL)):
+        if name == "fixed_v6_with_copy" and not has_v6:
+            continue
         if name.startswith("selector"):
             pkg.load_selector()
         nb = pkg.spmv_workspace_size(A.n_rows, A.n_cols, A.nnz, flags)
@@ -257,6 +309,26 @@ def time_create(A, pkg, dev):
     return out
 
 
+def kernel_record(pkg, pm, M, A, fn, stream, sv, wname=None, steps=30):
+    """Median event time of one product with the plan's current variant, its
+    rate on the bytes its kernel reads (own) and on the CRS compulsory bytes."""
+    import numpy as np
+    per, _ = time_launches(fn, steps, 3, stream)
+    t = float(np.median(per)) / 1000
+    vname = variant_name(pkg, M)
+    own = own_bytes(pkg, M, A, sv)
+    comp = pm.compulsory_bytes(A.n_rows, A.n_cols, A.nnz, 1, sv, sv)
+    rec = {"variant": vname, "kernel": kernel_name(vname, sv),
+           "kernel_ms": round(t * 1e3, 5), "gflops": round(pm.gflops(A.nnz, t), 1),
+           "own_bytes_per_launch": own, "own_gbs": round(own / t / 1e9, 1),
+           "own_frac": round(own / t / 1e9 / HBM_PEAK, 4),
+           "crs_equiv_gbs": round(comp / t / 1e9, 1),
+           "crs_equiv_frac": round(comp / t / 1e9 / HBM_PEAK, 4)}
+    if wname and sv == 8:
+        rec["traffic"] = stored_traffic(wname, vname)
+    return rec
+
+
 def run_extra(A, B, M, pkg, pm, dev, stream, args):
     import numpy as np
     import torch
@@ -264,19 +336,22 @@ def run_extra(A, B, M, pkg, pm, dev, stream, args):
     import crsgen
     ex = {}
     steps = max(20, args.steps // 4)
-    # variants on the same matrix
+    wname = "mesh3d_280_permuted_N21.95M" if A.n_rows != 6_000_000 else "hamiltonian_like_N6M"
+    # every variant (and V4 form) on the headline matrix
     Bd = torch.from_numpy(B).to(dev)
     C = torch.empty(A.n_rows, dtype=torch.float64, device=dev)
     var_ms = {}
-    v0 = M.variant
+    v0, f0 = M.variant, M.v4_form
     for v in range(pkg.SPMV_NUM_VARIANTS):
         if v == pkg.SPMV_V6_SELL64 and M.sell_slots is None:
             continue
         M.variant = v
-        per, _ = time_launches(lambda: pkg.spmv_apply(M.handle, Bd, pkg.SPMV_F64, C), steps, 3,
-                               stream)
-        var_ms[pkg.VARIANTS[v]] = round(float(np.median(per)), 5)
-    M.variant = v0
+        for f in ((0, 1, 2) if v == 4 else (f0,)):
+            M.v4_form = f
+            per, _ = time_launches(lambda: pkg.spmv_apply(M.handle, Bd, pkg.SPMV_F64, C), steps,
+                                   3, stream)
+            var_ms[variant_name(pkg, M)] = round(float(np.median(per)), 5)
+    M.variant, M.v4_form = v0, f0
     ex["variant_ms"] = var_ms
     log(f"variants: {var_ms}")
     # the timed loop reuses B, which stays in the 256 MB memory-side cache
@@ -285,21 +360,17 @@ def run_extra(A, B, M, pkg, pm, dev, stream, args):
     ex["headline_cold"] = {"ms": round(t * 1000, 5), "gflops": round(pm.gflops(A.nnz, t), 1),
                            "eff_gbs": round(pm.effective_gbs(A.n_rows, A.n_cols, A.nnz, t), 1)}
     log(f"headline cold: {ex['headline_cold']}")
-    ex["plan_create_ms"] = time_create(A, pkg, dev)
+    ex["plan_create_ms"] = time_create(A, pkg, dev, M.sell_slots is not None)
     # FP32 storage, FP64 accumulation
     M32 = pkg.CRSMatrix(A.n_rows, A.n_cols, A.row_ptr, A.col_idx, A.val.astype(np.float32),
                         val_dtype=torch.float32, flags=pkg.SPMV_SELECT_AUTOTUNE | SELL,
                         device=dev)
     B32 = torch.from_numpy(B.astype(np.float32)).to(dev)
-    per, _ = time_launches(lambda: pkg.spmv_apply(M32.handle, B32, pkg.SPMV_F32, C), steps, 5,
-                           stream)
-    t = float(np.mean(per)) / 1000
-    ex["mixed_fp32_storage"] = {
-        "gflops": round(pm.gflops(A.nnz, t), 1),
-        "eff_gbs": round(pm.effective_gbs(A.n_rows, A.n_cols, A.nnz, t, 1, 4, 4), 1),
-        "variant": variant_name(pkg, M32), "kernel_ms": round(t * 1000, 5)}
+    ex["mixed_fp32_storage"] = kernel_record(
+        pkg, pm, M32, A, lambda: pkg.spmv_apply(M32.handle, B32, pkg.SPMV_F32, C), stream, 4)
     log(f"mixed: {ex['mixed_fp32_storage']}")
-    del M32
+    del M32, B32, Bd, C
+    torch.cuda.empty_cache()
     # triad ceiling
     n = 1 << 27
     a = torch.empty(n, dtype=torch.float64, device=dev)
@@ -312,6 +383,9 @@ def run_extra(A, B, M, pkg, pm, dev, stream, args):
     ex["copy_gbs"] = round(16 * n / (float(np.median(per)) / 1000) / 1e9, 1)
     log(f"triad {ex['triad_gbs']} GB/s copy {ex['copy_gbs']} GB/s")
     del a, b, c
+    if wname != "hamiltonian_like_N6M":
+        ex["hamiltonian_like_N6M"] = run_hamiltonian(pkg, pm, dev, stream)
+        ex["rcm_mesh3d_280"] = run_rcm(pkg, pm, dev, stream, A=A, B=B)["mesh3d_280_permuted"]
     # multi-RHS on the 2D Laplacian (256^2)
     L = crsgen.laplace2d(256)
     ML = pkg.CRSMatrix.from_crs(L, device=dev)
@@ -337,24 +411,76 @@ def run_extra(A, B, M, pkg, pm, dev, stream, args):
                         "mixed_cold_gflops": round(pm.gflops(L.nnz, c32, k), 1)}
     ex["spmm_laplace2d_256"] = spmm
     log(f"spmm: {spmm}")
-    # multi-RHS on the headline matrix with its own plan (V6 copy: one pass for k <= 8)
-    big = {"variant": variant_name(pkg, M)}
-    for k in (2, 4, 8, 16):
-        Bk = torch.from_numpy(crsgen.uniform_vec(A.n_cols * k, 4).reshape(A.n_cols, k)).to(dev)
-        Ck = torch.empty((A.n_rows, k), dtype=torch.float64, device=dev)
-        per, _ = time_launches(lambda: pkg.spmm_apply(M.handle, k, Bk, k, pkg.SPMV_F64, Ck, k),
-                               20, 3, stream)
-        t = float(np.median(per)) / 1000
-        big[str(k)] = {"us": round(t * 1e6, 1), "fp64_gflops": round(pm.gflops(A.nnz, t, k), 1)}
-        del Bk, Ck
-    ex["spmm_" + ("hamiltonian_like_N6M" if A.n_rows == 6_000_000 else "workload")] = big
-    log(f"spmm on the workload: {big}")
-    ex["split_shard"] = run_split(A, B, pkg, pm, dev, stream)
     ex["batch_4096"] = run_batch(pkg, pm, dev, stream)
     ex["laplace2d_256"] = run_small(pkg, pm, dev, stream)
     ex["solvers_laplace2d_256"] = run_solvers(pkg, dev)
-    ex["mesh3d_280_permuted"] = run_mesh(pkg, pm, dev, stream)
     return ex
+
+
+def run_hamiltonian(pkg, pm, dev, stream):
+    """The Hamiltonian-like workload (N = 6.0M, 7 symmetric offset pairs): the
+    fastest kernel that reads the caller's CRS arrays (V0-V5, every V4 form)
+    and V6 (the chunked copy) in FP64 and FP32 storage, each on the bytes its
+    kernel reads and on the CRS compulsory bytes; multi-RHS; the split shard."""
+    import numpy as np
+    import torch
+
+    import crsgen
+    log("generating Hamiltonian-like matrix N=6,000,000")
+    A = crsgen.hamiltonian(6_000_000, seed=2)
+    B = crsgen.uniform_vec(A.n_cols, 2)
+    wname = "hamiltonian_like_N6M"
+    res = {"n_rows": A.n_rows, "nnz": A.nnz}
+    C = torch.empty(A.n_rows, dtype=torch.float64, device=dev)
+    for tag, vdt, bdt, code, sv in (("fp64", torch.float64, np.float64, pkg.SPMV_F64, 8),
+                                    ("fp32_storage", torch.float32, np.float32, pkg.SPMV_F32,
+                                     4)):
+        M = pkg.CRSMatrix(A.n_rows, A.n_cols, A.row_ptr, A.col_idx, A.val.astype(bdt),
+                          val_dtype=vdt, flags=pkg.SPMV_SELECT_AUTOTUNE | SELL, device=dev)
+        Bd = torch.from_numpy(B.astype(bdt)).to(dev)
+        at = pkg.spmv_get_autotune_times(M.handle)
+        picked, pform = M.variant, M.v4_form
+        rec = {"autotune_pick": variant_name(pkg, M)}
+        # the fastest reader of the CRS arrays, with its fastest V4 form
+        best = int(np.argmin(at[:6]))
+        M.variant = best
+        if best == 4:
+            forms = {}
+            for f in (0, 1, 2):
+                M.v4_form = f
+                per, _ = time_launches(lambda: pkg.spmv_apply(M.handle, Bd, code, C), 20, 3,
+                                       stream)
+                forms[f] = float(np.median(per))
+            M.v4_form = min(forms, key=forms.get)
+        rec["crs_kernel"] = kernel_record(pkg, pm, M, A,
+                                          lambda: pkg.spmv_apply(M.handle, Bd, code, C), stream,
+                                          sv, wname)
+        if M.sell_slots is not None:
+            M.variant = pkg.SPMV_V6_SELL64
+            rec["v6_copy"] = kernel_record(pkg, pm, M, A,
+                                           lambda: pkg.spmv_apply(M.handle, Bd, code, C), stream,
+                                           sv, wname)
+        M.variant, M.v4_form = picked, pform
+        if tag == "fp64":
+            big = {"variant": variant_name(pkg, M)}
+            for k in (2, 4, 8, 16):
+                Bk = torch.from_numpy(crsgen.uniform_vec(A.n_cols * k, 4).reshape(A.n_cols, k)
+                                      ).to(dev)
+                Ck = torch.empty((A.n_rows, k), dtype=torch.float64, device=dev)
+                per, _ = time_launches(
+                    lambda: pkg.spmm_apply(M.handle, k, Bk, k, pkg.SPMV_F64, Ck, k), 20, 3, stream)
+                t = float(np.median(per)) / 1000
+                comp = pm.compulsory_bytes(A.n_rows, A.n_cols, A.nnz, k)
+                big[str(k)] = {"us": round(t * 1e6, 1), "fp64_gflops": round(pm.gflops(A.nnz, t, k), 1),
+                               "crs_equiv_frac": round(comp / t / 1e9 / HBM_PEAK, 4)}
+                del Bk, Ck
+            rec["spmm"] = big
+        res[tag] = rec
+        log(f"hamiltonian {tag}: {rec}")
+        del M, Bd
+        torch.cuda.empty_cache()
+    res["split_shard"] = run_split(A, B, pkg, pm, dev, stream)
+    return res
 
 
 def run_split(A, B, pkg, pm, dev, stream):
@@ -393,18 +519,23 @@ def run_split(A, B, pkg, pm, dev, stream):
     return res
 
 
-def run_rcm(pkg, pm, dev, stream):
-    """Reverse Cuthill-McKee (host, library) on the two large workloads; the
-    reordered product P A P^T (P B) is timed against the product as given."""
+def run_rcm(pkg, pm, dev, stream, A=None, B=None, both=False):
+    """Reverse Cuthill-McKee (host, library) on the permuted mesh (and with
+    `both` the Hamiltonian-like matrix): host ordering and permutation times,
+    and the reordered product P A P^T (P B) against the product as given
+    (autotuned plans, kernel ms)."""
     import numpy as np
     import torch
 
     import crsgen
     out = {"metric": "RCM reordering effect (FP64 product, kernel ms)"}
-    for name, make, seed in (("mesh3d_280_permuted", lambda: crsgen.mesh3d(280, seed=3)[0], 3),
-                             ("hamiltonian_like_N6M", lambda: crsgen.hamiltonian(6_000_000, 2), 2)):
-        A = make()
-        B = crsgen.uniform_vec(A.n_cols, seed)
+    todo = [("mesh3d_280_permuted", lambda: crsgen.mesh3d(280, seed=3)[0], 3)]
+    if both:
+        todo.append(("hamiltonian_like_N6M", lambda: crsgen.hamiltonian(6_000_000, 2), 2))
+    for name, make, seed in todo:
+        if A is None or name != "mesh3d_280_permuted":
+            A = make()
+            B = crsgen.uniform_vec(A.n_cols, seed)
         t0 = time.perf_counter()
         perm = pkg.spmv_rcm_order(A.n_rows, A.row_ptr, A.col_idx, symmetric_part=True)
         t_rcm = time.perf_counter() - t0
@@ -428,6 +559,7 @@ def run_rcm(pkg, pm, dev, stream):
             torch.cuda.empty_cache()
         out[name] = res
         log(f"rcm {name}: {res}")
+        A = B = None
     return out
 
 
@@ -526,35 +658,6 @@ def run_small(pkg, pm, dev, stream):
     return res
 
 
-def run_mesh(pkg, pm, dev, stream):
-    """The permuted 3D stencil with random extras (N = 21.95M), FP64 and FP32 storage."""
-    import numpy as np
-    import torch
-
-    import crsgen
-    log("generating permuted 3D stencil matrix N=21,952,000")
-    A = crsgen.mesh3d(280, seed=3)[0]
-    B = crsgen.uniform_vec(A.n_cols, 3)
-    res = {"n_rows": A.n_rows, "nnz": A.nnz}
-    C = torch.empty(A.n_rows, dtype=torch.float64, device=dev)
-    for tag, vdt, bdt, code, sv in (("fp64", torch.float64, np.float64, pkg.SPMV_F64, 8),
-                                    ("mixed_fp32_storage", torch.float32, np.float32,
-                                     pkg.SPMV_F32, 4)):
-        M = pkg.CRSMatrix(A.n_rows, A.n_cols, A.row_ptr, A.col_idx, A.val.astype(bdt),
-                          val_dtype=vdt, flags=pkg.SPMV_SELECT_AUTOTUNE | SELL, device=dev)
-        Bd = torch.from_numpy(B.astype(bdt)).to(dev)
-        per, _ = time_launches(lambda: pkg.spmv_apply(M.handle, Bd, code, C), 30, 3, stream)
-        t = float(np.median(per)) / 1000
-        eff = pm.effective_gbs(A.n_rows, A.n_cols, A.nnz, t, 1, sv, sv)
-        res[tag] = {"variant": variant_name(pkg, M), "kernel_ms": round(t * 1e3, 4),
-                    "gflops": round(pm.gflops(A.nnz, t), 1), "eff_gbs": round(eff, 1),
-                    "pct_of_8tbs": round(100 * eff / HBM_PEAK, 1)}
-        del M, Bd
-        torch.cuda.empty_cache()
-    log(f"mesh: {res}")
-    return res
-
-
 def run_batch(pkg, pm, dev, stream):
     """Uneven batch: 4096 seeded matrices, N log-uniform in [100, 5000]."""
     import numpy as np
@@ -565,16 +668,22 @@ def run_batch(pkg, pm, dev, stream):
     mats = [crsgen.family_matrix(6, i, 100, 5000)[0] for i in range(4096)]
     Bt = pkg.Batch(mats, device=dev)
     nnz, rows = int(Bt.nnz.sum()), int(Bt.n_rows.sum())
+    # CRS compulsory bytes, and the bytes the tiles read: their 1- or 2-byte
+    # column deltas in place of 4-byte indices, plus row_ptr, B and C
     comp = sum(pm.compulsory_bytes(m.n_rows, m.n_cols, m.nnz) for m in mats)
+    own = Bt.stream_bytes + sum(4 * (m.n_rows + 1) + 8 * m.n_cols + 8 * m.n_rows for m in mats)
     B_all = torch.from_numpy(crsgen.uniform_vec(int(Bt.n_cols.sum()), 6)).to(dev)
     C_all = torch.empty(rows, dtype=torch.float64, device=dev)
     Bd, Cd, bh, ch = Bt.pointers(B_all, C_all)
-    res = {"count": 4096, "rows": rows, "nnz": nnz, "tiles": Bt.ntiles}
+    res = {"count": 4096, "rows": rows, "nnz": nnz, "tiles": Bt.ntiles,
+           "crs_compulsory_bytes": comp, "own_bytes_per_launch": own}
 
     def rec(name, fn, steps=20):
         per, _ = time_launches(fn, steps, 3, stream)
         t = float(np.median(per)) / 1000
-        res[name] = {"us": round(t * 1e6, 1), "eff_gbs": round(comp / t / 1e9, 1),
+        res[name] = {"us": round(t * 1e6, 1), "own_gbs": round(own / t / 1e9, 1),
+                     "own_frac": round(own / t / 1e9 / HBM_PEAK, 4),
+                     "crs_equiv_gbs": round(comp / t / 1e9, 1),
                      "gflops": round(pm.gflops(nnz, t), 1)}
 
     for mode, name in ((pkg.SPMV_BATCH_DYNAMIC, "persistent_dynamic"),
@@ -587,7 +696,8 @@ def run_batch(pkg, pm, dev, stream):
     # memory-side cache held from the previous launch
     t = cold_time(lambda: Bt.apply(Bd, Cd), stream)
     res["one_launch_tile_grid_cold"] = {"us": round(t * 1e6, 1),
-                                        "eff_gbs": round(comp / t / 1e9, 1),
+                                        "own_gbs": round(own / t / 1e9, 1),
+                                        "crs_equiv_gbs": round(comp / t / 1e9, 1),
                                         "gflops": round(pm.gflops(nnz, t), 1)}
     rec("separate_launches_4096", lambda: Bt.apply_each(bh, ch), steps=5)
     s = torch.cuda.Stream()
@@ -607,21 +717,67 @@ def run_batch(pkg, pm, dev, stream):
     return res
 
 
+def host_description():
+    """Cores, sockets, NUMA nodes and model of the host (lscpu), and the CPUs
+    this process may run on."""
+    import subprocess
+    info = {"usable_cpus": len(os.sched_getaffinity(0)), "os_cpu_count": os.cpu_count()}
+    try:
+        txt = subprocess.run(["lscpu"], capture_output=True, text=True, timeout=10).stdout
+        keys = {"Model name": "model", "Socket(s)": "sockets", "Core(s) per socket":
+                "cores_per_socket", "Thread(s) per core": "threads_per_core",
+                "NUMA node(s)": "numa_nodes", "CPU(s)": "cpus"}
+        for line in txt.splitlines():
+            k, _, v = line.partition(":")
+            if k.strip() in keys:
+                v = v.strip()
+                info[keys[k.strip()]] = int(v) if v.isdigit() else v
+    except (OSError, subprocess.SubprocessError):
+        pass
+    return info
+
+
 def cpu_baseline(A, B):
-    """The oracle (single-threaded plain C) timed on the host: whole-matrix
-    products repeated until about 10 s of CPU time have passed."""
+    """The oracle (single-threaded plain C) timed on one host core, and the
+    paper's node scheme (OpenMP static schedule over rows, first-touch
+    placement; oracle/node.c) on all the host CPUs this process may use, with
+    a host triad for its fraction of STREAM. Both on the headline matrix,
+    whole products repeated for a bounded sample."""
+    import numpy as np
+
     import oracle
-    log("cpu baseline: timing the oracle")
+    import oracle.node as node
+    host = host_description()
+    log(f"cpu baseline: timing the oracle on one core ({host})")
     reps, t = 0, 0.0
+    Cref = None
     while t < 10.0 and reps < 1000:
         t0 = time.perf_counter()
-        oracle.spmv(A.n_rows, A.row_ptr, A.col_idx, A.val, B)
+        Cref, _ = oracle.spmv(A.n_rows, A.row_ptr, A.col_idx, A.val, B)
         t += time.perf_counter() - t0
         reps += 1
     gf = 2.0 * A.nnz * reps / t / 1e9
-    return {"value": round(gf, 3), "unit": "GFlop/s", "cores": 1, "kind": "oracle",
-            "sample": f"{reps} full products of the same matrix (nnz={A.nnz}), "
-                      f"{t:.1f} s, single thread, includes the |a*b| magnitude sum"}
+    base = {"value": round(gf, 3), "unit": "GFlop/s", "cores": 1, "kind": "oracle",
+            "sample": f"{reps} full products of the headline matrix (nnz={A.nnz}), {t:.1f} s, "
+                      "single thread, includes the |a*b| magnitude sum",
+            "host": host}
+    log("cpu baseline: the paper's node scheme on all usable host CPUs")
+    C, nreps, secs = node.spmv_bench(A.n_rows, A.n_cols, A.row_ptr, A.col_idx, A.val, B,
+                                     min_seconds=8.0, max_reps=200)
+    triad = node.triad_gbs(1 << 27, 10)
+    ngf = 2.0 * A.nnz * nreps / secs / 1e9
+    from paper_1101_0091_amd import perfmodel as pm
+    comp = pm.compulsory_bytes(A.n_rows, A.n_cols, A.nnz)
+    gbs = comp * nreps / secs / 1e9
+    scheme = {"value": round(ngf, 3), "unit": "GFlop/s", "threads": node.threads(),
+              "kind": "OpenMP static rows + first touch (paper Sect. 2)",
+              "eff_gbs": round(gbs, 2), "host_triad_gbs": round(triad, 2),
+              "pct_of_host_triad": round(100.0 * gbs / triad, 1),
+              "equals_oracle_bitwise": bool(np.array_equal(C.view(np.int64),
+                                                           Cref.view(np.int64))),
+              "sample": f"{nreps} full products, {secs:.1f} s"}
+    log(f"node scheme: {scheme}")
+    return base, scheme
 
 
 if __name__ == "__main__":

@@ -197,6 +197,12 @@ int spmv_get_autotune_times(spmv_handle h, double* us);
 /* Slots of the V6 copy (host out): 64 * sum of chunk widths, >= nnz; the
  * padding is slots - nnz. SPMV_ERR_STATE if the plan has no V6 copy. */
 int spmv_get_sell_slots(spmv_handle h, int64_t* slots);
+/* Bytes one V6 product reads from the copy (host out): per chunk its offset
+ * and delta flag, its slot bases where it has deltas, and per slot the value
+ * and the column (1- or 2-byte delta or 4-byte index). B and C come on top.
+ * Copies the chunk widths and flags to the host (blocking). SPMV_ERR_STATE if
+ * the plan has no V6 copy. */
+int spmv_get_sell_stream_bytes(spmv_handle h, int64_t* bytes);
 /* Chunks of the V6 copy read through 8-bit and through 16-bit column deltas,
  * and all chunks (host out). Copies the per-chunk flags to the host (a
  * blocking copy after the device work of create, which has completed when
@@ -311,6 +317,12 @@ int spmv_batch_get_num_tiles(spmv_batch_handle h, int64_t* ntiles);
  * All three give bitwise-identical results. */
 typedef enum { SPMV_BATCH_DYNAMIC = 0, SPMV_BATCH_STATIC = 1, SPMV_BATCH_TILE_GRID = 2 } spmv_batch_mode;
 int spmv_batch_set_mode(spmv_batch_handle h, int mode);
+/* Bytes one spmv_batch_apply reads for the matrices' nonzeros (host out): per
+ * tile its record, the values, the chunk's columns (1- or 2-byte deltas where
+ * the tile has them, else 4-byte indices) and a long last row's columns past
+ * the chunk. row_ptr, B and C come on top. Copies the tile list to the host
+ * (blocking). */
+int spmv_batch_get_stream_bytes(spmv_batch_handle h, int64_t* bytes);
 int spmv_batch_destroy(spmv_batch_handle h);
 
 /* -------------------------------------------------------------- reordering */

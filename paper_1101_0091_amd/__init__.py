@@ -43,7 +43,8 @@ SPMV_MLP_PARAMS = 5638
 EXPORTS = (
     "spmv_workspace_size", "spmv_create", "spmv_apply", "spmm_apply", "spmv_get_variant",
     "spmv_set_variant", "spmv_get_features", "spmv_get_predictions", "spmv_get_autotune_times",
-    "spmv_get_num_blocks", "spmv_get_sell_slots", "spmv_get_sell_deltas", "spmv_get_v4_staged", "spmv_get_v4_form", "spmv_set_v4_form", "spmv_destroy", "spmv_batch_workspace_size", "spmv_batch_create",
+    "spmv_get_num_blocks", "spmv_get_sell_slots", "spmv_get_sell_deltas", "spmv_get_v4_staged", "spmv_get_v4_form", "spmv_set_v4_form", "spmv_get_sell_stream_bytes",
+    "spmv_batch_get_stream_bytes", "spmv_destroy", "spmv_batch_workspace_size", "spmv_batch_create",
     "spmv_batch_apply", "spmv_batch_apply_each", "spmv_batch_get_num_tiles", "spmv_batch_set_mode",
     "spmv_batch_destroy", "spmv_graph_begin", "spmv_graph_end", "spmv_graph_launch",
     "spmv_graph_destroy", "spmv_selector_load", "spmv_selector_loaded",
@@ -95,6 +96,8 @@ def lib():
             "spmv_get_sell_deltas": [P, P, P, P],
             "spmv_get_v4_staged": [P, P],
             "spmv_get_v4_form": [P, P, P],
+            "spmv_get_sell_stream_bytes": [P, P],
+            "spmv_batch_get_stream_bytes": [P, P],
             "spmv_set_v4_form": [P, ctypes.c_int],
             "spmv_destroy": [P],
             "spmv_batch_workspace_size": [i32, i64, i64, P],
@@ -278,6 +281,20 @@ def spmv_get_v4_form(h):
 
 def spmv_set_v4_form(h, form: int) -> None:
     _check(lib().spmv_set_v4_form(h, int(form)))
+
+
+def spmv_get_sell_stream_bytes(h) -> int:
+    """Bytes one V6 product reads from the plan's chunked copy."""
+    n = ctypes.c_int64(0)
+    _check(lib().spmv_get_sell_stream_bytes(h, ctypes.byref(n)))
+    return int(n.value)
+
+
+def spmv_batch_get_stream_bytes(h) -> int:
+    """Bytes one batch apply reads for the matrices' nonzeros."""
+    n = ctypes.c_int64(0)
+    _check(lib().spmv_batch_get_stream_bytes(h, ctypes.byref(n)))
+    return int(n.value)
 
 
 def spmv_destroy(h) -> None:

@@ -527,6 +527,32 @@ int spmv_get_sell_slots(spmv_handle h, int64_t* slots) {
   return SPMV_OK;
 }
 
+int spmv_get_sell_stream_bytes(spmv_handle h, int64_t* bytes) {
+  if (!h || !bytes) return fail(SPMV_ERR_INVALID_ARG, "null argument");
+  const Plan& p = h->p;
+  if (!p.sell_ok) return fail(SPMV_ERR_STATE, "this plan has no V6 copy");
+  const int64_t nch = p.sell_nch;
+  const int64_t sv = p.vdt == SPMV_F64 ? 8 : 4;
+  int64_t total = 0;
+  if (nch > 0) {
+    std::vector<int32_t> w((size_t)nch), f((size_t)nch, 0);
+    SPMV_HIP(hipMemcpy(w.data(), p.sell_width, sizeof(int32_t) * (size_t)nch,
+                       hipMemcpyDeviceToHost));
+    if (!p.sell_wide)
+      SPMV_HIP(hipMemcpy(f.data(), p.sell_flag, sizeof(int32_t) * (size_t)nch,
+                         hipMemcpyDeviceToHost));
+    for (int64_t k = 0; k < nch; ++k) {
+      const int64_t slots = 64 * (int64_t)w[k];
+      const int64_t col = f[k] == 8 ? 1 : f[k] == 16 ? 2 : 4;
+      // chunk offset and delta flag, the slot bases (delta chunks), then per
+      // slot its value and its column (delta or index)
+      total += 8 + (f[k] ? 4 * (int64_t)w[k] : 0) + slots * (sv + col);
+    }
+  }
+  *bytes = total;
+  return SPMV_OK;
+}
+
 int spmv_get_sell_deltas(spmv_handle h, int64_t* chunks8, int64_t* chunks16, int64_t* chunks) {
   if (!h || !chunks8 || !chunks16 || !chunks) return fail(SPMV_ERR_INVALID_ARG, "null argument");
   if (!h->p.sell_ok) return fail(SPMV_ERR_STATE, "this plan has no V6 copy");
@@ -719,6 +745,29 @@ int spmv_batch_set_mode(spmv_batch_handle h, int mode) {
 int spmv_batch_get_num_tiles(spmv_batch_handle h, int64_t* ntiles) {
   if (!h || !ntiles) return fail(SPMV_ERR_INVALID_ARG, "null argument");
   *ntiles = h->b.ntiles;
+  return SPMV_OK;
+}
+
+int spmv_batch_get_stream_bytes(spmv_batch_handle h, int64_t* bytes) {
+  if (!h || !bytes) return fail(SPMV_ERR_INVALID_ARG, "null argument");
+  const Batch& b = h->b;
+  const int64_t sv = b.vdt == SPMV_F64 ? 8 : 4;
+  int64_t total = 0;
+  if (b.ntiles > 0) {
+    std::vector<int32_t> t((size_t)(kTileInts * b.ntiles));
+    SPMV_HIP(hipMemcpy(t.data(), b.tiles, sizeof(int32_t) * t.size(), hipMemcpyDeviceToHost));
+    for (int64_t k = 0; k < b.ntiles; ++k) {
+      const int32_t* tl = t.data() + kTileInts * k;
+      const int64_t n = (int64_t)tl[4] - tl[3];
+      if (tl[2] <= tl[1] || n < 0) continue;
+      const int64_t in = n < kBlockBudget ? n : kBlockBudget;
+      const int64_t col = tl[7] == 8 ? 1 : tl[7] == 16 ? 2 : 4;
+      // the tile record, the values, the chunk's columns (as deltas where the
+      // tile has them) and a long last row's columns past the chunk
+      total += 4 * kTileInts + n * sv + in * col + (n - in) * 4;
+    }
+  }
+  *bytes = total;
   return SPMV_OK;
 }
 

@@ -7,7 +7,8 @@ import numpy as np
 
 from . import (SPMV_ERR_STATE, SPMV_F32, SPMV_F64, SPMV_SELECT_DEFAULT, SPMV_SELECT_MLP,
                SpmvError, dtype_code, spmv_get_sell_deltas, spmv_get_sell_slots, spmv_get_v4_staged,
-               spmv_get_v4_form, spmv_set_v4_form,
+               spmv_get_v4_form, spmv_set_v4_form, spmv_get_sell_stream_bytes,
+               spmv_batch_get_stream_bytes,
                load_selector, spmv_selector_loaded, spmm_apply, spmv_apply, spmv_batch_apply,
                spmv_batch_apply_each, spmv_batch_create, spmv_batch_destroy, spmv_batch_set_mode,
                spmv_batch_get_num_tiles, spmv_batch_workspace_size, spmv_create, spmv_destroy,
@@ -115,6 +116,17 @@ class CRSMatrix:
             raise
 
     @property
+    def sell_stream_bytes(self):
+        """Bytes one V6 product reads from the chunked copy, or None if the
+        plan has none."""
+        try:
+            return spmv_get_sell_stream_bytes(self.handle)
+        except SpmvError as e:
+            if e.status == SPMV_ERR_STATE:
+                return None
+            raise
+
+    @property
     def sell_deltas(self):
         """(chunks read through 8-bit column deltas, through 16-bit ones, all
         chunks), or None if the plan has no V6 copy."""
@@ -189,6 +201,12 @@ class Batch:
                                         self.rp_ptrs, self.ci_ptrs, self.val_ptrs, self.code,
                                         self.workspace, self.ws_bytes, stream)
         self.ntiles = spmv_batch_get_num_tiles(self.handle)
+
+    @property
+    def stream_bytes(self) -> int:
+        """Bytes one apply reads for the matrices' nonzeros (row_ptr, B and C
+        not included)."""
+        return spmv_batch_get_stream_bytes(self.handle)
 
     def pointers(self, B_all, C_all):
         """Per-matrix device addresses into one slab of B (sum n_cols) and C (sum n_rows)."""

@@ -22,6 +22,9 @@ def _ensure_built():
         crsgen.build()
     if not os.path.exists(os.path.join(ROOT, "oracle", "liboracle.so")):
         oracle.build()
+    if not os.path.exists(os.path.join(ROOT, "oracle", "libnode.so")):
+        import oracle.node
+        oracle.node.build()
 
 
 _ensure_built()
