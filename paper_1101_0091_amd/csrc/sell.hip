@@ -296,7 +296,9 @@ __device__ __forceinline__ double sell_pairs_row(int64_t a, int32_t w, int lane,
         if (p + u < P) {
           v[u] = dev::ld_stream(vp + (int64_t)(p + u) * kChunk);
           d[u] = dev::ld_stream(dp + (int64_t)(p + u) * kChunk);
-          b[u] = *reinterpret_cast<const i32x2*>(bp + 2 * (p + u));
+          // two 4-byte loads: a chunk's bases start at an offset that can
+          // be odd, so the pair is only 4-byte aligned
+          b[u] = i32x2{bp[2 * (p + u)], bp[2 * (p + u) + 1]};
         } else {
           v[u] = V2{(VT)0, (VT)0};
           d[u] = 0xFFFFFFFFu;
@@ -441,7 +443,9 @@ __device__ __forceinline__ double sell_quads_row(int64_t a, int32_t w, int lane,
         if (q + u < Q) {
           v[u] = dev::ld_stream(vp + (int64_t)(q + u) * kChunk);
           d[u] = dev::ld_stream(dp + (int64_t)(q + u) * kChunk);
-          b[u] = *reinterpret_cast<const i32x4*>(bp + 4 * (q + u));
+          // four 4-byte loads: a chunk's bases are only 4-byte aligned
+          b[u] = i32x4{bp[4 * (q + u)], bp[4 * (q + u) + 1], bp[4 * (q + u) + 2],
+                       bp[4 * (q + u) + 3]};
         } else {
           v[u] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
           if constexpr (DB == 16)
