@@ -243,6 +243,24 @@ int spmv_cg_solve(spmv_handle h, const double* b, double* x, double tol, int32_t
                   int32_t* iters, double* relres, void* stream);
 
 /*
+ * spmv_cg_solve for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid it): the
+ * solver scratch (residual, search direction, A p, the float32 copy for
+ * FP32-storage plans, the reduction partials and arrival counters) lives in
+ * a file-scope device array of the library, 32 MiB per GPU, held from the
+ * first call on that GPU until the process ends. No call allocates, frees or
+ * calls an allocating routine. Iterations run as separate launches (no graph
+ * mode). Arguments, results and synchronisation as spmv_cg_solve; the plan's
+ * device must be current (else SPMV_ERR_STATE).
+ * Limit: n <= 1,197,888 (28 bytes per row plus 13 KB), else
+ * SPMV_ERR_UNSUPPORTED. Every call on a GPU shares that GPU's array and the
+ * array keeps the last call's contents (each call initialises what it reads):
+ * calls that overlap in time on one GPU race, from any host thread or stream.
+ */
+int spmv_cg_solve_noalloc(spmv_handle h, const double* b, double* x, double tol, int32_t maxit,
+                          int32_t check_every, int32_t* iters, double* relres, void* stream);
+
+/*
  * k steps of the Lanczos recurrence (no reorthogonalisation) from the device
  * start vector v0 (float64[n], not modified, must be nonzero). Host out:
  * alpha[0..k-1] (diagonal of T_k) and beta[0..k-1] with beta[j] = beta_{j+1}

@@ -53,7 +53,7 @@ EXPORTS = (
     "spmv_status_string", "spmv_last_error", "spmv_version", "spmv_split_workspace_size",
     "spmv_split_create", "spmv_split_apply", "spmv_split_get_nnz", "spmv_split_destroy",
     "spmv_rcm_order", "spmv_permute_crs", "spmv_cg_workspace_size", "spmv_cg_solve",
-    "spmv_lanczos_workspace_size", "spmv_lanczos",
+    "spmv_lanczos_workspace_size", "spmv_lanczos", "spmv_cg_solve_noalloc",
 )
 
 
@@ -128,6 +128,7 @@ def lib():
             "spmv_cg_workspace_size": [i64, P],
             "spmv_cg_solve": [P, P, P, f64, i32, i32, i32, P, sz, P, P, P],
             "spmv_lanczos_workspace_size": [i64, i32, P],
+            "spmv_cg_solve_noalloc": [P, P, P, f64, i32, i32, P, P, P],
             "spmv_lanczos": [P, P, i32, P, P, P, sz, P],
             "spmv_permute_crs": [i64, P, P, P, ctypes.c_int, P, P, P, P],
             "spmv_status_string": [ctypes.c_int],
@@ -486,6 +487,16 @@ def spmv_cg_solve(h, b, x, tol, maxit, check_every, use_graph, workspace, ws_byt
     _check(lib().spmv_cg_solve(h, _ptr(b), _ptr(x), float(tol), int(maxit), int(check_every),
                                int(bool(use_graph)), _ptr(workspace), int(ws_bytes),
                                ctypes.byref(it), ctypes.byref(rr), _stream(stream)))
+    return int(it.value), float(rr.value)
+
+
+def spmv_cg_solve_noalloc(h, b, x, tol, maxit, check_every, stream=None):
+    """spmv_cg_solve with the library's own static scratch (no allocation).
+    Returns (iterations, recurrence relative residual)."""
+    it, rr = ctypes.c_int32(0), ctypes.c_double(0.0)
+    _check(lib().spmv_cg_solve_noalloc(h, _ptr(b), _ptr(x), float(tol), int(maxit),
+                                       int(check_every), ctypes.byref(it), ctypes.byref(rr),
+                                       _stream(stream)))
     return int(it.value), float(rr.value)
 
 

@@ -3,6 +3,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -804,6 +805,70 @@ int spmv_cg_solve(spmv_handle h, const double* b, double* x, double tol, int32_t
   double rr = 0.0;
   const int st = run_cg(P, b, x, tol, maxit, check_every, use_graph != 0, workspace, &it, &rr,
                         as_stream(stream));
+  *iters = it;
+  *relres = rr;
+  return st;
+}
+
+}  // extern "C"
+
+// ---- CG with library-held scratch, for callers that cannot allocate
+//
+// `scratch` is one file-scope device array; every GPU the library runs on
+// holds its own copy (at its own address) until the process ends. In host
+// code the array's name is a host-side stand-in, not a device address: its
+// device address is looked up once per device, with that device current,
+// and only that pointer is handed to kernels.
+namespace {
+constexpr size_t kNoAllocScratchBytes = size_t(32) << 20;
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_dev[kMaxDevices] = {};
+}  // namespace
+
+static __device__ __align__(256) unsigned char scratch[kNoAllocScratchBytes];
+
+namespace {
+int scratch_device_ptr(int dev, void** out) {
+  if (dev < 0 || dev >= kMaxDevices)
+    return fail(SPMV_ERR_UNSUPPORTED, "device index beyond the scratch table");
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_dev[dev]) {
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return hip_fail(e, "hipGetSymbolAddress(scratch)");
+    if (!p) return fail(SPMV_ERR_HIP, "hipGetSymbolAddress(scratch) returned null");
+    g_scratch_dev[dev] = p;
+  }
+  *out = g_scratch_dev[dev];
+  return SPMV_OK;
+}
+}  // namespace
+
+extern "C" {
+
+int spmv_cg_solve_noalloc(spmv_handle h, const double* b, double* x, double tol, int32_t maxit,
+                          int32_t check_every, int32_t* iters, double* relres, void* stream) {
+  if (!h || !iters || !relres) return fail(SPMV_ERR_INVALID_ARG, "null argument");
+  const Plan& P = h->p;
+  if (P.n_rows != P.n_cols) return fail(SPMV_ERR_INVALID_ARG, "CG needs a square matrix");
+  if (P.n_rows > 0 && (!b || !x)) return fail(SPMV_ERR_INVALID_ARG, "b or x is null");
+  if (!(tol >= 0.0) || maxit < 0) return fail(SPMV_ERR_INVALID_ARG, "tol >= 0 and maxit >= 0");
+  const size_t need = cg_workspace_bytes(P.n_rows);
+  if (need > kNoAllocScratchBytes)
+    return fail(SPMV_ERR_UNSUPPORTED,
+                "n = " + std::to_string(P.n_rows) + " needs " + std::to_string(need) +
+                    " bytes of solver scratch; the library holds " +
+                    std::to_string(kNoAllocScratchBytes) + " (n <= 1197888)");
+  int dev = 0;
+  SPMV_HIP(hipGetDevice(&dev));
+  if (dev != P.device) return fail(SPMV_ERR_STATE, "the plan's device must be current");
+  void* ws = nullptr;
+  int st = scratch_device_ptr(dev, &ws);
+  if (st) return st;
+  int it = 0;
+  double rr = 0.0;
+  st = run_cg(P, b, x, tol, maxit, check_every, false, ws, &it, &rr, as_stream(stream));
   *iters = it;
   *relres = rr;
   return st;
