@@ -708,11 +708,17 @@ def run_batch(pkg, pm, dev, stream):
     pkg.spmv_graph_begin(s)
     Bt.apply(Bd, Cd, stream=s)
     g_one = pkg.spmv_graph_end(s)
+    Bt.set_mode(pkg.SPMV_BATCH_DYNAMIC)
+    pkg.spmv_graph_begin(s)
+    Bt.apply(Bd, Cd, stream=s)
+    g_dyn = pkg.spmv_graph_end(s)
+    Bt.set_mode(pkg.SPMV_BATCH_TILE_GRID)
     torch.cuda.synchronize()
     rec("graph_of_4096_launches", lambda: pkg.spmv_graph_launch(g_each, stream), steps=5)
-    rec("graph_of_persistent", lambda: pkg.spmv_graph_launch(g_one, stream))
-    pkg.spmv_graph_destroy(g_each)
-    pkg.spmv_graph_destroy(g_one)
+    rec("graph_of_one_tile_grid_launch", lambda: pkg.spmv_graph_launch(g_one, stream))
+    rec("graph_of_persistent_dynamic", lambda: pkg.spmv_graph_launch(g_dyn, stream))
+    for g in (g_each, g_one, g_dyn):
+        pkg.spmv_graph_destroy(g)
     log(f"batch: {res}")
     return res
 

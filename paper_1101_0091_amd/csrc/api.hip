@@ -460,7 +460,10 @@ int spmm_apply(spmv_handle h, int32_t k, const void* B, int64_t ldb, int b_dtype
   // lane per row (5-point Laplacians, 262k and 1M rows: the copy took 1.1-1.3x
   // as long at k = 4 and 1.5-1.8x at k = 8; a 15-entry-per-row matrix ran
   // 1.1-2x faster from the copy)
-  if (p.variant == SPMV_V6_SELL64 && p.sell_ok && k <= 8 && p.nnz >= 8 * p.n_rows)
+  // (lane groups per row, one 16-byte B vector per lane: k = 4, 8, 16, 32
+  // in float64, 8 .. 64 in float32, aligned operands)
+  if (p.variant == SPMV_V6_SELL64 && p.sell_ok && p.nnz >= 8 * p.n_rows &&
+      (k <= 8 || sell_spmm_lanes_fit(p, k, B, ldb, C, ldc)))
     return launch_sell_spmm(p, k, B, ldb, C, ldc, as_stream(stream));
   return launch_spmm(p, k, B, ldb, C, ldc, as_stream(stream));
 }
@@ -595,7 +598,7 @@ BatchLayout batch_layout(int32_t count, int64_t max_tiles) {
   BatchLayout L;
   size_t o = 0;
   L.err = o;
-  o += 256;  // err[2] at 0, tile counters[2] at 128
+  o += 256 + align256(sizeof(unsigned int) * kBatchCounterWords);  // err[2], then the counters
   L.tiles = o;
   o += align256(sizeof(int32_t) * kTileInts * (size_t)std::max<int64_t>(max_tiles, 1));
   L.deltas = o;
@@ -663,10 +666,13 @@ int spmv_batch_create(spmv_batch_handle* h, int32_t count, const int64_t* n_rows
   b.deltas = reinterpret_cast<uint8_t*>(ws + L.deltas);
   b.ntiles = ntiles;
   b.err = reinterpret_cast<int32_t*>(ws + L.err);
-  b.counters = reinterpret_cast<unsigned int*>(ws + L.err + 128);
+  b.counters = reinterpret_cast<unsigned int*>(ws + L.err + 256);
   int dev = 0;
   hipGetDevice(&dev);
-  b.grid = batch_grid(dev);
+  if (int st0 = batch_grids(dev, val_dtype, &b.grid_static, &b.grid_dynamic)) {
+    delete H;
+    return st0;
+  }
   b.tile_offset_host = new int64_t[(size_t)count + 1];
   std::memcpy(b.tile_offset_host, toff.data(), sizeof(int64_t) * ((size_t)count + 1));
   b.rp_host = new const int32_t*[(size_t)count];

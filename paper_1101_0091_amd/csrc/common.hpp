@@ -130,13 +130,16 @@ struct Batch {
   uint8_t* deltas = nullptr;  // device [ntiles][2 * kBlockBudget]: column deltas per tile chunk
   int64_t ntiles = 0;
   int32_t* err = nullptr;     // device
-  unsigned int* counters = nullptr;  // device [2]: next tile, finished workgroups
+  // device: kBatchQueues claim counters, then the finished-workgroup counter,
+  // kBatchCounterStride words apart
+  unsigned int* counters = nullptr;
   int mode = SPMV_BATCH_TILE_GRID;
   int64_t* tile_offset_host = nullptr;  // host [count+1]
   const int32_t** rp_host = nullptr;    // host copies of the device pointer arrays
   const int32_t** ci_host = nullptr;
   const void** val_host = nullptr;
-  int grid = 0;
+  int grid_static = 0;   // resident workgroups of the persistent kernels
+  int grid_dynamic = 0;  // (CUs x workgroups per CU at their occupancy)
 };
 
 // ---------------------------------------------------------------- errors
@@ -187,7 +190,12 @@ int launch_batch_build(Batch& b, const int64_t* tile_offset_dev, const int64_t* 
                        const int64_t* n_cols_dev, const int64_t* nnz_dev, hipStream_t s);
 int launch_batch_apply(const Batch& b, int64_t t0, int64_t t1, const void* const* Bs,
                        double* const* Cs, const void* B1, double* C1, hipStream_t s);
-int batch_grid(int device);
+constexpr int kBatchQueues = kNumXCD;   // claim queues of the dynamic batch kernel
+constexpr int kBatchCounterStride = 32;  // 128 bytes between counters
+constexpr int kBatchCounterWords = (kBatchQueues + 1) * kBatchCounterStride;
+// workgroups of the static and dynamic persistent kernels that fit on the
+// device at once, for value type vdt
+int batch_grids(int device, int vdt, int* g_static, int* g_dynamic);
 int launch_counters_init(unsigned int* c, hipStream_t s);
 // mlp.hip
 int launch_mlp_forward(const float* theta, const float* X, int nb, float* Y, float* Z1,
@@ -211,6 +219,10 @@ int64_t sell_chunks(int64_t n_rows);
 int64_t sell_capacity(int64_t nnz);
 int launch_sell_build(Plan& p, hipStream_t s);
 int launch_sell(const Plan& p, const void* B, double* C, hipStream_t s);
+// whether the lane-group multi-RHS kernel of the chunked copy takes this k
+// and these operands (k / vector width in {2, 4, 8, 16}, 16-byte alignment)
+bool sell_spmm_lanes_fit(const Plan& p, int k, const void* B, int64_t ldb, const double* C,
+                         int64_t ldc);
 int launch_sell_spmm(const Plan& p, int k, const void* B, int64_t ldb, double* C, int64_t ldc,
                      hipStream_t s);
 // window.hip

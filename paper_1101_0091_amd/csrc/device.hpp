@@ -90,6 +90,17 @@ __device__ __forceinline__ double widen(T x) {
   return (double)x;
 }
 
+// Workgroup barrier that orders LDS accesses only. __syncthreads also waits
+// for every outstanding global access of the wave (on CDNA one counter covers
+// loads and stores), so a persistent workgroup would sit out the write latency
+// of one tile's results before loading the next tile; this barrier lets those
+// stores drain while the next loads are in flight.
+__device__ __forceinline__ void lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+  __builtin_amdgcn_s_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
 // ------------------------------------------------------------ XCD remap
 // Workgroups are dispatched round-robin over the 8 XCDs (w -> XCD w % 8).
 // Map them so that each XCD walks one contiguous range of tiles, which keeps

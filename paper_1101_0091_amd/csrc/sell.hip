@@ -747,6 +747,133 @@ __global__ __launch_bounds__(kWG) void k_sell_spmm(int64_t nch, int64_t n,
   }
 }
 
+// Multi-RHS from the chunked copy with LPR lanes per row: lane g of a row
+// owns the CPL columns c0 + g CPL .. (one 16-byte vector of B: 2 float64 or
+// 4 float32), so the LPR lanes of a row read its B row segment as one
+// contiguous piece, and the 64 / LPR rows of a wavefront (consecutive rows of
+// one chunk) read consecutive segments where their columns are consecutive.
+// Wavefront w takes part w % LPR of chunk w / LPR. A row's entries are taken
+// kSpmmLU per round, all their loads issued before the first is used; the
+// lanes of a row load the same value and column (one memory access).
+// Needs B, C, ldb and ldc aligned to the vector (checked by the caller) and
+// c0 + LPR CPL <= k. With remap set, each XCD takes a contiguous range of
+// chunks (instead of every eighth workgroup), so that B rows shared by rows a
+// few thousand apart (offset diagonals) can meet again in that XCD's L2.
+constexpr int kSpmmLU = 16;
+
+template <typename VT, typename BT, int LPR, int DB>
+__device__ __forceinline__ void sell_spmm_lanes_rows(int64_t a, int32_t w, int row, int g,
+                                                     int32_t c0,
+                                                     const int32_t* __restrict__ sci,
+                                                     const uint16_t* __restrict__ sdl,
+                                                     const int32_t* __restrict__ sbase,
+                                                     const VT* __restrict__ sval,
+                                                     const BT* __restrict__ B, int64_t ldb,
+                                                     double* acc) {
+  constexpr int G = kGroup<VT>;
+  constexpr int CPL = 16 / sizeof(BT);
+  using V = typename std::conditional<sizeof(BT) == 8, f64x2, f32x4>::type;
+  using DT = typename std::conditional<DB == 16, uint16_t, uint8_t>::type;
+  const DT* dp = reinterpret_cast<const DT*>(sdl + a * kChunk);
+  const int32_t* bp = sbase + a;
+  for (int32_t j = 0; j < w; j += kSpmmLU) {
+    VT vr[kSpmmLU];
+    int32_t c[kSpmmLU];
+    if constexpr (DB > 0) {
+      uint32_t d[kSpmmLU];
+      int32_t b[kSpmmLU];
+#pragma unroll
+      for (int u = 0; u < kSpmmLU; ++u) {
+        if (j + u < w) {
+          const int64_t o = slot_offset<G>(j + u, row, w);
+          vr[u] = dev::ld_stream(sval + a * kChunk + o);
+          d[u] = dev::ld_stream(dp + o);
+          b[u] = bp[j + u];
+        } else {
+          vr[u] = (VT)0;
+          d[u] = kPad<DB>;
+          b[u] = 0;
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < kSpmmLU; ++u) asm volatile("" : "+v"(d[u]));
+#pragma unroll
+      for (int u = 0; u < kSpmmLU; ++u) c[u] = delta_col<DB>(d[u], b[u]);
+    } else {
+#pragma unroll
+      for (int u = 0; u < kSpmmLU; ++u) {
+        if (j + u < w) {
+          const int64_t o = a * kChunk + slot_offset<G>(j + u, row, w);
+          vr[u] = dev::ld_stream(sval + o);
+          c[u] = dev::ld_stream(sci + o);
+        } else {
+          vr[u] = (VT)0;
+          c[u] = -1;
+        }
+      }
+    }
+    V x[kSpmmLU];
+#pragma unroll
+    for (int u = 0; u < kSpmmLU; ++u) {
+      x[u] = V{};
+      if (c[u] >= 0)
+        x[u] = *reinterpret_cast<const V*>(B + (int64_t)c[u] * ldb + c0 + g * CPL);
+    }
+    // the values and segments in their own types until every load is issued
+#pragma unroll
+    for (int u = 0; u < kSpmmLU; ++u) {
+      asm volatile("" : "+v"(vr[u]));
+      asm volatile("" : "+v"(x[u]));
+    }
+    // masked slots add fma(0, 0, acc) = acc exactly (acc is never -0)
+#pragma unroll
+    for (int u = 0; u < kSpmmLU; ++u) {
+      const double v = dev::widen(vr[u]);
+      acc[0] = fma(v, (double)x[u][0], acc[0]);
+      acc[1] = fma(v, (double)x[u][1], acc[1]);
+      if constexpr (CPL == 4) {
+        acc[2] = fma(v, (double)x[u][2], acc[2]);
+        acc[3] = fma(v, (double)x[u][3], acc[3]);
+      }
+    }
+  }
+}
+
+template <typename VT, typename BT, int LPR>
+__global__ __launch_bounds__(kWG) void k_sell_spmm_lanes(
+    int64_t nch, int64_t n, const int32_t* __restrict__ off, const int32_t* __restrict__ sci,
+    const int32_t* __restrict__ flag, const int32_t* __restrict__ sbase,
+    const uint16_t* __restrict__ sdl, const VT* __restrict__ sval, const BT* __restrict__ B,
+    int64_t ldb, double* __restrict__ C, int64_t ldc, int32_t c0, int remap) {
+  constexpr int CPL = 16 / sizeof(BT);
+  const int64_t blk = remap ? dev::xcd_remap(blockIdx.x, gridDim.x) : (int64_t)blockIdx.x;
+  const int64_t wv = __builtin_amdgcn_readfirstlane(
+      (int32_t)((blk * kWG + threadIdx.x) / kChunk));
+  const int64_t chunk = wv / LPR;
+  if (chunk >= nch) return;
+  const int lane = threadIdx.x % kChunk;
+  const int row = (int)(wv % LPR) * (kChunk / LPR) + lane / LPR;  // row inside the chunk
+  const int g = lane % LPR;
+  const int64_t a = off[chunk];
+  const int32_t w = (int32_t)(off[chunk + 1] - a);
+  double acc[CPL];
+#pragma unroll
+  for (int t = 0; t < CPL; ++t) acc[t] = 0.0;
+  const int db = flag ? flag[chunk] : 0;
+  if (db == 8)
+    sell_spmm_lanes_rows<VT, BT, LPR, 8>(a, w, row, g, c0, sci, sdl, sbase, sval, B, ldb, acc);
+  else if (db == 16)
+    sell_spmm_lanes_rows<VT, BT, LPR, 16>(a, w, row, g, c0, sci, sdl, sbase, sval, B, ldb, acc);
+  else
+    sell_spmm_lanes_rows<VT, BT, LPR, 0>(a, w, row, g, c0, sci, sdl, sbase, sval, B, ldb, acc);
+  const int64_t r = chunk * kChunk + row;
+  if (r < n) {
+    double* out = C + r * ldc + c0 + g * CPL;
+#pragma unroll
+    for (int t = 0; t < CPL; t += 2) *reinterpret_cast<f64x2*>(out + t) = f64x2{acc[t], acc[t + 1]};
+  }
+}
+
 inline unsigned grid_chunks(int64_t nch) {
   return (unsigned)((nch * kChunk + kWG - 1) / kWG);
 }
@@ -800,9 +927,40 @@ int sell_spmm_pass(const Plan& p, int k, int c0, const BT* B, int64_t ldb, doubl
   return SPMV_OK;
 }
 
+template <typename VT, typename BT, int LPR>
+int sell_spmm_lanes_pass(const Plan& p, int c0, const BT* B, int64_t ldb, double* C,
+                         int64_t ldc, hipStream_t s) {
+  const int64_t threads = p.sell_nch * LPR * kChunk;
+  // contiguous chunk ranges per XCD once B outgrows the 256 MB last-level
+  // cache (measured on the Hamiltonian-like matrix: 12% faster at 768 MB of
+  // B, 3% slower at 384 MB)
+  const int remap = (double)p.n_cols * (LPR * 16) > 512.0 * (1 << 20);
+  k_sell_spmm_lanes<VT, BT, LPR><<<(unsigned)((threads + kWG - 1) / kWG), kWG, 0, s>>>(
+      p.sell_nch, p.n_rows, p.sell_off, p.sell_ci, p.sell_wide ? nullptr : p.sell_flag,
+      p.sell_base, p.sell_dl, static_cast<const VT*>(p.sell_val), B, ldb, C, ldc, c0, remap);
+  SPMV_HIP(hipGetLastError());
+  return SPMV_OK;
+}
+
 template <typename VT, typename BT>
 int sell_spmm_typed(const Plan& p, int k, const BT* B, int64_t ldb, double* C, int64_t ldc,
                     hipStream_t s) {
+  // lane groups: k a multiple of the vector width, at most 16 lanes per row
+  // in one pass, B and C aligned to 16-byte vectors
+  constexpr int CPL = 16 / sizeof(BT);
+  const bool lanes_ok = k % CPL == 0 && k >= 2 * CPL && k <= 16 * CPL &&
+                        (double)p.sell_nch * (k / CPL) * kChunk < 4294967295.0 &&
+                        reinterpret_cast<uintptr_t>(B) % 16 == 0 && ldb % CPL == 0 &&
+                        reinterpret_cast<uintptr_t>(C) % 16 == 0 && ldc % 2 == 0;
+  if (lanes_ok) {
+    switch (k / CPL) {
+      case 2: return sell_spmm_lanes_pass<VT, BT, 2>(p, 0, B, ldb, C, ldc, s);
+      case 4: return sell_spmm_lanes_pass<VT, BT, 4>(p, 0, B, ldb, C, ldc, s);
+      case 8: return sell_spmm_lanes_pass<VT, BT, 8>(p, 0, B, ldb, C, ldc, s);
+      case 16: return sell_spmm_lanes_pass<VT, BT, 16>(p, 0, B, ldb, C, ldc, s);
+      default: break;  // other widths: column blocks below
+    }
+  }
   // columns in blocks of KB = the smallest of 1, 2, 4, 8 covering min(k, 8)
   const int KB = k >= 5 ? 8 : k >= 3 ? 4 : k == 2 ? 2 : 1;
   // vector loads of B row segments need them aligned to the load width:
@@ -841,6 +999,16 @@ int sell_spmm_typed(const Plan& p, int k, const BT* B, int64_t ldb, double* C, i
   return SPMV_OK;
 }
 }  // namespace
+
+bool sell_spmm_lanes_fit(const Plan& p, int k, const void* B, int64_t ldb, const double* C,
+                         int64_t ldc) {
+  const int cpl = p.vdt == SPMV_F64 ? 2 : 4;
+  const int lpr = k % cpl == 0 ? k / cpl : 0;
+  return (lpr == 2 || lpr == 4 || lpr == 8 || lpr == 16) &&
+         (double)p.sell_nch * lpr * kChunk < 4294967295.0 &&
+         reinterpret_cast<uintptr_t>(B) % 16 == 0 && ldb % cpl == 0 &&
+         reinterpret_cast<uintptr_t>(C) % 16 == 0 && ldc % 2 == 0;
+}
 
 int launch_sell_spmm(const Plan& p, int k, const void* B, int64_t ldb, double* C, int64_t ldc,
                      hipStream_t s) {

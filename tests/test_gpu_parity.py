@@ -201,14 +201,15 @@ def test_spmm_vs_oracle(k, dt):
 
 
 @pytest.mark.parametrize("dt", ["f64", "f32"])
-@pytest.mark.parametrize("k", [1, 2, 3, 4, 5, 6, 7, 8, 9, 16, 17])
+@pytest.mark.parametrize("k", [1, 2, 3, 4, 5, 6, 7, 8, 9, 16, 17, 32, 64])
 @pytest.mark.parametrize("name", ["hamiltonian_200k", "laplace2d_256"])
 def test_spmm_from_v6_copy(name, k, dt):
     """A plan running V6 multiplies blocks of right-hand sides from its chunked
-    copy when its rows average at least 8 entries (column blocks of up to 8,
-    vector loads of B row segments, a scalar partial last block), else with
-    the row-group kernel (the 5-point Laplacian); also with padded leading
-    dimensions."""
+    copy when its rows average at least 8 entries (lane groups per row for
+    k = 4, 8, 16, 32 in float64 and 8 .. 64 in float32; else column blocks of
+    up to 8, vector loads of B row segments, a scalar partial last block),
+    else with the row-group kernel (the 5-point Laplacian); also with padded
+    leading dimensions, odd (scalar paths) and aligned (lane groups)."""
     A, _ = case(name)
     Bh = crsgen.uniform_vec(A.n_cols * k, 5).reshape(A.n_cols, k)
     tdt = torch.float32 if dt == "f32" else torch.float64
@@ -228,6 +229,13 @@ def test_spmm_from_v6_copy(name, k, dt):
     Cp = Cp.cpu().numpy()
     assert oracle.bound_ok(Cp[:, :k], Cref, A.row_ptr, S)[0]
     assert np.all(Cp[:, k] == 7.0)
+    Ba = torch.zeros((A.n_cols, k + 4), dtype=tdt, device=DEV)
+    Ba[:, :k] = _gpu(Bh)
+    Ca = torch.full((A.n_rows, k + 2), 7.0, dtype=torch.float64, device=DEV)
+    pkg.spmm_apply(M.handle, k, Ba, k + 4, M.code, Ca, k + 2)
+    Ca = Ca.cpu().numpy()
+    assert oracle.bound_ok(Ca[:, :k], Cref, A.row_ptr, S)[0]
+    assert np.all(Ca[:, k:] == 7.0)
 
 
 @pytest.mark.parametrize("dt", ["f64", "f32"])
@@ -745,7 +753,9 @@ def test_sell_deltas_degenerate_chunks(shape, dt):
 def test_batch_full_size_4096():
     """The batch the benchmark times (4096 matrices, seed 6, N log-uniform in
     [100, 5000]) in its launch mode (one tile-grid launch): every row of every
-    matrix against the oracle, and the graph of the one launch bitwise equal."""
+    matrix against the oracle; the persistent grids (static ranges, and claims
+    from per-XCD queues, repeated so the counters' self-reset is used) and the
+    graphs of the tile grid and of the dynamic kernel bitwise equal."""
     mats = _batch_mats(4096, 6)
     Bt = pkg.Batch(mats, device=DEV)
     Bh = crsgen.uniform_vec(int(Bt.n_cols.sum()), 6)
@@ -761,20 +771,28 @@ def test_batch_full_size_4096():
         ok, worst = oracle.bound_ok(got[Bt.row_off[m]:Bt.row_off[m + 1]], Cref, A.row_ptr, S)
         assert ok, (m, worst)
     first = C_all.clone()
-    s = torch.cuda.Stream()
-    torch.cuda.synchronize()
-    pkg.spmv_graph_begin(s)
-    Bt.apply(Bd, Cd, stream=s)
-    g = pkg.spmv_graph_end(s)
-    try:
+    for mode in (pkg.SPMV_BATCH_STATIC, pkg.SPMV_BATCH_DYNAMIC):
+        Bt.set_mode(mode)
         for _ in range(3):
             C_all.fill_(float("nan"))
-            torch.cuda.synchronize()
-            pkg.spmv_graph_launch(g, s)
-            s.synchronize()
-            assert torch.equal(C_all, first)
-    finally:
-        pkg.spmv_graph_destroy(g)
+            Bt.apply(Bd, Cd)
+            assert torch.equal(C_all, first), mode
+    s = torch.cuda.Stream()
+    for mode in (pkg.SPMV_BATCH_TILE_GRID, pkg.SPMV_BATCH_DYNAMIC):
+        Bt.set_mode(mode)
+        torch.cuda.synchronize()
+        pkg.spmv_graph_begin(s)
+        Bt.apply(Bd, Cd, stream=s)
+        g = pkg.spmv_graph_end(s)
+        try:
+            for _ in range(3):
+                C_all.fill_(float("nan"))
+                torch.cuda.synchronize()
+                pkg.spmv_graph_launch(g, s)
+                s.synchronize()
+                assert torch.equal(C_all, first), mode
+        finally:
+            pkg.spmv_graph_destroy(g)
 
 
 @pytest.mark.parametrize("mode", ["default", "mlp"])
