@@ -15,10 +15,8 @@ triad) go into "extra".
 from __future__ import annotations
 
 import argparse
-import hashlib
 import json
 import os
-import re
 import sys
 import time
 
@@ -55,20 +53,9 @@ KERNEL_SOURCES = {"V6_sell64": ("sell.hip", "device.hpp", "common.hpp"),
 DEFAULT_SOURCES = ("spmv_kernels.hip", "device.hpp", "common.hpp")
 
 
-def _code_only(text: str) -> str:
-    """Source text without comments and with whitespace collapsed: an edit to a
-    comment does not change a kernel."""
-    text = re.sub(r"/\*.*?\*/", " ", text, flags=re.S)
-    text = re.sub(r"//[^\n]*", " ", text)
-    return " ".join(text.split())
-
-
 def kernel_source_hash(variant_name: str) -> str:
-    h = hashlib.sha256()
-    for f in KERNEL_SOURCES.get(variant_name, DEFAULT_SOURCES):
-        src = open(os.path.join(ROOT, "paper_1101_0091_amd", "csrc", f)).read()
-        h.update(_code_only(src).encode())
-    return h.hexdigest()[:16]
+    from paper_1101_0091_amd.selector import source_hash
+    return source_hash(KERNEL_SOURCES.get(variant_name, DEFAULT_SOURCES))
 
 
 def stored_traffic(workload: str, variant_name: str):

@@ -77,9 +77,9 @@ typedef enum {
   SPMV_NUM_VARIANTS = 7
 } spmv_variant;
 
-/* The MLP selector ranks V0..V5; V6 is chosen by autotune, by a timed duel
- * with the selector's pick (SPMV_FLAG_SELL), or by name. */
-#define SPMV_NUM_SELECTOR_OUTPUTS 6
+/* The MLP selector ranks V0..V6; its V6 output is ignored for a plan without
+ * the V6 copy (no SPMV_FLAG_SELL, or the copy did not fit its reserve). */
+#define SPMV_NUM_SELECTOR_OUTPUTS 7
 
 /* spmv_create flags. The low byte selects how the variant is chosen. */
 #define SPMV_SELECT_DEFAULT 0x0u  /* MLP selector if loaded, else V4 */
@@ -127,7 +127,7 @@ typedef enum {
 #define SPMV_FLAG_SELL_WIDE 0x100000u
 
 #define SPMV_NUM_FEATURES 16
-#define SPMV_MLP_PARAMS 5638 /* 16->64->64->6: W1 b1 W2 b2 W3 b3, [out,in] row-major */
+#define SPMV_MLP_PARAMS 5703 /* 16->64->64->7: W1 b1 W2 b2 W3 b3, [out,in] row-major */
 
 /* ---------------------------------------------------------- single matrix */
 
@@ -185,7 +185,7 @@ int spmv_get_variant(spmv_handle h, int* variant);
 int spmv_set_variant(spmv_handle h, int variant);
 /* The 16 row-statistics features computed at create (host out, float64[16]). */
 int spmv_get_features(spmv_handle h, double* features);
-/* The selector's predicted relative log2 times of V0..V5 from create (host
+/* The selector's predicted relative log2 times of V0..V6 from create (host
  * out, float[SPMV_NUM_SELECTOR_OUTPUTS]); SPMV_ERR_STATE if no selector ran. */
 int spmv_get_predictions(spmv_handle h, float* pred);
 /* Per-variant times in microseconds measured by SPMV_SELECT_AUTOTUNE (host
@@ -394,16 +394,18 @@ int spmv_graph_destroy(spmv_graph_handle g);
 int spmv_selector_load(const float* params, const float* feat_mu, const float* feat_sigma,
                        const float* feat_lo, const float* feat_hi, float margin);
 int spmv_selector_loaded(int* loaded);
-/* Load a packed weights file (host path): 8-byte magic "SPMVSEL1", then
+/* Load a packed weights file (host path): 8-byte magic "SPMVSEL2", then
  * little-endian float32 params[SPMV_MLP_PARAMS], mu[16], sigma[16], lo[16],
  * hi[16], margin[1]. SPMV_ERR_INVALID_ARG if the file is missing or malformed. */
 int spmv_selector_load_file(const char* path);
 
 /*
  * Selector network kernels (device arrays, float32), used by the trainer.
- *  forward:  X[nb,16] -> Y[nb,6]; Z1, Z2 [nb,64] keep pre-activations
- *  backward: mean-squared-error loss against T[nb,6] -> grad[SPMV_MLP_PARAMS];
- *            dz scratch: float[nb*(64+64+6)]
+ *  forward:  X[nb,16] -> Y[nb,7]; Z1, Z2 [nb,64] keep pre-activations
+ *  backward: squared-error loss against T[nb,7], summed over the targets
+ *            that are not NaN (a NaN target is a variant without a time, such
+ *            as V6 where the copy did not fit) and divided by nb*7
+ *            -> grad[SPMV_MLP_PARAMS]; dz scratch: float[nb*(64+64+7)]
  *  adam:     one Adam step t>=1 on theta with moments m, v (all [SPMV_MLP_PARAMS])
  */
 int spmv_mlp_forward(const float* theta, const float* X, int32_t nb, float* Y, float* Z1,

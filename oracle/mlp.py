@@ -1,22 +1,23 @@
 """Float64 oracle of the kernel-variant selector network.
 
 TEST INFRASTRUCTURE ONLY (see the package docstring). The paper has no
-learned component; this is the plain definition of a 16 -> 64 -> 64 -> 6
-multilayer perceptron with ReLU activations, mean-squared-error loss and the
-Adam update (Kingma and Ba, 2015, Algorithm 1), written with numpy matrix
-products as the only library step.
+learned component; this is the plain definition of a 16 -> 64 -> 64 -> 7
+multilayer perceptron with ReLU activations, squared-error loss over the
+targets that are present (a NaN target marks a variant without a time and
+adds nothing), and the Adam update (Kingma and Ba, 2015, Algorithm 1),
+written with numpy matrix products as the only library step.
 
-Flat parameter layout (float, 5638 entries), shared with the GPU kernels as a
-*format* only: W1[64,16] b1[64] W2[64,64] b2[64] W3[6,64] b3[6], each weight
+Flat parameter layout (float, 5703 entries), shared with the GPU kernels as a
+*format* only: W1[64,16] b1[64] W2[64,64] b2[64] W3[7,64] b3[7], each weight
 matrix row-major as [out, in].
 """
 from __future__ import annotations
 
 import numpy as np
 
-N_IN, N_H1, N_H2, N_OUT = 16, 64, 64, 6
+N_IN, N_H1, N_H2, N_OUT = 16, 64, 64, 7
 SHAPES = [(N_H1, N_IN), (N_H1,), (N_H2, N_H1), (N_H2,), (N_OUT, N_H2), (N_OUT,)]
-N_PARAMS = sum(int(np.prod(s)) for s in SHAPES)  # 5638
+N_PARAMS = sum(int(np.prod(s)) for s in SHAPES)  # 5703
 
 
 def unpack(theta: np.ndarray):
@@ -33,7 +34,7 @@ def pack(parts) -> np.ndarray:
 
 
 def forward(theta: np.ndarray, X: np.ndarray):
-    """X (batch, 16) -> (Y (batch, 6), cache)."""
+    """X (batch, 16) -> (Y (batch, 7), cache)."""
     W1, b1, W2, b2, W3, b3 = unpack(theta)
     X = np.asarray(X, dtype=np.float64)
     z1 = X @ W1.T + b1
@@ -45,9 +46,11 @@ def forward(theta: np.ndarray, X: np.ndarray):
 
 
 def loss(Y: np.ndarray, T: np.ndarray) -> float:
-    """Mean over batch and outputs of (Y - T)^2."""
-    d = np.asarray(Y, dtype=np.float64) - np.asarray(T, dtype=np.float64)
-    return float(np.mean(d * d))
+    """Sum of (Y - T)^2 over the targets that are not NaN, divided by the
+    number of all entries (batch x outputs)."""
+    T = np.asarray(T, dtype=np.float64)
+    d = np.where(np.isnan(T), 0.0, np.asarray(Y, dtype=np.float64) - T)
+    return float(np.sum(d * d) / d.size)
 
 
 def backward(theta: np.ndarray, cache, Y: np.ndarray, T: np.ndarray) -> np.ndarray:
@@ -55,7 +58,8 @@ def backward(theta: np.ndarray, cache, Y: np.ndarray, T: np.ndarray) -> np.ndarr
     W1, b1, W2, b2, W3, b3 = unpack(theta)
     X, z1, h1, z2, h2 = cache
     nb = Y.shape[0]
-    dY = 2.0 * (np.asarray(Y, np.float64) - np.asarray(T, np.float64)) / (nb * N_OUT)
+    T = np.asarray(T, np.float64)
+    dY = np.where(np.isnan(T), 0.0, 2.0 * (np.asarray(Y, np.float64) - T) / (nb * N_OUT))
     dW3 = dY.T @ h2
     db3 = dY.sum(axis=0)
     dz2 = (dY @ W3) * (z2 > 0.0)

@@ -26,7 +26,7 @@ VARIANTS = ("V0_thread_row", "V1_lanes4", "V2_lanes16", "V3_wave_row", "V4_lds_b
             "V5_binned", "V6_sell64")
 SPMV_NUM_VARIANTS = 7
 SPMV_V6_SELL64 = 6
-SPMV_NUM_SELECTOR_OUTPUTS = 6
+SPMV_NUM_SELECTOR_OUTPUTS = 7
 SPMV_SELECT_DEFAULT, SPMV_SELECT_MLP, SPMV_SELECT_AUTOTUNE, SPMV_SELECT_FIXED = 0, 1, 2, 3
 SPMV_FLAG_SKIP_VALIDATE = 0x10000
 SPMV_FLAG_SELL = 0x20000
@@ -38,7 +38,7 @@ SPMV_V4_PLAIN, SPMV_V4_STAGED, SPMV_V4_WINDOWS = 0, 1, 2
 V4_FORMS = ("plain", "staged", "windows")
 SPMV_BATCH_DYNAMIC, SPMV_BATCH_STATIC, SPMV_BATCH_TILE_GRID = 0, 1, 2
 SPMV_NUM_FEATURES = 16
-SPMV_MLP_PARAMS = 5638
+SPMV_MLP_PARAMS = 5703
 
 EXPORTS = (
     "spmv_workspace_size", "spmv_create", "spmv_apply", "spmm_apply", "spmv_get_variant",

@@ -55,9 +55,8 @@ PlanLayout plan_layout(int64_t n_rows, int64_t n_cols, int64_t nnz, uint32_t fla
   L.bin_base = o;
   o += align256(4 * (size_t)kStatsGrid * kNumBins);
   const uint32_t mode = flags & 0xFFu;
-  // timing scratch: autotune, the MLP fallback, and the V6 duel of selector plans
-  if (mode == SPMV_SELECT_MLP || mode == SPMV_SELECT_AUTOTUNE ||
-      (mode == SPMV_SELECT_DEFAULT && (flags & SPMV_FLAG_SELL))) {
+  // timing scratch: autotune and the MLP selector's fallback to it
+  if (mode == SPMV_SELECT_MLP || mode == SPMV_SELECT_AUTOTUNE) {
     L.at_B = o;
     o += align256(8 * (size_t)std::max<int64_t>(n_cols, 1));
     L.at_C = o;
@@ -152,43 +151,13 @@ int autotune(Plan& p, hipStream_t s) {
   return SPMV_OK;
 }
 
-// Median of three timed launches of variant v (after one warm-up), in ms.
-int time_variant(Plan& p, int v, hipStream_t s, float* med) {
-  int st = launch_spmv(p, v, p.at_B, p.at_C, s);
-  if (st) return st;
-  hipEvent_t e0, e1;
-  SPMV_HIP(hipEventCreate(&e0));
-  SPMV_HIP(hipEventCreate(&e1));
-  float ms[3] = {0.0f, 0.0f, 0.0f};
-  for (int r = 0; r < 3 && !st; ++r) {
-    hipEventRecord(e0, s);
-    st = launch_spmv(p, v, p.at_B, p.at_C, s);
-    hipEventRecord(e1, s);
-    if (!st && hipEventSynchronize(e1) != hipSuccess) st = fail(SPMV_ERR_HIP, "event sync");
-    if (!st) hipEventElapsedTime(&ms[r], e0, e1);
-  }
-  hipEventDestroy(e0);
-  hipEventDestroy(e1);
-  std::sort(ms, ms + 3);
-  *med = ms[1];
-  return st;
-}
-
-// The selector ranks V0..V5 only; when the plan also has the V6 copy, its
-// pick is timed against V6 and the faster one is kept.
-int duel_with_v6(Plan& p, hipStream_t s) {
-  if (!p.sell_ok || !p.at_B || p.variant == SPMV_V6_SELL64) return SPMV_OK;
-  int st = launch_fill(p.at_B, p.vdt, p.n_cols, 1.0, s);
-  float t_pick = 0.0f, t_v6 = 0.0f;
-  if (!st) st = time_variant(p, p.variant, s, &t_pick);
-  if (!st) st = time_variant(p, SPMV_V6_SELL64, s, &t_v6);
-  if (!st && t_v6 < t_pick) p.variant = SPMV_V6_SELL64;
-  return st;
-}
+// The selector's V6 output counts only for a plan with the V6 copy.
+bool selector_output_usable(const Plan& p, int v) { return v != SPMV_V6_SELL64 || p.sell_ok; }
 
 bool selector_confident(const Plan& p) {
-  float best = p.pred[0], second = INFINITY;
-  for (int v = 1; v < SPMV_NUM_SELECTOR_OUTPUTS; ++v) {
+  float best = INFINITY, second = INFINITY;
+  for (int v = 0; v < SPMV_NUM_SELECTOR_OUTPUTS; ++v) {
+    if (!selector_output_usable(p, v)) continue;
     if (p.pred[v] < best) {
       second = best;
       best = p.pred[v];
@@ -202,10 +171,12 @@ bool selector_confident(const Plan& p) {
   return true;
 }
 
-int argmin6(const float* x) {
-  int b = 0;
-  for (int v = 1; v < SPMV_NUM_SELECTOR_OUTPUTS; ++v)
-    if (x[v] < x[b]) b = v;
+// The selector's pick: the smallest predicted time among the usable outputs
+// (the first such output on ties).
+int selector_pick(const Plan& p) {
+  int b = -1;
+  for (int v = 0; v < SPMV_NUM_SELECTOR_OUTPUTS; ++v)
+    if (selector_output_usable(p, v) && (b < 0 || p.pred[v] < p.pred[b])) b = v;
   return b;
 }
 
@@ -403,15 +374,12 @@ int plan_build(Plan& p, int64_t n_rows, int64_t n_cols, int64_t nnz, const int32
   } else if (mode == SPMV_SELECT_AUTOTUNE) {
     st = autotune(p, s);
   } else if (mode == SPMV_SELECT_MLP) {
-    if (p.have_pred && selector_confident(p)) {
-      p.variant = argmin6(p.pred);
-      st = duel_with_v6(p, s);
-    } else {
+    if (p.have_pred && selector_confident(p))
+      p.variant = selector_pick(p);
+    else
       st = autotune(p, s);
-    }
   } else {  // default
-    p.variant = p.have_pred ? argmin6(p.pred) : SPMV_V4_LDS_BLOCK;
-    st = duel_with_v6(p, s);
+    p.variant = p.have_pred ? selector_pick(p) : SPMV_V4_LDS_BLOCK;
   }
   return st;
 }
@@ -1114,7 +1082,7 @@ int spmv_selector_load_file(const char* path) {
   const size_t m = std::fread(magic, 1, 8, f);
   const size_t n = std::fread(buf.data(), sizeof(float), kFloats + 1, f);
   std::fclose(f);
-  if (m != 8 || std::memcmp(magic, "SPMVSEL1", 8) != 0 || n != kFloats)
+  if (m != 8 || std::memcmp(magic, "SPMVSEL2", 8) != 0 || n != kFloats)
     return fail(SPMV_ERR_INVALID_ARG, std::string("malformed selector file ") + path);
   const float* p = buf.data();
   const float* mu = p + SPMV_MLP_PARAMS;

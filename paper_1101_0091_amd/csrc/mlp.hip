@@ -1,11 +1,11 @@
-// Kernel-variant selector network: 16 -> 64 -> 64 -> 6, ReLU, float32.
+// Kernel-variant selector network: 16 -> 64 -> 64 -> 7, ReLU, float32.
 //
 // Forward, backward (mean-squared error) and Adam update kernels. Training
 // runs on the GPU through these kernels; the trained weights live in a
 // per-device global array that plan creation reads. All reductions have a
 // fixed order (no atomics), so training is reproducible.
 //
-// Flat parameter layout: W1[64,16] b1[64] W2[64,64] b2[64] W3[6,64] b3[6].
+// Flat parameter layout: W1[64,16] b1[64] W2[64,64] b2[64] W3[7,64] b3[7].
 #include <cmath>
 
 #include "common.hpp"
@@ -13,7 +13,7 @@
 namespace spmv {
 namespace {
 
-constexpr int NI = 16, H1 = 64, H2 = 64, NO = 6;
+constexpr int NI = 16, H1 = 64, H2 = 64, NO = 7;
 constexpr int oW1 = 0, oB1 = oW1 + H1 * NI, oW2 = oB1 + H1, oB2 = oW2 + H2 * H1,
               oW3 = oB2 + H2, oB3 = oW3 + NO * H2, NPAR = oB3 + NO;
 static_assert(NPAR == SPMV_MLP_PARAMS, "parameter layout");
@@ -46,7 +46,8 @@ __global__ __launch_bounds__(64) void k_mlp_fwd(const float* __restrict__ th,
   }
 }
 
-// Per-sample deltas: dY = 2 (Y - T) / (nb * 6), dZ2, dZ1 (ReLU'(0) = 0).
+// Per-sample deltas: dY = 2 (Y - T) / (nb * 7), 0 where the target is NaN (no
+// time for that variant); dZ2, dZ1 (ReLU'(0) = 0).
 __global__ __launch_bounds__(64) void k_mlp_bwd_sample(
     const float* __restrict__ th, const float* __restrict__ Z1, const float* __restrict__ Z2,
     const float* __restrict__ Y, const float* __restrict__ T, int nb, float* __restrict__ dY,
@@ -55,7 +56,8 @@ __global__ __launch_bounds__(64) void k_mlp_bwd_sample(
   const int b = blockIdx.x, j = threadIdx.x;
   if (b >= nb) return;
   if (j < NO) {
-    const float d = 2.0f * (Y[(int64_t)b * NO + j] - T[(int64_t)b * NO + j]) / (float)(nb * NO);
+    const float t = T[(int64_t)b * NO + j];
+    const float d = t == t ? 2.0f * (Y[(int64_t)b * NO + j] - t) / (float)(nb * NO) : 0.0f;
     dy[j] = d;
     dY[(int64_t)b * NO + j] = d;
   }

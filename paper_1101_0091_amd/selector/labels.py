@@ -1,13 +1,15 @@
-"""Label run for the kernel-variant selector: time every variant on the
+"""Label run for the kernel-variant selector: time every variant V0-V6 on the
 seeded matrix collection (N log-uniform in [1e4, 2e7]; uniform, power-law
-or banded rows) and append one JSON line per matrix. Resumable: matrices
-already in the output file are skipped.
+or banded rows) and append one JSON line per matrix. V4 runs in the form the
+plan chooses by default; V6 only where the chunked copy fits its reserve
+(else its time is null). Every variant is timed in two separate passes (the
+median of 7 launches each), so the label noise can be measured.
+
+The sidecar FILE.meta.json holds the hash of the kernel sources the labels
+were taken with; a run refuses to append to labels of other sources.
+Resumable: matrices already in the output file are skipped.
 
     python -m paper_1101_0091_amd.selector.labels --out FILE [--start 0 --stop 512]
-    python -m paper_1101_0091_amd.selector.labels --out FILE --retime-v6
-
---retime-v6 re-times only V6 for the records of FILE that have a chunked
-copy and rewrites FILE (the V0-V5 times are kept).
 """
 from __future__ import annotations
 
@@ -17,18 +19,18 @@ import os
 import sys
 import time
 
+from . import LABEL_SOURCES, labels_meta_path, source_hash
+
 SEED = 5
 NLO, NHI = 1e4, 2e7
 
 
-def time_variants(M, Bd, C, reps=7, warmup=2, variants=None):
+def time_variants(M, Bd, C, variants, reps=7, warmup=2):
     import numpy as np
     import torch
-
-    import paper_1101_0091_amd as pkg
     s = torch.cuda.current_stream()
     out = []
-    for v in (range(pkg.SPMV_NUM_SELECTOR_OUTPUTS) if variants is None else variants):
+    for v in variants:
         M.variant = v
         for _ in range(warmup):
             M.apply(Bd, C)
@@ -43,15 +45,29 @@ def time_variants(M, Bd, C, reps=7, warmup=2, variants=None):
     return out
 
 
+def check_meta(path: str) -> None:
+    """Write the sidecar for a new label file, or check an existing one."""
+    meta = {"kernel_source_hash": source_hash(), "files": list(LABEL_SOURCES),
+            "variants": "V0-V6", "seed": SEED, "n_range": [NLO, NHI]}
+    mp = labels_meta_path(path)
+    if os.path.exists(path) and os.path.getsize(path) > 0:
+        old = json.load(open(mp)) if os.path.exists(mp) else {}
+        if old.get("kernel_source_hash") != meta["kernel_source_hash"]:
+            raise SystemExit(f"{path} was labelled with other kernel sources "
+                             f"({old.get('kernel_source_hash')} != {meta['kernel_source_hash']}); "
+                             "start a new file")
+    else:
+        with open(mp, "w") as f:
+            json.dump(meta, f, indent=1)
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser()
     ap.add_argument("--out", required=True)
     ap.add_argument("--start", type=int, default=0)
     ap.add_argument("--stop", type=int, default=512)
-    ap.add_argument("--retime-v6", action="store_true")
     args = ap.parse_args(argv)
-    if args.retime_v6:
-        return retime_v6(args.out)
+    check_meta(args.out)
     import torch
 
     import crsgen
@@ -75,50 +91,26 @@ def main(argv=None):
                                    device=dev)
         Bd = torch.from_numpy(B).to(dev)
         C = torch.empty(A.n_rows, dtype=torch.float64, device=dev)
-        us = time_variants(M, Bd, C)
-        # V6 (chunked copy) is outside the selector's outputs; its time is kept
-        # for reference where the copy fits its reserve
-        us6 = (time_variants(M, Bd, C, variants=(pkg.SPMV_V6_SELL64,))[0]
-               if M.sell_slots is not None else None)
+        has6 = M.sell_slots is not None
+        vs = list(range(7 if has6 else 6))
+        us = time_variants(M, Bd, C, vs)
+        us_rep = time_variants(M, Bd, C, vs)
+        if not has6:
+            us.append(None)
+            us_rep.append(None)
         rec = {"id": i, "n": A.n_rows, "nnz": A.nnz, "family": crsgen.FAMILY_NAMES[prm["family"]],
                "width": prm["width"], "features": [float(x) for x in M.features],
-               "us": [round(t, 3) for t in us], "gen_s": round(tg, 2),
-               "us_v6": None if us6 is None else round(us6, 3),
-               "sell_slots": M.sell_slots}
+               "us": [None if t is None else round(t, 3) for t in us],
+               "us_rep": [None if t is None else round(t, 3) for t in us_rep],
+               "v4_form": pkg.V4_FORMS[M.v4_form], "sell_slots": M.sell_slots,
+               "gen_s": round(tg, 2)}
         with open(args.out, "a") as f:
             f.write(json.dumps(rec) + "\n")
-        print(f"[labels] {i} n={A.n_rows} nnz={A.nnz} {rec['family']} best=V{us.index(min(us))} "
+        best = min(range(len(vs)), key=lambda v: us[v])
+        print(f"[labels] {i} n={A.n_rows} nnz={A.nnz} {rec['family']} best=V{best} "
               f"us={rec['us']} ({time.time() - t0:.1f}s)", flush=True)
         del M, Bd, C, A
         torch.cuda.empty_cache()
-
-
-def retime_v6(path):
-    import torch
-
-    import crsgen
-    import paper_1101_0091_amd as pkg
-    recs = [json.loads(line) for line in open(path)]
-    dev = torch.device("cuda:0")
-    for r in recs:
-        if r.get("sell_slots") is None:
-            continue
-        t0 = time.time()
-        A, _ = crsgen.family_matrix(SEED, r["id"], NLO, NHI)
-        B = crsgen.uniform_vec(A.n_cols, SEED)
-        M = pkg.CRSMatrix.from_crs(A, flags=pkg.SPMV_FLAG_VARIANT(6) | pkg.SPMV_FLAG_SELL,
-                                   device=dev)
-        Bd = torch.from_numpy(B).to(dev)
-        C = torch.empty(A.n_rows, dtype=torch.float64, device=dev)
-        r["us_v6"] = round(time_variants(M, Bd, C, variants=(pkg.SPMV_V6_SELL64,))[0], 3)
-        print(f"[labels] {r['id']} V6 {r['us_v6']} us, best of V0-V5 {min(r['us'])} us "
-              f"({time.time() - t0:.1f}s)", flush=True)
-        del M, Bd, C, A
-        torch.cuda.empty_cache()
-    with open(path, "w") as f:
-        for r in recs:
-            f.write(json.dumps(r) + "\n")
-    return 0
 
 
 if __name__ == "__main__":

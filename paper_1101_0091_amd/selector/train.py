@@ -3,9 +3,11 @@ kernels (spmv_mlp_forward / spmv_mlp_backward / spmv_mlp_adam), then write
 the packed weights file and a held-out evaluation report.
 
 Target per matrix and variant: relative log2 time, log2 t_v minus the mean
-over the six variants (the network ranks variants; argmin of the output is
-the choice). Inputs: the 16 row-statistics features, standardised with the
-training-set mean and standard deviation.
+over the variants timed on that matrix (the network ranks variants; the
+argmin of the usable outputs is the choice). V6 has no time where the chunked
+copy did not fit; its target is then NaN, which the loss skips. Inputs: the
+16 row-statistics features, standardised with the training-set mean and
+standard deviation.
 
     python -m paper_1101_0091_amd.selector.train --labels FILE --out-dir DIR
 """
@@ -19,10 +21,9 @@ import sys
 
 import numpy as np
 
-from . import evaluate, pack_weights, split_ids
+from . import N_OUT, N_PARAMS, evaluate, geomean, labels_meta, pack_weights, split_ids
 
-N_PARAMS = 5638
-SHAPES = [(64, 16), (64,), (64, 64), (64,), (6, 64), (6,)]
+SHAPES = [(64, 16), (64,), (64, 64), (64,), (N_OUT, 64), (N_OUT,)]
 
 
 def he_init(seed: int) -> np.ndarray:
@@ -34,21 +35,40 @@ def he_init(seed: int) -> np.ndarray:
             parts.append(rng.uniform(-lim, lim, size=s))
         else:
             parts.append(np.zeros(s))
-    return np.concatenate([p.ravel() for p in parts]).astype(np.float32)
+    theta = np.concatenate([p.ravel() for p in parts]).astype(np.float32)
+    assert theta.size == N_PARAMS
+    return theta
 
 
-def load_labels(path):
+def load_labels(path, key="us"):
+    """Records sorted by id, features F, times T[:, 7] (NaN: not timed), ids."""
     recs = [json.loads(line) for line in open(path) if line.strip()]
     recs.sort(key=lambda r: r["id"])
     F = np.array([r["features"] for r in recs], dtype=np.float64)
-    T = np.array([r["us"] for r in recs], dtype=np.float64)
+    T = np.array([[np.nan if t is None else t for t in r[key]] for r in recs], dtype=np.float64)
     ids = np.array([r["id"] for r in recs])
     return recs, F, T, ids
 
 
 def targets(T):
     lt = np.log2(T)
-    return lt - lt.mean(axis=1, keepdims=True)
+    return lt - np.nanmean(lt, axis=1, keepdims=True)
+
+
+def label_noise(path):
+    """Run-to-run spread of the labels: geomean over matrices and variants of
+    max(t1, t2) / min(t1, t2) for the two timing passes, and the same for the
+    best variant of the first pass alone."""
+    _, _, T1, _ = load_labels(path, "us")
+    _, _, T2, _ = load_labels(path, "us_rep")
+    ok = ~np.isnan(T1) & ~np.isnan(T2)
+    r = np.maximum(T1[ok], T2[ok]) / np.minimum(T1[ok], T2[ok])
+    b = np.nanargmin(T1, axis=1)
+    rb = np.array([max(T1[i, v], T2[i, v]) / min(T1[i, v], T2[i, v]) for i, v in enumerate(b)])
+    # the fraction of matrices whose best variant differs between the passes
+    flip = float(np.mean(np.nanargmin(T1, axis=1) != np.nanargmin(T2, axis=1)))
+    return {"label_noise_geomean": geomean(r), "label_noise_best_geomean": geomean(rb),
+            "label_best_variant_flip_rate": flip}
 
 
 def main(argv=None):
@@ -79,15 +99,16 @@ def main(argv=None):
     m = torch.zeros_like(th)
     v = torch.zeros_like(th)
     g = torch.empty_like(th)
-    P = torch.empty((nb, 6), dtype=torch.float32, device=dev)
+    P = torch.empty((nb, N_OUT), dtype=torch.float32, device=dev)
     Z1 = torch.empty((nb, 64), dtype=torch.float32, device=dev)
     Z2 = torch.empty((nb, 64), dtype=torch.float32, device=dev)
-    scratch = torch.empty(nb * (6 + 64 + 64), dtype=torch.float32, device=dev)
+    scratch = torch.empty(nb * (N_OUT + 64 + 64), dtype=torch.float32, device=dev)
+    have = ~torch.isnan(Ytr)
     hist = []
     for t in range(1, args.steps + 1):
         pkg.spmv_mlp_forward(th, Xtr, nb, P, Z1, Z2)
         if t == 1 or t % 500 == 0 or t == args.steps:
-            loss = float(((P - Ytr) ** 2).mean())
+            loss = float(torch.where(have, (P - Ytr) ** 2, 0.0).sum()) / P.numel()
             hist.append((t, loss))
             print(f"[train] step {t} loss {loss:.5f}", flush=True)
         pkg.spmv_mlp_backward(th, Xtr, Z1, Z2, P, Ytr, nb, scratch, g)
@@ -104,11 +125,13 @@ def main(argv=None):
                  (lo - pad).astype(np.float32), (hi + pad).astype(np.float32), args.margin)
     # held-out predictions with the GPU forward kernel
     Xte = torch.from_numpy(X[te]).to(dev)
-    Pte = torch.empty((len(te), 6), dtype=torch.float32, device=dev)
+    Pte = torch.empty((len(te), N_OUT), dtype=torch.float32, device=dev)
     Z1e = torch.empty((len(te), 64), dtype=torch.float32, device=dev)
     Z2e = torch.empty((len(te), 64), dtype=torch.float32, device=dev)
     pkg.spmv_mlp_forward(th, Xte, len(te), Pte, Z1e, Z2e)
     rep = evaluate(F, T, tr, te, Pte.cpu().numpy())
+    rep.update(label_noise(args.labels))
+    rep["kernel_source_hash"] = labels_meta(args.labels)["kernel_source_hash"]
     rep["loss_history"] = hist
     rep["steps"] = args.steps
     rep["lr"] = args.lr

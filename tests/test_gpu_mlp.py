@@ -30,7 +30,8 @@ def _inputs(nb, seed):
         rng = np.random.default_rng(s)
         th = (rng.integers(-4, 5, size=mlp.N_PARAMS) / 16.0).astype(np.float32)
         X = (rng.integers(-8, 9, size=(nb, 16)) / 2.0).astype(np.float32)
-        T = (rng.integers(-64, 65, size=(nb, 6)) / 16.0).astype(np.float32)
+        T = (rng.integers(-64, 65, size=(nb, 7)) / 16.0).astype(np.float32)
+        T[::2, 6] = np.nan  # V6 without a time on every other sample
         Yabs, (_, m1, _, m2, _) = mlp.forward(np.abs(th.astype(np.float64)),
                                               np.abs(X.astype(np.float64)))
         if m1.max() < 2.0**19 and m2.max() < 2.0**15 and Yabs.max() < 2.0**10:
@@ -53,7 +54,7 @@ def _run_forward(th, X):
     nb = X.shape[0]
     thd = torch.from_numpy(th).to(DEV)
     Xd = torch.from_numpy(X).to(DEV)
-    Y = torch.empty((nb, 6), dtype=torch.float32, device=DEV)
+    Y = torch.empty((nb, 7), dtype=torch.float32, device=DEV)
     Z1 = torch.empty((nb, 64), dtype=torch.float32, device=DEV)
     Z2 = torch.empty((nb, 64), dtype=torch.float32, device=DEV)
     pkg.spmv_mlp_forward(thd, Xd, nb, Y, Z1, Z2)
@@ -70,11 +71,11 @@ def test_forward_and_backward_vs_oracle(nb):
     assert np.array_equal(Z1.cpu().numpy(), cache[1])
     assert np.array_equal(Z2.cpu().numpy(), cache[3])
     Td = torch.from_numpy(T).to(DEV)
-    scratch = torch.empty(nb * (6 + 64 + 64), dtype=torch.float32, device=DEV)
+    scratch = torch.empty(nb * (7 + 64 + 64), dtype=torch.float32, device=DEV)
     grad = torch.empty(mlp.N_PARAMS, dtype=torch.float32, device=DEV)
     pkg.spmv_mlp_backward(thd, Xd, Z1, Z2, Y, Td, nb, scratch, grad)
     gref = mlp.backward(th64, cache, Yref, T64)
-    dYabs = 2.0 * np.abs(Yref - T64) / (nb * 6)
+    dYabs = np.where(np.isnan(T64), 0.0, 2.0 * np.abs(Yref - T64) / (nb * 7))
     gabs = _abs_backward(th64, cache, dYabs)
     err = np.abs(grad.cpu().numpy() - gref)
     assert np.all(err <= 1e-4 * gabs + 1e-30), float(np.max(err / (gabs + 1e-30)))
@@ -104,15 +105,15 @@ def test_training_reduces_loss():
     nb = 256
     rng = np.random.default_rng(9)
     X = rng.standard_normal((nb, 16)).astype(np.float32)
-    Wt = rng.standard_normal((16, 6)) / 4
+    Wt = rng.standard_normal((16, 7)) / 4
     T = np.tanh(X.astype(np.float64) @ Wt).astype(np.float32)
     th = _theta32(5) * 0.5
     thd = torch.from_numpy(th).to(DEV)
     Xd, Td = torch.from_numpy(X).to(DEV), torch.from_numpy(T).to(DEV)
-    Y = torch.empty((nb, 6), dtype=torch.float32, device=DEV)
+    Y = torch.empty((nb, 7), dtype=torch.float32, device=DEV)
     Z1 = torch.empty((nb, 64), dtype=torch.float32, device=DEV)
     Z2 = torch.empty((nb, 64), dtype=torch.float32, device=DEV)
-    sc = torch.empty(nb * 134, dtype=torch.float32, device=DEV)
+    sc = torch.empty(nb * 135, dtype=torch.float32, device=DEV)
     g = torch.empty(mlp.N_PARAMS, dtype=torch.float32, device=DEV)
     m = torch.zeros_like(g)
     v = torch.zeros_like(g)
@@ -142,7 +143,12 @@ def test_selector_in_create_matches_oracle_forward():
     yref, _ = mlp.forward(th.astype(np.float64), x[None, :])
     yabs, _ = mlp.forward(np.abs(th.astype(np.float64)), np.abs(x[None, :]))
     assert np.all(np.abs(pred - yref[0]) <= 1e-4 * yabs[0] + 1e-6)
-    assert M.variant == int(np.argmin(pred))
+    # no V6 copy: the V6 output is not a candidate
+    assert M.variant == int(np.argmin(pred[:6]))
+    # with the copy every output is
+    Ms = pkg.CRSMatrix.from_crs(A, flags=pkg.SPMV_FLAG_SELL, device=DEV)
+    assert Ms.sell_slots is not None
+    assert Ms.variant == int(np.argmin(pkg.spmv_get_predictions(Ms.handle)))
     # MLP mode with an unreachable margin falls back to autotune
     pkg.spmv_selector_load(th, mu, sigma, lo, hi, 1e9)
     M2 = pkg.CRSMatrix.from_crs(A, flags=pkg.SPMV_SELECT_MLP, device=DEV)
@@ -163,10 +169,10 @@ def test_packaged_selector_choice_matches_oracle():
     agree = 0
     for idx in range(12):
         A, _ = crsgen.family_matrix(9, idx, 2e3, 3e5)
-        M = pkg.CRSMatrix.from_crs(A, device=DEV)
+        M = pkg.CRSMatrix.from_crs(A, device=DEV)  # no V6 copy: outputs V0-V5
         f = oracle.row_features(A.n_rows, A.row_ptr, A.col_idx)
         x = ((f.astype(np.float32) - mu) / sigma).astype(np.float64)
-        y = mlp.forward(theta.astype(np.float64), x[None, :])[0][0]
+        y = mlp.forward(theta.astype(np.float64), x[None, :])[0][0][:6]
         srt = np.sort(y)
         if srt[1] - srt[0] > 1e-3:
             assert M.variant == int(np.argmin(y)), (idx, M.variant, y)

@@ -796,19 +796,24 @@ def test_batch_full_size_4096():
 
 
 @pytest.mark.parametrize("mode", ["default", "mlp"])
-def test_selector_plan_duels_with_v6(mode):
-    """With the V6 copy, a selector plan keeps either the network's pick or V6
-    (whichever its timed duel found faster) and multiplies correctly; without
-    the copy it keeps the network's pick."""
+def test_selector_plan_masks_v6(mode):
+    """A selector plan picks the smallest predicted time over V0-V6 when it
+    holds the V6 copy and over V0-V5 when it does not (the same network
+    outputs), and multiplies correctly."""
     A, B = case("hamiltonian_200k")
     flags = pkg.SPMV_SELECT_DEFAULT if mode == "default" else pkg.SPMV_SELECT_MLP
     M0 = pkg.CRSMatrix.from_crs(A, flags=flags, device=DEV)
     M = pkg.CRSMatrix.from_crs(A, flags=flags | SELL, device=DEV)
     assert M.sell_slots is not None
-    if M0.variant != 6 and pkg.spmv_selector_loaded():
-        assert M.variant in (M0.variant, pkg.SPMV_V6_SELL64)
+    if pkg.spmv_selector_loaded():
+        p0, p = pkg.spmv_get_predictions(M0.handle), pkg.spmv_get_predictions(M.handle)
+        assert np.array_equal(p0, p)
+        if mode == "default":
+            assert M0.variant == int(np.argmin(p[:6]))
+            assert M.variant == int(np.argmin(p))
     Cref, S = oracle.spmv(A.n_rows, A.row_ptr, A.col_idx, A.val, B)
     assert oracle.bound_ok(M.apply(_gpu(B)).cpu().numpy(), Cref, A.row_ptr, S)[0]
+    assert oracle.bound_ok(M0.apply(_gpu(B)).cpu().numpy(), Cref, A.row_ptr, S)[0]
 
 
 @pytest.mark.parametrize("dt", ["f64", "f32"])

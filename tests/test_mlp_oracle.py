@@ -15,29 +15,51 @@ def _theta(seed):
 
 
 def test_param_count():
-    assert mlp.N_PARAMS == 5638
+    # 64*16 + 64 + 64*64 + 64 + 7*64 + 7
+    assert mlp.N_PARAMS == 5703
 
 
 def test_zero_weights_closed_form():
     th = np.zeros(mlp.N_PARAMS)
-    th[-6:] = np.arange(6)  # b3
+    th[-7:] = np.arange(7)  # b3
     X = np.random.default_rng(0).standard_normal((5, 16))
-    T = np.ones((5, 6))
+    T = np.ones((5, 7))
     Y, cache = mlp.forward(th, X)
-    assert np.array_equal(Y, np.tile(np.arange(6.0), (5, 1)))
+    assert np.array_equal(Y, np.tile(np.arange(7.0), (5, 1)))
     g = mlp.backward(th, cache, Y, T)
-    # dL/db3 = 2 (b3 - 1) / 6 (mean over batch of identical rows)
-    assert np.allclose(g[-6:], 2 * (np.arange(6) - 1) / 6)
-    assert np.all(g[:-6] == 0)
+    # dL/db3 = 2 (b3 - 1) / 7 (mean over batch of identical rows)
+    assert np.allclose(g[-7:], 2 * (np.arange(7) - 1) / 7)
+    assert np.all(g[:-7] == 0)
+    assert mlp.loss(Y, T) == np.mean((np.arange(7.0) - 1) ** 2)
+
+
+def test_missing_targets_closed_form():
+    """A NaN target (a variant without a time) adds nothing to the loss or
+    the gradient; the denominator stays batch x outputs."""
+    th = np.zeros(mlp.N_PARAMS)
+    th[-7:] = np.arange(7)
+    X = np.random.default_rng(1).standard_normal((4, 16))
+    T = np.ones((4, 7))
+    T[:, 6] = np.nan
+    T[1, 2] = np.nan
+    Y, cache = mlp.forward(th, X)
+    g = mlp.backward(th, cache, Y, T)
+    # b3[v] gets 2 (v - 1) / (4 * 7) from each row whose target v is present
+    rows = np.array([4, 4, 3, 4, 4, 4, 0])
+    assert np.allclose(g[-7:], rows * 2 * (np.arange(7) - 1) / 28)
+    sq = (np.arange(7.0) - 1) ** 2
+    assert np.isclose(mlp.loss(Y, T), (sq @ rows) / 28)
 
 
 def test_gradient_finite_differences():
     th = _theta(1)
     rng = np.random.default_rng(2)
     X = rng.standard_normal((7, 16))
-    T = rng.standard_normal((7, 6))
+    T = rng.standard_normal((7, 7))
+    T[rng.random((7, 7)) < 0.2] = np.nan  # missing targets
     L, g = mlp.loss_and_grad(th, X, T)
-    idx = list(rng.choice(mlp.N_PARAMS, size=300, replace=False)) + list(range(5632, 5638))
+    n = mlp.N_PARAMS
+    idx = list(rng.choice(n, size=300, replace=False)) + list(range(n - 7, n))
     fd = mlp.grad_fd(th, X, T, h=1e-6, idx=idx)
     for i in idx:
         assert abs(fd[i] - g[i]) <= 1e-6 * max(1.0, abs(g[i])) * 10 + 1e-9, (i, fd[i], g[i])
@@ -50,7 +72,7 @@ def test_relu_derivative_zero_at_zero():
     th[W1n:W1n + 64] = 0.0
     X = np.zeros((1, 16))
     Y, cache = mlp.forward(th, X)
-    g = mlp.backward(th, cache, Y, np.zeros((1, 6)))
+    g = mlp.backward(th, cache, Y, np.zeros((1, 7)))
     assert np.all(g[W1n:W1n + 64] == 0)
 
 
