@@ -26,8 +26,8 @@ def test_kernel_source_hash_is_per_variant():
 
 
 def test_kernel_source_hash_ignores_comments():
-    import bench
+    from paper_1101_0091_amd.selector import code_only
     a = "int f(int x) {  // one\n  return x + 1; /* two */ }\n"
     b = "int f(int x) {\n  return x + 1;\n}  // changed comment\n"
-    assert bench._code_only(a) == bench._code_only(b)
-    assert bench._code_only(a) != bench._code_only(a.replace("x + 1", "x + 2"))
+    assert code_only(a) == code_only(b)
+    assert code_only(a) != code_only(a.replace("x + 1", "x + 2"))
