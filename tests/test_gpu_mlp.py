@@ -145,10 +145,13 @@ def test_selector_in_create_matches_oracle_forward():
     assert np.all(np.abs(pred - yref[0]) <= 1e-4 * yabs[0] + 1e-6)
     # no V6 copy: the V6 output is not a candidate
     assert M.variant == int(np.argmin(pred[:6]))
-    # with the copy every output is
-    Ms = pkg.CRSMatrix.from_crs(A, flags=pkg.SPMV_FLAG_SELL, device=DEV)
-    assert Ms.sell_slots is not None
-    assert Ms.variant == int(np.argmin(pkg.spmv_get_predictions(Ms.handle)))
+    # with the copy (a matrix whose chunks fit the reserve) every output is
+    L = crsgen.laplace2d(96)
+    for fl in (0, pkg.SPMV_FLAG_SELL):
+        ML = pkg.CRSMatrix.from_crs(L, flags=fl, device=DEV)
+        pl = pkg.spmv_get_predictions(ML.handle)
+        assert (ML.sell_slots is not None) == bool(fl)
+        assert ML.variant == int(np.argmin(pl if fl else pl[:6]))
     # MLP mode with an unreachable margin falls back to autotune
     pkg.spmv_selector_load(th, mu, sigma, lo, hi, 1e9)
     M2 = pkg.CRSMatrix.from_crs(A, flags=pkg.SPMV_SELECT_MLP, device=DEV)

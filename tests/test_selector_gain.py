@@ -66,17 +66,22 @@ def test_choices_are_masked_like_plan_creation():
 
 
 def test_network_vs_fixed_variant_and_rule():
-    """The network's held-out choices against the best single variant (chosen
-    on the training set) and the best threshold rule, next to the label
-    noise (the spread between the two timing passes)."""
+    """The network's held-out choices against the best single fixed policy
+    (chosen on the training set) and the best threshold rule, next to the
+    label noise (the spread between the two timing passes). On the current
+    kernels the fixed policy 'V6 where the copy fits, else V4' is already
+    within 2% of the per-matrix best, less than the label noise, so no
+    selector can show a gain beyond the noise; the network's choices are
+    within 1% of the best and not worse than the fixed policy."""
     F, T, tr, te, P = _heldout_predictions()
     rep = evaluate(F, T, tr, te, P)
     noise = label_noise(DEFAULT_LABELS)
-    gain = rep["fixed_geomean_vs_best"] / rep["mlp_geomean_vs_best"]
-    assert rep["mlp_geomean_vs_best"] < 1.10
-    # the network's gain over the best fixed variant is outside the noise
-    assert gain > noise["label_noise_best_geomean"], (gain, noise)
-    assert rep["mlp_geomean_vs_best"] <= rep["rule_geomean_vs_best"] * 1.01
+    assert rep["mlp_geomean_vs_best"] < 1.01
+    assert rep["mlp_geomean_vs_best"] <= rep["fixed_geomean_vs_best"]
+    assert rep["mlp_geomean_vs_best"] <= rep["rule_geomean_vs_best"]
+    # headroom of any selector over the fixed policy, against the noise
+    assert rep["fixed_geomean_vs_best"] < noise["label_noise_best_geomean"]
+    assert rep["mlp_hit_rate"] > 0.8
 
 
 def test_report_matches_oracle_recomputation():
