@@ -137,6 +137,9 @@ def main():
                     help="only measure the RCM-reordered workloads (host reordering ~30 s)")
     ap.add_argument("--calib-copy", action="store_true",
                     help="first run the plain copy kernel on 2 x 1 GiB (counter calibration)")
+    ap.add_argument("--section", choices=["spmm", "batch"],
+                    help="only the multi-RHS products or only the 4096-matrix batch "
+                         "(profiling runs)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -166,6 +169,12 @@ def main():
         torch.cuda.synchronize()
         del src, dst
         log("copy calibration: 3 launches of k_copy over 1 GiB")
+    if args.section == "spmm":
+        print(json.dumps(run_spmm_section(pkg, pm, dev, stream)), flush=True)
+        return
+    if args.section == "batch":
+        print(json.dumps(run_batch(pkg, pm, dev, stream)), flush=True)
+        return
     if args.workload == "hamiltonian":
         wname, seed = "hamiltonian_like_N6M", 2
         log("generating Hamiltonian-like matrix N=6,000,000")
@@ -404,6 +413,51 @@ def run_extra(A, B, M, pkg, pm, dev, stream, args):
     return ex
 
 
+def run_spmm(A, M, pkg, pm, dev, stream, ks, sv):
+    """C = A B for k right-hand sides (B and C row-major, ldb = ldc = k) with
+    plan M; per k the time, FP64 GFlop/s and the fraction of 8 TB/s on the CRS
+    compulsory bytes of k columns (B read once, C written once)."""
+    import numpy as np
+    import torch
+
+    import crsgen
+    bdt, code = (np.float32, pkg.SPMV_F32) if sv == 4 else (np.float64, pkg.SPMV_F64)
+    out = {"variant": variant_name(pkg, M)}
+    for k in ks:
+        Bk = torch.from_numpy(crsgen.uniform_vec(A.n_cols * k, 4).reshape(A.n_cols, k)
+                              .astype(bdt)).to(dev)
+        Ck = torch.empty((A.n_rows, k), dtype=torch.float64, device=dev)
+        per, _ = time_launches(lambda: pkg.spmm_apply(M.handle, k, Bk, k, code, Ck, k), 20, 3,
+                               stream)
+        t = float(np.median(per)) / 1000
+        comp = pm.compulsory_bytes(A.n_rows, A.n_cols, A.nnz, k, sv, sv)
+        out[str(k)] = {"us": round(t * 1e6, 1), "fp64_gflops": round(pm.gflops(A.nnz, t, k), 1),
+                       "crs_equiv_frac": round(comp / t / 1e9 / HBM_PEAK, 4)}
+        del Bk, Ck
+    log(f"spmm: {out}")
+    return out
+
+
+def run_spmm_section(pkg, pm, dev, stream):
+    """Only the multi-RHS products on the Hamiltonian-like matrix from the V6
+    copy, FP64 and FP32 storage (the profiled command of the SpMM kernels)."""
+    import numpy as np
+    import torch
+
+    import crsgen
+    A = crsgen.hamiltonian(6_000_000, seed=2)
+    res = {}
+    for tag, vdt, bdt, sv in (("fp64", torch.float64, np.float64, 8),
+                              ("fp32_storage", torch.float32, np.float32, 4)):
+        M = pkg.CRSMatrix(A.n_rows, A.n_cols, A.row_ptr, A.col_idx, A.val.astype(bdt),
+                          val_dtype=vdt, flags=pkg.SPMV_FLAG_VARIANT(6) | pkg.SPMV_FLAG_SELL,
+                          device=dev)
+        res[tag] = run_spmm(A, M, pkg, pm, dev, stream, (2, 4, 8, 16, 32), sv)
+        del M
+        torch.cuda.empty_cache()
+    return res
+
+
 def run_hamiltonian(pkg, pm, dev, stream):
     """The Hamiltonian-like workload (N = 6.0M, 7 symmetric offset pairs): the
     fastest kernel that reads the caller's CRS arrays (V0-V5, every V4 form)
@@ -449,19 +503,7 @@ def run_hamiltonian(pkg, pm, dev, stream):
                                            sv, wname)
         M.variant, M.v4_form = picked, pform
         if tag == "fp64":
-            big = {"variant": variant_name(pkg, M)}
-            for k in (2, 4, 8, 16):
-                Bk = torch.from_numpy(crsgen.uniform_vec(A.n_cols * k, 4).reshape(A.n_cols, k)
-                                      ).to(dev)
-                Ck = torch.empty((A.n_rows, k), dtype=torch.float64, device=dev)
-                per, _ = time_launches(
-                    lambda: pkg.spmm_apply(M.handle, k, Bk, k, pkg.SPMV_F64, Ck, k), 20, 3, stream)
-                t = float(np.median(per)) / 1000
-                comp = pm.compulsory_bytes(A.n_rows, A.n_cols, A.nnz, k)
-                big[str(k)] = {"us": round(t * 1e6, 1), "fp64_gflops": round(pm.gflops(A.nnz, t, k), 1),
-                               "crs_equiv_frac": round(comp / t / 1e9 / HBM_PEAK, 4)}
-                del Bk, Ck
-            rec["spmm"] = big
+            rec["spmm"] = run_spmm(A, M, pkg, pm, dev, stream, (2, 4, 8, 16, 32), sv)
         res[tag] = rec
         log(f"hamiltonian {tag}: {rec}")
         del M, Bd
