@@ -305,13 +305,14 @@ def test_full_size_hamiltonian_and_mesh():
 
 def test_full_size_spmm_hamiltonian():
     """Multi-RHS on the full N = 6.0M Hamiltonian-like matrix with the plan the
-    benchmark times (autotuned, V6 copy requested): k = 2 and 8 run from the
-    chunked copy through its 8-bit deltas, k = 16 on the CRS row-group
-    kernel; every entry checked against the oracle."""
+    benchmark times (autotuned, V6 copy requested), from the chunked copy
+    through its 8-bit deltas: k = 2 in column blocks, k = 8, 16 and 32 in
+    lane groups (k = 32: 1.5 GB of B, XCD-contiguous chunk order); every
+    entry checked against the oracle."""
     A = crsgen.hamiltonian(6_000_000, seed=2)
     M = pkg.CRSMatrix.from_crs(A, flags=pkg.SPMV_SELECT_AUTOTUNE | SELL, device=DEV)
     assert M.variant == pkg.SPMV_V6_SELL64
-    for k in (2, 8, 16):
+    for k in (2, 8, 16, 32):
         Bh = crsgen.uniform_vec(A.n_cols * k, 4).reshape(A.n_cols, k)
         Cref, S = oracle.spmm(A.n_rows, A.row_ptr, A.col_idx, A.val, Bh)
         C = M.spmm(_gpu(Bh)).cpu().numpy()
