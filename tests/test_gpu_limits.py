@@ -95,3 +95,44 @@ def test_largest_plan_fp32_storage(big):
     _check(M, B32, rows_d, expect, (4, 6))
     del M, v32, B32
     torch.cuda.empty_cache()
+
+
+def test_many_rows_capped_grids():
+    """70M rows: V3 (64 lanes per row) and V2 (16) need more than 2^32 work
+    items as one lane per lane-slot, which one dispatch cannot hold; their
+    grids are capped and loop over the rows. A diagonal matrix with small
+    integer entries makes every product exact: sampled rows against the
+    oracle, every row against the diagonal's closed form a_ii b_i, for each
+    variant V0-V5 and for an autotuned plan."""
+    n = 70_000_000
+    i = torch.arange(n, device=DEV, dtype=torch.int64)
+    rp = torch.arange(n + 1, device=DEV, dtype=torch.int32)
+    ci = rp[:n].clone()
+    val = ((i % 7) - 3).to(torch.float64)
+    B = ((i % 5) - 2).to(torch.float64)
+    want = val * B  # exact: small integers
+    del i
+    rng = np.random.default_rng(5)
+    rows = np.unique(np.concatenate([rng.choice(n, 500, replace=False), [0, 63, 64, n - 1]]))
+    vs = ((rows % 7) - 3).astype(np.float64)
+    bs = ((rows % 5) - 2).astype(np.float64)
+    expect, _ = oracle.spmv(len(rows), np.arange(len(rows) + 1, dtype=np.int32),
+                            np.arange(len(rows), dtype=np.int32), vs, bs)
+    rows_d = torch.from_numpy(rows).to(DEV)
+    C = torch.empty(n, dtype=torch.float64, device=DEV)
+    M = pkg.CRSMatrix(n, n, rp, ci, val, flags=pkg.SPMV_FLAG_VARIANT(0), device=DEV)
+    for v in range(6):
+        M.variant = v
+        C.fill_(float("nan"))
+        M.apply(B, C)
+        assert np.array_equal(C[rows_d].cpu().numpy(), expect), v
+        assert torch.equal(C, want), v
+    del M
+    Ma = pkg.CRSMatrix(n, n, rp, ci, val, flags=pkg.SPMV_SELECT_AUTOTUNE, device=DEV)
+    t = pkg.spmv_get_autotune_times(Ma.handle)
+    assert np.all(np.isfinite(t[:6])), t
+    C.fill_(float("nan"))
+    Ma.apply(B, C)
+    assert torch.equal(C, want)
+    del Ma, C, rp, ci, val, B, want
+    torch.cuda.empty_cache()
