@@ -98,11 +98,9 @@ typedef enum {
  * deltas (10 bytes); other chunks read the 4-byte columns. All give the same
  * products in the same order. A pattern whose padded size
  * exceeds it still gets a plan, without V6 (spmv_get_sell_slots reports
- * SPMV_ERR_STATE); asking for V6 by name then fails with UNSUPPORTED. The
- * selector ranks V0..V5 only: with SPMV_SELECT_DEFAULT or SPMV_SELECT_MLP and
- * a built copy, its pick is timed against V6 at create (a warm-up and three
- * launches each, on a B of ones) and the faster is kept; autotune times V6
- * with the others. */
+ * SPMV_ERR_STATE); asking for V6 by name then fails with UNSUPPORTED. With
+ * a built copy the selector's V6 output is a candidate (without one it is
+ * ignored), and autotune times V6 with the others. */
 #define SPMV_FLAG_SELL 0x20000u
 /* V4 in its B-staging form: each row block copies a range of B into LDS (its
  * exact column span when that fits 2048 entries, 4096 for float32 plans, else
@@ -156,7 +154,8 @@ int spmv_workspace_size(int64_t n_rows, int64_t n_cols, int64_t nnz, uint32_t fl
  * device (row_ptr[0]=0, nondecreasing, row_ptr[n_rows]=nnz, 0<=col<n_cols)
  * and SPMV_ERR_BAD_CRS is returned on violation. This call synchronises the
  * stream: once to read back the analysis, and again for every timed launch
- * of autotune or of the V6 duel (see SPMV_FLAG_SELL). Apply calls never do.
+ * of autotune (also when SPMV_SELECT_MLP falls back to it). Apply calls never
+ * do.
  */
 int spmv_create(spmv_handle* h, int64_t n_rows, int64_t n_cols, int64_t nnz,
                 const int32_t* row_ptr, const int32_t* col_idx, const void* val,

@@ -1,6 +1,6 @@
 // CRS product kernels: variants V0..V5 (V4 in its plain and its B-staging
-// form) and the multi-RHS form; V6, which reads a chunked copy of the matrix,
-// is in sell.hip.
+// form; its window form is in window.hip) and the multi-RHS form; V6, which
+// reads a chunked copy of the matrix, is in sell.hip.
 //
 // All compute C(i) = sum_j val(j) * B(col_idx(j)) (the paper's Sect. 1.2
 // loop) with float64 accumulation; they differ only in how rows and nonzeros
