@@ -370,7 +370,13 @@ __global__ __launch_bounds__(WAVES * 64) void k_win_rows(int64_t n_rows, int64_t
 // coverage, never correctness), then the `nw` bins with the largest counts,
 // ties to the smaller bin. Unused entries are -1. The entries the chosen
 // windows hold are added to h->win_covered.
-constexpr int kHash = 8192;
+// 4096 slots (32 KB of LDS with the counts, four workgroups per CU): the
+// permuted mesh's super-blocks hold ~2,700 distinct bins, most of them single
+// random extras; 8192 slots took 1.8 ms longer there (two workgroups per CU),
+// 2048 slots overflowed and probed long
+constexpr int kHash = 4096;
+constexpr int kHashLog = 12;
+static_assert(kHash == 1 << kHashLog, "hash size");
 constexpr int kProbe = 32;
 constexpr int kSelWG = 256;
 
@@ -407,7 +413,7 @@ __global__ __launch_bounds__(kSelWG) void k_sb_windows(int64_t n_rows, int64_t n
       const int32_t lb = __shfl(bin, leader);
       const uint64_t same = __ballot(act && bin == lb);
       if (lane == leader) {
-        uint32_t slot = ((uint32_t)lb * 2654435761u) >> (32 - 13);
+        uint32_t slot = ((uint32_t)lb * 2654435761u) >> (32 - kHashLog);
         for (int t = 0; t < kProbe; ++t) {
           const int32_t old = atomicCAS(&key[slot], -1, lb);
           if (old == -1 || old == lb) {

@@ -50,6 +50,7 @@ def check_meta(path: str) -> None:
     meta = {"kernel_source_hash": source_hash(), "files": list(LABEL_SOURCES),
             "variants": "V0-V6", "seed": SEED, "n_range": [NLO, NHI]}
     mp = labels_meta_path(path)
+    os.makedirs(os.path.dirname(os.path.abspath(path)), exist_ok=True)
     if os.path.exists(path) and os.path.getsize(path) > 0:
         old = json.load(open(mp)) if os.path.exists(mp) else {}
         if old.get("kernel_source_hash") != meta["kernel_source_hash"]:
