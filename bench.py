@@ -137,9 +137,9 @@ def main():
                     help="only measure the RCM-reordered workloads (host reordering ~30 s)")
     ap.add_argument("--calib-copy", action="store_true",
                     help="first run the plain copy kernel on 2 x 1 GiB (counter calibration)")
-    ap.add_argument("--section", choices=["spmm", "batch"],
-                    help="only the multi-RHS products or only the 4096-matrix batch "
-                         "(profiling runs)")
+    ap.add_argument("--section", choices=["spmm", "batch", "batch-modes"],
+                    help="only the multi-RHS products, only the 4096-matrix batch, or only "
+                         "its one-launch modes (profiling runs)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -172,8 +172,9 @@ def main():
     if args.section == "spmm":
         print(json.dumps(run_spmm_section(pkg, pm, dev, stream)), flush=True)
         return
-    if args.section == "batch":
-        print(json.dumps(run_batch(pkg, pm, dev, stream)), flush=True)
+    if args.section in ("batch", "batch-modes"):
+        print(json.dumps(run_batch(pkg, pm, dev, stream, each=args.section == "batch")),
+              flush=True)
         return
     if args.workload == "hamiltonian":
         wname, seed = "hamiltonian_like_N6M", 2
@@ -687,7 +688,7 @@ def run_small(pkg, pm, dev, stream):
     return res
 
 
-def run_batch(pkg, pm, dev, stream):
+def run_batch(pkg, pm, dev, stream, each=True):
     """Uneven batch: 4096 seeded matrices, N log-uniform in [100, 5000]."""
     import numpy as np
     import torch
@@ -728,6 +729,9 @@ def run_batch(pkg, pm, dev, stream):
                                         "own_gbs": round(own / t / 1e9, 1),
                                         "crs_equiv_gbs": round(comp / t / 1e9, 1),
                                         "gflops": round(pm.gflops(nnz, t), 1)}
+    if not each:  # the one-launch modes only (counter runs)
+        log(f"batch: {res}")
+        return res
     rec("separate_launches_4096", lambda: Bt.apply_each(bh, ch), steps=5)
     s = torch.cuda.Stream()
     torch.cuda.synchronize()

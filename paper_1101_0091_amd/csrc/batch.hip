@@ -193,10 +193,8 @@ __device__ __forceinline__ void batch_tile(dev::BlockLds& L, const int32_t* __re
 // range's tiles in turn, l, l + g, l + 2 g, ... At any moment the tiles in
 // flight on an XCD are neighbours, as in the one-workgroup-per-tile launch
 // (contiguous ranges per workgroup put the workgroups' tiles far apart and
-// ran 1.1x slower on the 4096-matrix batch). Held to 8 wavefronts per SIMD
-// (64 registers; a few spill): at its natural 82 registers only 5 of the 8
-// workgroups a CU holds in the one-per-tile launch were resident, and the
-// static split cannot make up for fewer tiles in flight.
+// ran 1.1x slower on the 4096-matrix batch). 8 wavefronts per SIMD, as many
+// workgroups per CU as the one-per-tile launch.
 template <typename VT, typename BT>
 __global__ __launch_bounds__(kWG, 8) void k_batch_static(
     int64_t t0, int64_t t1, const int32_t* __restrict__ tiles,
@@ -272,9 +270,8 @@ __device__ __forceinline__ void next_claim(ClaimState& S, int x, int64_t t0, int
   out[1] = ce;
 }
 
-// 6 wavefronts per SIMD (80 registers, no spills) measured best.
 template <typename VT, typename BT>
-__global__ __launch_bounds__(kWG, 6) void k_batch_dynamic(
+__global__ __launch_bounds__(kWG, 8) void k_batch_dynamic(
     int64_t t0, int64_t t1, const int32_t* __restrict__ tiles,
     const int32_t* const* __restrict__ rps, const int32_t* const* __restrict__ cis,
     const void* const* __restrict__ vals, const void* const* __restrict__ Bs,
