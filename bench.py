@@ -256,7 +256,18 @@ def main():
         # the paper's practice: performance against the measured STREAM triad
         out["pct_of_box_triad"] = round(100.0 * achieved / extra["triad_gbs"], 2)
     if not args.no_cpu_baseline:
-        out["cpu_baseline"], out["host_node_scheme"] = cpu_baseline(A, B)
+        gpu_results = None
+        if not args.f32:
+            # the headline product (last timed launch) and the FP32-storage
+            # product of the same matrix, for the accuracy report
+            M32 = pkg.CRSMatrix(A.n_rows, A.n_cols, A.row_ptr, A.col_idx, A.val.astype(np.float32),
+                                val_dtype=torch.float32, flags=SELL, device=dev)
+            C32 = M32.apply(torch.from_numpy(B.astype(np.float32)).to(dev))
+            gpu_results = (C.cpu().numpy(), C32.cpu().numpy())
+            del M32, C32
+        out["cpu_baseline"], out["host_node_scheme"], acc = cpu_baseline(A, B, gpu_results)
+        if acc:
+            out["accuracy_vs_oracle"] = acc
         out["paper_cpu_context"] = PAPER_CPU
     print(json.dumps(out), flush=True)
 
@@ -776,12 +787,16 @@ def host_description():
     return info
 
 
-def cpu_baseline(A, B):
+def cpu_baseline(A, B, gpu_results=None):
     """The oracle (single-threaded plain C) timed on one host core, and the
     paper's node scheme (OpenMP static schedule over rows, first-touch
     placement; oracle/node.c) on all the host CPUs this process may use, with
     a host triad for its fraction of STREAM. Both on the headline matrix,
-    whole products repeated for a bounded sample."""
+    whole products repeated for a bounded sample. With the GPU's FP64 and
+    FP32-storage products of the same matrix, also their error against the
+    oracle's FP64 product: the FP64 one against the per-row bound
+    8 nnz_row 2^-53 S_i, the FP32-storage one as max |dC| / S_i and the
+    relative 2-norm (reported, not bounded)."""
     import numpy as np
 
     import oracle
@@ -792,7 +807,7 @@ def cpu_baseline(A, B):
     Cref = None
     while t < 10.0 and reps < 1000:
         t0 = time.perf_counter()
-        Cref, _ = oracle.spmv(A.n_rows, A.row_ptr, A.col_idx, A.val, B)
+        Cref, Sref = oracle.spmv(A.n_rows, A.row_ptr, A.col_idx, A.val, B)
         t += time.perf_counter() - t0
         reps += 1
     gf = 2.0 * A.nnz * reps / t / 1e9
@@ -816,7 +831,20 @@ def cpu_baseline(A, B):
                                                            Cref.view(np.int64))),
               "sample": f"{nreps} full products, {secs:.1f} s"}
     log(f"node scheme: {scheme}")
-    return base, scheme
+    acc = None
+    if gpu_results is not None:
+        c64, c32 = gpu_results
+        ok, worst = oracle.bound_ok(c64, Cref, A.row_ptr, Sref)
+        nz = Sref > 0
+        d32 = np.abs(c32 - Cref)
+        acc = {"fp64_within_bound": bool(ok), "fp64_worst_error_over_bound": float(worst),
+               "fp64_bitwise_equal_rows": float(np.mean(c64.view(np.int64) ==
+                                                        Cref.view(np.int64))),
+               "fp32_storage_max_err_over_S": float(np.max(d32[nz] / Sref[nz])),
+               "fp32_storage_rel_2norm": float(np.linalg.norm(c32 - Cref) /
+                                               np.linalg.norm(Cref))}
+        log(f"accuracy vs the oracle: {acc}")
+    return base, scheme, acc
 
 
 if __name__ == "__main__":
