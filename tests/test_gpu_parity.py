@@ -161,14 +161,50 @@ def test_concurrent_applies_on_two_streams(v):
 
 
 def test_deterministic_repeats():
+    """Run to run, 50 repeats of every product path give the same bits (the
+    race detector): every variant on power-law rows, the three V4 forms on
+    the permuted stencil, V6 and its lane-group multi-RHS kernel on the
+    Hamiltonian-like matrix, and the batch's persistent kernels (whose tile
+    order changes from launch to launch; each tile's sums do not)."""
+    reps = 50
     A, B = case("powerlaw_60k")
     M = pkg.CRSMatrix.from_crs(A, device=DEV)
     Bd = _gpu(B)
     for v in variants(M):
         M.variant = v
         first = M.apply(Bd).clone()
-        for _ in range(20):
+        for _ in range(reps):
             assert torch.equal(M.apply(Bd), first), v
+    Am, Bm = case("mesh3d_48_permuted")
+    Mm = pkg.CRSMatrix.from_crs(Am, flags=pkg.SPMV_FLAG_VARIANT(4), device=DEV)
+    Bmd = _gpu(Bm)
+    for f in (pkg.SPMV_V4_PLAIN, pkg.SPMV_V4_STAGED, pkg.SPMV_V4_WINDOWS):
+        Mm.v4_form = f
+        first = Mm.apply(Bmd).clone()
+        for _ in range(reps):
+            assert torch.equal(Mm.apply(Bmd), first), f
+    Ah, Bh = case("hamiltonian_200k")
+    Mh = pkg.CRSMatrix.from_crs(Ah, flags=pkg.SPMV_FLAG_VARIANT(6) | SELL, device=DEV)
+    first = Mh.apply(_gpu(Bh)).clone()
+    for _ in range(reps):
+        assert torch.equal(Mh.apply(_gpu(Bh)), first)
+    Bk = _gpu(crsgen.uniform_vec(Ah.n_cols * 8, 4).reshape(Ah.n_cols, 8))
+    first = Mh.spmm(Bk).clone()
+    for _ in range(reps):
+        assert torch.equal(Mh.spmm(Bk), first)
+    mats = _batch_mats(300, 8)
+    Bt = pkg.Batch(mats, device=DEV)
+    B_all = _gpu(crsgen.uniform_vec(int(Bt.n_cols.sum()), 8))
+    C_all = torch.zeros(int(Bt.n_rows.sum()), dtype=torch.float64, device=DEV)
+    Bp, Cp, _, _ = Bt.pointers(B_all, C_all)
+    for mode in (pkg.SPMV_BATCH_STATIC, pkg.SPMV_BATCH_DYNAMIC):
+        Bt.set_mode(mode)
+        Bt.apply(Bp, Cp)
+        first = C_all.clone()
+        for _ in range(reps):
+            C_all.fill_(float("nan"))
+            Bt.apply(Bp, Cp)
+            assert torch.equal(C_all, first), mode
 
 
 @pytest.mark.parametrize("dt", ["f64", "f32"])
