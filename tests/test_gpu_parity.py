@@ -602,6 +602,38 @@ def _banded_ragged(n, half, seed, jitter):
 
 
 @pytest.mark.parametrize("dt", ["f64", "f32"])
+@pytest.mark.parametrize("k", [4, 8, 16, 32])
+def test_spmm_lanes_ragged_last_chunk(k, dt):
+    """The lane-group multi-RHS kernel on 10,007 rows (the last 64-row chunk
+    holds 23 rows) with rows of different lengths: every entry against the
+    oracle, bitwise equal to the column-block/row-group path that an odd
+    leading dimension selects, and the 64 C rows past the matrix untouched."""
+    A = _banded_ragged(10_007, 20, seed=11, jitter=3)
+    n = A.n_rows
+    tdt = torch.float32 if dt == "f32" else torch.float64
+    val = A.val.astype(np.float32) if dt == "f32" else A.val
+    Bh = crsgen.uniform_vec(A.n_cols * k, 7).reshape(A.n_cols, k)
+    if dt == "f32":
+        Bh = Bh.astype(np.float32)
+    Cref, S = oracle.spmm(A.n_rows, A.row_ptr, A.col_idx, val, Bh)
+    M = pkg.CRSMatrix(A.n_rows, A.n_cols, A.row_ptr, A.col_idx, val, val_dtype=tdt,
+                      flags=pkg.SPMV_FLAG_VARIANT(6) | SELL, device=DEV)
+    assert M.sell_slots is not None
+    Cbig = torch.full((n + 64, k), 7.0, dtype=torch.float64, device=DEV)
+    pkg.spmm_apply(M.handle, k, _gpu(Bh), k, M.code, Cbig, k)
+    C = Cbig[:n].cpu().numpy()
+    ok, worst = oracle.bound_ok(C, Cref, A.row_ptr, S)
+    assert ok, worst
+    assert torch.all(Cbig[n:] == 7.0)
+    # an odd leading dimension of B takes the scalar paths: same products, same order
+    Bo = torch.zeros((A.n_cols, k + 1), dtype=tdt, device=DEV)
+    Bo[:, :k] = _gpu(Bh)
+    Co = torch.empty((n, k), dtype=torch.float64, device=DEV)
+    pkg.spmm_apply(M.handle, k, Bo, k + 1, M.code, Co, k)
+    assert torch.equal(Co, Cbig[:n])
+
+
+@pytest.mark.parametrize("dt", ["f64", "f32"])
 @pytest.mark.parametrize("n,half,jitter", [(10_007, 20, 3), (4_099, 7, 1), (130, 1, 1),
                                            (65, 40, 0), (64, 0, 0)])
 def test_sell_layout_rounds_and_ragged_tail(n, half, jitter, dt):
