@@ -488,6 +488,34 @@ def test_batch_vs_oracle_and_each(dt):
             assert torch.equal(C_all, C1), mode
 
 
+@pytest.mark.parametrize("count", [1, 2, 3, 5, 9])
+def test_batch_fewer_tiles_than_queues(count):
+    """Batches of a few small matrices: a persistent grid smaller than the 8
+    per-XCD ranges (static: as many ranges as workgroups; dynamic: every
+    range still drained by stealing), each mode against the oracle and
+    bitwise equal to the tile grid, repeated so the dynamic counters reset."""
+    mats = [crsgen.family_matrix(4, i, 100, 400)[0] for i in range(count)]
+    Bt = pkg.Batch(mats, device=DEV)
+    Bh = crsgen.uniform_vec(int(Bt.n_cols.sum()), 4)
+    B_all = _gpu(Bh)
+    C_all = torch.full((int(Bt.n_rows.sum()),), float("nan"), dtype=torch.float64, device=DEV)
+    Bd, Cd, _, _ = Bt.pointers(B_all, C_all)
+    Bt.set_mode(pkg.SPMV_BATCH_TILE_GRID)
+    Bt.apply(Bd, Cd)
+    ref = C_all.clone()
+    got = ref.cpu().numpy()
+    for m, A in enumerate(mats):
+        b = Bh[Bt.col_off[m]:Bt.col_off[m + 1]]
+        Cref, S = oracle.spmv(A.n_rows, A.row_ptr, A.col_idx, A.val, b)
+        assert oracle.bound_ok(got[Bt.row_off[m]:Bt.row_off[m + 1]], Cref, A.row_ptr, S)[0], m
+    for mode in (pkg.SPMV_BATCH_STATIC, pkg.SPMV_BATCH_DYNAMIC):
+        Bt.set_mode(mode)
+        for _ in range(3):
+            C_all.fill_(float("nan"))
+            Bt.apply(Bd, Cd)
+            assert torch.equal(C_all, ref), (mode, Bt.ntiles)
+
+
 def test_graph_replay_matches_eager():
     mats = _batch_mats(300, 7)
     Bt = pkg.Batch(mats, device=DEV)
