@@ -137,9 +137,10 @@ def main():
                     help="only measure the RCM-reordered workloads (host reordering ~30 s)")
     ap.add_argument("--calib-copy", action="store_true",
                     help="first run the plain copy kernel on 2 x 1 GiB (counter calibration)")
-    ap.add_argument("--section", choices=["spmm", "batch", "batch-modes"],
-                    help="only the multi-RHS products, only the 4096-matrix batch, or only "
-                         "its one-launch modes (profiling runs)")
+    ap.add_argument("--section", choices=["spmm", "batch", "batch-modes", "split"],
+                    help="only the multi-RHS products, only the 4096-matrix batch, only "
+                         "its one-launch modes, or only the split product over shard sizes "
+                         "(profiling runs)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -175,6 +176,9 @@ def main():
     if args.section in ("batch", "batch-modes"):
         print(json.dumps(run_batch(pkg, pm, dev, stream, each=args.section == "batch")),
               flush=True)
+        return
+    if args.section == "split":
+        print(json.dumps(run_split_section(pkg, pm, dev, stream)), flush=True)
         return
     if args.workload == "hamiltonian":
         wname, seed = "hamiltonian_like_N6M", 2
@@ -470,6 +474,22 @@ def run_spmm_section(pkg, pm, dev, stream):
     return res
 
 
+def run_split_section(pkg, pm, dev, stream):
+    """Only the split product, on shards of 1/16, 1/8, 1/4 and 1/2 of the
+    Hamiltonian-like matrix centred on its middle row: how the penalty of the
+    second pass changes with the shard size."""
+    import crsgen
+    A = crsgen.hamiltonian(6_000_000, seed=2)
+    B = crsgen.uniform_vec(A.n_cols, 2)
+    n = A.n_rows
+    res = {}
+    for s in (16, 8, 4, 2):
+        log(f"split shard 1/{s}")
+        res[f"1/{s}"] = run_split(A, B, pkg, pm, dev, stream, n // 2 - n // (2 * s),
+                                  n // 2 + n // (2 * s))
+    return res
+
+
 def run_hamiltonian(pkg, pm, dev, stream):
     """The Hamiltonian-like workload (N = 6.0M, 7 symmetric offset pairs): the
     fastest kernel that reads the caller's CRS arrays (V0-V5, every V4 form)
@@ -524,15 +544,17 @@ def run_hamiltonian(pkg, pm, dev, stream):
     return res
 
 
-def run_split(A, B, pkg, pm, dev, stream):
+def run_split(A, B, pkg, pm, dev, stream, r0=None, r1=None):
     """The split product of eq. (2) on one shard of the workload at its real
-    shape: rows [3N/8, 4N/8) of 8 row shards, local columns = the same range
-    (the columns that shard would own). Compared with the unsplit product of
-    the same rows; the model's penalty is eq. (2) / eq. (1) at kappa = 0."""
+    shape: by default rows [3N/8, 4N/8) of 8 row shards, local columns = the
+    same range (the columns that shard would own). Compared with the unsplit
+    product of the same rows; the model's penalty is eq. (2) / eq. (1) at
+    kappa = 0."""
     import numpy as np
     import torch
     n = A.n_rows
-    r0, r1 = 3 * n // 8, 4 * n // 8
+    if r0 is None:
+        r0, r1 = 3 * n // 8, 4 * n // 8
     s0, s1 = int(A.row_ptr[r0]), int(A.row_ptr[r1])
     rp = (A.row_ptr[r0:r1 + 1] - A.row_ptr[r0]).astype(np.int32)
     ci, va = A.col_idx[s0:s1], A.val[s0:s1]
@@ -554,6 +576,11 @@ def run_split(A, B, pkg, pm, dev, stream):
     # GPU byte form: the split adds a second row_ptr (4 B/row) and a C read + write (16 B/row)
     base = 12 * nnz + 4 * (rows + 1) + 8 * rows + 8 * rows
     res["gpu_model_penalty"] = round((base + 4 * (rows + 1) + 16 * rows) / base - 1, 4)
+    # the streams each launch must move (B gathers left out), as a rate
+    b_unsplit = 12 * nnz + 4 * (rows + 1) + 8 * rows
+    b_remote = 12 * S.nnz_remote + 4 * (rows + 1) + 16 * rows
+    res["unsplit_stream_gbs"] = round(b_unsplit / res["unsplit_us"] / 1e3, 1)
+    res["pass1_stream_gbs"] = round(b_remote / res["split_pass1_us"] / 1e3, 1)
     log(f"split: {res}")
     del U, S
     torch.cuda.empty_cache()
