@@ -250,7 +250,13 @@ def main():
                      "kernel_ms_min": round(float(np.min(per)), 5),
                      "algorithmic_bytes_per_launch": own,
                      "crs_compulsory_bytes_per_launch": comp,
-                     "kappa_bytes_per_nnz": kappa},
+                     "kappa_bytes_per_nnz": kappa,
+                     # the counted traffic over the kernel's time: how close the
+                     # bytes it actually moves come to the peak
+                     "traffic_gbs": (None if traffic is None else
+                                     round(traffic / (k_ms / 1000.0) / 1e9, 1)),
+                     "traffic_frac": (None if traffic is None else
+                                      round(traffic / (k_ms / 1000.0) / 1e9 / HBM_PEAK, 4))},
     }
     extra = {}
     if not args.no_extra:
