@@ -137,9 +137,11 @@ def main():
                     help="only measure the RCM-reordered workloads (host reordering ~30 s)")
     ap.add_argument("--calib-copy", action="store_true",
                     help="first run the plain copy kernel on 2 x 1 GiB (counter calibration)")
-    ap.add_argument("--section", choices=["spmm", "batch", "batch-modes", "split"],
+    ap.add_argument("--section",
+                    choices=["spmm", "batch", "batch-modes", "split", "config3-parts"],
                     help="only the multi-RHS products, only the 4096-matrix batch, only "
-                         "its one-launch modes, or only the split product over shard sizes "
+                         "its one-launch modes, only the split product over shard sizes, or "
+                         "only config 3 taken apart into its stencil and its random extras "
                          "(profiling runs)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -179,6 +181,10 @@ def main():
         return
     if args.section == "split":
         print(json.dumps(run_split_section(pkg, pm, dev, stream)), flush=True)
+        return
+    if args.section == "config3-parts":
+        print(json.dumps(run_config3_parts(pkg, pm, dev, stream, max(20, args.steps // 4))),
+              flush=True)
         return
     if args.workload == "hamiltonian":
         wname, seed = "hamiltonian_like_N6M", 2
@@ -493,6 +499,75 @@ def run_split_section(pkg, pm, dev, stream):
         log(f"split shard 1/{s}")
         res[f"1/{s}"] = run_split(A, B, pkg, pm, dev, stream, n // 2 - n // (2 * s),
                                   n // 2 + n // (2 * s))
+    return res
+
+
+def mesh_stencil_mask(A, p, m):
+    """True for the entries of the permuted mesh matrix that belong to its
+    7-point stencil (p[new] = old), False for the random extras."""
+    import numpy as np
+    rows = np.repeat(np.arange(A.n_rows, dtype=np.int32), np.diff(A.row_ptr))
+    i = p[rows].astype(np.int64)
+    del rows
+    d = p[A.col_idx].astype(np.int64) - i
+    x, y, z = i % m, (i // m) % m, i // (m * m)
+    mm = m * m
+    return ((d == 0) | ((d == 1) & (x < m - 1)) | ((d == -1) & (x > 0)) |
+            ((d == m) & (y < m - 1)) | ((d == -m) & (y > 0)) |
+            ((d == mm) & (z < m - 1)) | ((d == -mm) & (z > 0)))
+
+
+def run_config3_parts(pkg, pm, dev, stream, steps):
+    """Config 3 taken apart: its 7-point stencil alone and its ~17M random
+    extras alone, each with the plan the autotuner picks, then the extras as
+    a second pass adding into C after the stencil product (the split
+    machinery with an empty local window), against the one-pass product."""
+    import numpy as np
+    import torch
+
+    import crsgen
+    m = 280
+    A, p = crsgen.mesh3d(m, seed=3)
+    B = crsgen.uniform_vec(A.n_cols, 3)
+    st = mesh_stencil_mask(A, p, m)
+    n = A.n_rows
+    parts = {}
+    for tag, keep in (("stencil", st), ("extras", ~st)):
+        lens = np.bincount(np.repeat(np.arange(n, dtype=np.int32), np.diff(A.row_ptr))[keep],
+                           minlength=n)
+        rp = np.concatenate([[0], np.cumsum(lens)]).astype(np.int32)
+        parts[tag] = crsgen.CRS(n, n, rp, A.col_idx[keep], A.val[keep])
+    del st
+    Bd = torch.from_numpy(B).to(dev)
+    res = {"nnz": A.nnz, "nnz_stencil": parts["stencil"].nnz, "nnz_extras": parts["extras"].nnz,
+           "rows_with_extras": int(np.count_nonzero(np.diff(parts["extras"].row_ptr)))}
+    plans = {}
+    for tag, M_A in (("full", A), ("stencil", parts["stencil"]), ("extras", parts["extras"])):
+        M = pkg.CRSMatrix.from_crs(M_A, flags=pkg.SPMV_SELECT_AUTOTUNE | SELL, device=dev)
+        C = torch.empty(n, dtype=torch.float64, device=dev)
+        log(f"config3 parts: {tag} plan {variant_name(pkg, M)}")
+        res[tag] = kernel_record(pkg, pm, M, M_A,
+                                 lambda: pkg.spmv_apply(M.handle, Bd, pkg.SPMV_F64, C), stream, 8,
+                                 steps=steps)
+        plans[tag] = (M, C)
+    # two passes: stencil product, then the extras added by the split's remote pass
+    E = parts["extras"]
+    S = pkg.SplitMatrix(n, n, E.row_ptr, E.col_idx, E.val, 0, 0, device=dev)
+    Ms, C2 = plans["stencil"]
+
+    def two_pass():
+        pkg.spmv_apply(Ms.handle, Bd, pkg.SPMV_F64, C2)
+        S.apply(Bd, C2, pass_=1)
+    per, _ = time_launches(two_pass, steps, 3, stream)
+    res["two_pass_ms"] = round(float(np.median(per)), 5)
+    per, _ = time_launches(lambda: S.apply(Bd, C2, pass_=1), steps, 3, stream)
+    res["extras_second_pass_ms"] = round(float(np.median(per)), 5)
+    two_pass()
+    Mf, Cf = plans["full"]
+    pkg.spmv_apply(Mf.handle, Bd, pkg.SPMV_F64, Cf)
+    torch.cuda.synchronize()
+    res["two_pass_max_rel_diff"] = float(((C2 - Cf).abs().max() / Cf.abs().max()).item())
+    log(f"config3 parts: {res}")
     return res
 
 
