@@ -31,3 +31,22 @@ def test_kernel_source_hash_ignores_comments():
     b = "int f(int x) {\n  return x + 1;\n}  // changed comment\n"
     assert code_only(a) == code_only(b)
     assert code_only(a) != code_only(a.replace("x + 1", "x + 2"))
+
+
+def test_mesh_stencil_mask_separates_the_extras():
+    """The stencil/extras split of the config-3 profiling section: on small
+    permuted meshes with many extras, the entries it calls stencil are
+    exactly the mesh generated without extras (same rows, same columns)."""
+    import numpy as np
+
+    import bench
+    import crsgen
+    for m, seed in ((12, 3), (17, 8)):
+        A, p = crsgen.mesh3d(m, seed=seed, extra_frac=0.4)
+        S, _ = crsgen.mesh3d(m, seed=seed, extra_frac=0.0)
+        st = bench.mesh_stencil_mask(A, p, m)
+        rows = np.repeat(np.arange(A.n_rows), np.diff(A.row_ptr))
+        lens = np.bincount(rows[st], minlength=A.n_rows)
+        assert np.array_equal(np.concatenate([[0], np.cumsum(lens)]), S.row_ptr)
+        assert np.array_equal(A.col_idx[st], S.col_idx)
+        assert (~st).sum() == A.nnz - S.nnz > 0
