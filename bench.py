@@ -138,11 +138,11 @@ def main():
     ap.add_argument("--calib-copy", action="store_true",
                     help="first run the plain copy kernel on 2 x 1 GiB (counter calibration)")
     ap.add_argument("--section",
-                    choices=["spmm", "batch", "batch-modes", "split", "config3-parts"],
+                    choices=["spmm", "batch", "batch-modes", "split", "config3-parts", "small"],
                     help="only the multi-RHS products, only the 4096-matrix batch, only "
                          "its one-launch modes, only the split product over shard sizes, or "
-                         "only config 3 taken apart into its stencil and its random extras "
-                         "(profiling runs)")
+                         "only config 3 taken apart into its stencil and its random extras, or "
+                         "only the 2D Laplacian's product and multi-RHS products (profiling runs)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -181,6 +181,11 @@ def main():
         return
     if args.section == "split":
         print(json.dumps(run_split_section(pkg, pm, dev, stream)), flush=True)
+        return
+    if args.section == "small":
+        print(json.dumps({"laplace2d_256": run_small(pkg, pm, dev, stream),
+                          "spmm_laplace2d_256": run_spmm_small(pkg, pm, dev, stream)}),
+              flush=True)
         return
     if args.section == "config3-parts":
         print(json.dumps(run_config3_parts(pkg, pm, dev, stream, max(20, args.steps // 4))),
@@ -410,31 +415,7 @@ def run_extra(A, B, M, pkg, pm, dev, stream, args):
     if wname != "hamiltonian_like_N6M":
         ex["hamiltonian_like_N6M"] = run_hamiltonian(pkg, pm, dev, stream)
         ex["rcm_mesh3d_280"] = run_rcm(pkg, pm, dev, stream, A=A, B=B)["mesh3d_280_permuted"]
-    # multi-RHS on the 2D Laplacian (256^2)
-    L = crsgen.laplace2d(256)
-    ML = pkg.CRSMatrix.from_crs(L, device=dev)
-    ML32 = pkg.CRSMatrix(L.n_rows, L.n_cols, L.row_ptr, L.col_idx, L.val.astype(np.float32),
-                         val_dtype=torch.float32, device=dev)
-    spmm = {}
-    for k in (1, 4, 8, 16, 32):
-        Bk = torch.from_numpy(crsgen.uniform_vec(L.n_cols * k, 4).reshape(L.n_cols, k)).to(dev)
-        Ck = torch.empty((L.n_rows, k), dtype=torch.float64, device=dev)
-        per, _ = time_launches(lambda: pkg.spmm_apply(ML.handle, k, Bk, k, pkg.SPMV_F64, Ck, k),
-                               50, 5, stream)
-        t64 = float(np.median(per)) / 1000
-        Bk32 = Bk.float()
-        per, _ = time_launches(lambda: pkg.spmm_apply(ML32.handle, k, Bk32, k, pkg.SPMV_F32, Ck,
-                                                      k), 50, 5, stream)
-        t32 = float(np.median(per)) / 1000
-        c64 = cold_time(lambda: pkg.spmm_apply(ML.handle, k, Bk, k, pkg.SPMV_F64, Ck, k), stream)
-        c32 = cold_time(lambda: pkg.spmm_apply(ML32.handle, k, Bk32, k, pkg.SPMV_F32, Ck, k),
-                        stream)
-        spmm[str(k)] = {"fp64_gflops": round(pm.gflops(L.nnz, t64, k), 1),
-                        "mixed_gflops": round(pm.gflops(L.nnz, t32, k), 1),
-                        "fp64_cold_gflops": round(pm.gflops(L.nnz, c64, k), 1),
-                        "mixed_cold_gflops": round(pm.gflops(L.nnz, c32, k), 1)}
-    ex["spmm_laplace2d_256"] = spmm
-    log(f"spmm: {spmm}")
+    ex["spmm_laplace2d_256"] = run_spmm_small(pkg, pm, dev, stream)
     ex["batch_4096"] = run_batch(pkg, pm, dev, stream)
     ex["laplace2d_256"] = run_small(pkg, pm, dev, stream)
     ex["solvers_laplace2d_256"] = run_solvers(pkg, dev)
@@ -765,6 +746,65 @@ def run_solvers(pkg, dev):
     return res
 
 
+def graph_rate(pkg, fn, stream, reps=100):
+    """Seconds per call of `reps` calls captured back to back into one HIP
+    graph and replayed: the GPU-side rate of a product repeated on one stream
+    (as in an iterative solver), free of the per-call host cost of this
+    Python driver. `fn(s)` issues one call on stream s."""
+    import numpy as np
+    import torch
+    s = torch.cuda.Stream()
+    torch.cuda.synchronize()
+    pkg.spmv_graph_begin(s)
+    for _ in range(reps):
+        fn(s)
+    g = pkg.spmv_graph_end(s)
+    try:
+        per, _ = time_launches(lambda: pkg.spmv_graph_launch(g, stream), 10, 2, stream)
+    finally:
+        torch.cuda.synchronize()
+        pkg.spmv_graph_destroy(g)
+    return float(np.median(per)) / 1000 / reps
+
+
+def run_spmm_small(pkg, pm, dev, stream):
+    """Multi-RHS on the 2D Laplacian (256^2), k = 1, 4, 8, 16, 32, FP64 and
+    FP32 storage: event-timed per call, back to back, and cold."""
+    import numpy as np
+    import torch
+
+    import crsgen
+    L = crsgen.laplace2d(256)
+    ML = pkg.CRSMatrix.from_crs(L, flags=SELL, device=dev)
+    ML32 = pkg.CRSMatrix(L.n_rows, L.n_cols, L.row_ptr, L.col_idx, L.val.astype(np.float32),
+                         val_dtype=torch.float32, flags=SELL, device=dev)
+    spmm = {}
+    for k in (1, 4, 8, 16, 32):
+        Bk = torch.from_numpy(crsgen.uniform_vec(L.n_cols * k, 4).reshape(L.n_cols, k)).to(dev)
+        Ck = torch.empty((L.n_rows, k), dtype=torch.float64, device=dev)
+        Bk32 = Bk.float()
+        def f64(s=None):
+            pkg.spmm_apply(ML.handle, k, Bk, k, pkg.SPMV_F64, Ck, k, s)
+
+        def f32(s=None):
+            pkg.spmm_apply(ML32.handle, k, Bk32, k, pkg.SPMV_F32, Ck, k, s)
+        per, _ = time_launches(f64, 50, 5, stream)
+        t64 = float(np.median(per)) / 1000
+        per, _ = time_launches(f32, 50, 5, stream)
+        t32 = float(np.median(per)) / 1000
+        b64, b32 = graph_rate(pkg, f64, stream), graph_rate(pkg, f32, stream)
+        c64, c32 = cold_time(f64, stream), cold_time(f32, stream)
+        spmm[str(k)] = {"fp64_gflops": round(pm.gflops(L.nnz, t64, k), 1),
+                        "mixed_gflops": round(pm.gflops(L.nnz, t32, k), 1),
+                        "fp64_graph_gflops": round(pm.gflops(L.nnz, b64, k), 1),
+                        "mixed_graph_gflops": round(pm.gflops(L.nnz, b32, k), 1),
+                        "fp64_cold_gflops": round(pm.gflops(L.nnz, c64, k), 1),
+                        "mixed_cold_gflops": round(pm.gflops(L.nnz, c32, k), 1),
+                        "fp64_us": round(t64 * 1e6, 2), "fp64_graph_us": round(b64 * 1e6, 2)}
+    log(f"spmm: {spmm}")
+    return spmm
+
+
 def cold_time(fn, stream, reps=20):
     """Median duration (s) of fn with every cache cold: a 1 GiB buffer is
     written before each timed call."""
@@ -799,7 +839,9 @@ def run_small(pkg, pm, dev, stream):
     per, _ = time_launches(lambda: pkg.spmv_apply(M.handle, Bd, pkg.SPMV_F64, C), 50, 5, stream)
     warm = float(np.median(per)) / 1000
     cold_t = cold_time(lambda: pkg.spmv_apply(M.handle, Bd, pkg.SPMV_F64, C), stream)
+    g1 = graph_rate(pkg, lambda s: pkg.spmv_apply(M.handle, Bd, pkg.SPMV_F64, C, s), stream)
     res = {"variant": variant_name(pkg, M), "warm_us": round(warm * 1e6, 2),
+           "graph_us": round(g1 * 1e6, 2), "graph_gflops": round(pm.gflops(L.nnz, g1), 1),
            "cold_us": round(cold_t * 1e6, 2), "warm_gflops": round(pm.gflops(L.nnz, warm), 1),
            "cold_gflops": round(pm.gflops(L.nnz, cold_t), 1),
            "warm_eff_gbs": round(comp / warm / 1e9, 1), "cold_eff_gbs": round(comp / cold_t / 1e9, 1)}
