@@ -1,0 +1,150 @@
+"""Seeded random matrices of mixed structure through every product path.
+
+Each seed draws one small matrix from five structure families (uniform row
+lengths with empty rows; banded rows permuted within blocks, so that the B
+windows, the staged ranges and the chunked copy's column deltas all come
+into play; power-law lengths with rows longer than one row block; columns
+near the row's position at 8- and 16-bit delta distances, in rows of
+near-uniform length so that the chunked copy is built with its deltas;
+duplicate and unsorted columns in wide rectangular shapes), with random
+sizes that end in ragged tails. Every variant and every V4 form is checked
+against the oracle within the bound (the window form bit for bit), in both
+storage precisions, and a multi-RHS product with random k and padded
+leading dimensions against the oracle's, padding left untouched."""
+import numpy as np
+import pytest
+
+import crsgen
+import oracle
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+import paper_1101_0091_amd as pkg  # noqa: E402
+
+DEV = "cuda:0"
+SEEDS = list(range(40))
+
+
+def _csr(n_rows, n_cols, rows):
+    lens = np.array([len(r) for r in rows], dtype=np.int64)
+    rp = np.concatenate([[0], np.cumsum(lens)]).astype(np.int32)
+    ci = (np.concatenate(rows) if lens.sum() else np.zeros(0)).astype(np.int32)
+    return rp, ci
+
+
+def fuzz_matrix(seed):
+    """(CRS, family name) for one seed; sizes and structure drawn from it."""
+    rng = np.random.default_rng(1000 + seed)
+    fam = seed % 5
+    if fam == 0:  # uniform lengths, a fifth of the rows empty
+        n, m = int(rng.integers(1, 4000)), int(rng.integers(1, 6000))
+        lens = rng.poisson(rng.uniform(0.5, 40), size=n)
+        lens[rng.random(n) < 0.2] = 0
+        rows = [np.sort(rng.choice(m, size=min(int(l), m), replace=False)) for l in lens]
+    elif fam == 1:  # banded, rows and columns permuted within blocks of 512
+        n = int(rng.integers(600, 5000))
+        m = n
+        w = int(rng.integers(1, 40))
+        perm = np.arange(n)
+        for b in range(0, n, 512):
+            perm[b:b + 512] = b + rng.permutation(min(512, n - b))
+        inv = np.empty(n, dtype=np.int64)
+        inv[perm] = np.arange(n)
+        rows = []
+        for i in range(n):
+            o = perm[i]
+            cols = np.arange(max(0, o - w), min(n, o + w + 1))
+            rows.append(np.sort(inv[cols]))
+    elif fam == 2:  # power-law lengths, a few rows past one row block
+        n, m = int(rng.integers(100, 3000)), int(rng.integers(2500, 9000))
+        lens = np.minimum((rng.pareto(1.1, size=n) * 3).astype(np.int64), m)
+        lens[rng.integers(0, n, size=2)] = int(rng.integers(2049, min(m, 6000) + 1))
+        rows = [np.sort(rng.choice(m, size=int(l), replace=False)) for l in lens]
+    elif fam == 3:  # columns near the row's position: 8-bit (odd seeds) or 16-bit deltas
+        n = int(rng.integers(100, 4000))
+        m, spread = (n, 60) if seed % 2 else (n + int(rng.integers(0, 50_000)), 20_000)
+        rows = []
+        for i in range(n):
+            # near-uniform lengths, so that the chunked copy fits
+            c = (i * (m - 1)) // max(n - 1, 1)
+            offs = rng.integers(-spread, spread + 1, size=int(rng.integers(10, 15)))
+            rows.append(np.unique(np.clip(c + offs, 0, m - 1)))
+    else:  # duplicates and unsorted columns, wide rectangular
+        n, m = int(rng.integers(1, 2000)), int(rng.integers(1000, 200_000))
+        rows = []
+        for i in range(n):
+            r = rng.integers(0, m, size=int(rng.integers(0, 25)))
+            if len(r) > 2:
+                r = np.concatenate([r, r[:2]])  # repeated columns
+            rows.append(r)  # unsorted
+    rp, ci = _csr(n, m, rows)
+    val = rng.standard_normal(ci.shape[0])
+    val[rng.random(ci.shape[0]) < 0.05] = 0.0
+    return crsgen.CRS(n, m, rp, ci, val), ("uniform", "banded", "powerlaw", "clustered",
+                                           "dup_unsorted")[fam]
+
+
+def _rhs(A, seed, k=None):
+    rng = np.random.default_rng(2000 + seed)
+    shape = (A.n_cols,) if k is None else (A.n_cols, k)
+    B = rng.uniform(-1, 1, size=shape)
+    B[rng.random(shape) < 0.05] = 0.0
+    return B
+
+
+@pytest.mark.parametrize("dt", ["f64", "f32"])
+@pytest.mark.parametrize("seed", SEEDS)
+def test_fuzz_every_variant_and_form(seed, dt):
+    A, fam = fuzz_matrix(seed)
+    B = _rhs(A, seed)
+    if dt == "f32":
+        val_h, B_h, tdt = A.val.astype(np.float32), B.astype(np.float32), torch.float32
+    else:
+        val_h, B_h, tdt = A.val, B, torch.float64
+    Cref, S = oracle.spmv(A.n_rows, A.row_ptr, A.col_idx, val_h, B_h)
+    M = pkg.CRSMatrix(A.n_rows, A.n_cols, A.row_ptr, A.col_idx, val_h, val_dtype=tdt,
+                      flags=pkg.SPMV_FLAG_VARIANT(4) | pkg.SPMV_FLAG_SELL, device=DEV)
+    if fam in ("banded", "clustered"):
+        assert M.sell_slots is not None, (seed, fam)
+    Bd = torch.from_numpy(np.ascontiguousarray(B_h)).to(DEV)
+    for v in range(pkg.SPMV_NUM_VARIANTS):
+        if v == pkg.SPMV_V6_SELL64 and M.sell_slots is None:
+            continue
+        M.variant = v
+        for f in ((pkg.SPMV_V4_PLAIN, pkg.SPMV_V4_STAGED, pkg.SPMV_V4_WINDOWS) if v == 4
+                  else (None,)):
+            if f is not None:
+                M.v4_form = f
+            C = torch.full((A.n_rows,), float("nan"), dtype=torch.float64, device=DEV)
+            M.apply(Bd, C)
+            Ch = C.cpu().numpy()
+            ok, worst = oracle.bound_ok(Ch, Cref, A.row_ptr, S)
+            assert ok, (seed, fam, dt, v, f, worst)
+            if f == pkg.SPMV_V4_WINDOWS:
+                assert np.array_equal(Ch.view(np.int64), Cref.view(np.int64)), (seed, fam, dt)
+
+
+@pytest.mark.parametrize("seed", SEEDS[::2])
+def test_fuzz_multi_rhs_padded(seed):
+    A, fam = fuzz_matrix(seed)
+    rng = np.random.default_rng(3000 + seed)
+    k = int(rng.integers(1, 41))
+    pb, pc = int(rng.integers(0, 4)), int(rng.integers(0, 3))
+    for dt in ("f64", "f32"):
+        Bh = _rhs(A, seed, k)
+        val = A.val
+        tdt = torch.float64
+        if dt == "f32":
+            Bh, val, tdt = Bh.astype(np.float32), A.val.astype(np.float32), torch.float32
+        Cref, S = oracle.spmm(A.n_rows, A.row_ptr, A.col_idx, val, Bh)
+        M = pkg.CRSMatrix(A.n_rows, A.n_cols, A.row_ptr, A.col_idx, val, val_dtype=tdt,
+                          flags=pkg.SPMV_FLAG_SELL, device=DEV)
+        Bp = torch.zeros((A.n_cols, k + pb), dtype=tdt, device=DEV)
+        Bp[:, :k] = torch.from_numpy(np.ascontiguousarray(Bh)).to(DEV)
+        Cp = torch.full((A.n_rows, k + pc), 7.0, dtype=torch.float64, device=DEV)
+        pkg.spmm_apply(M.handle, k, Bp, k + pb, M.code, Cp, k + pc)
+        Cp = Cp.cpu().numpy()
+        ok, worst = oracle.bound_ok(Cp[:, :k], Cref, A.row_ptr, S)
+        assert ok, (seed, fam, dt, k, pb, pc, worst)
+        assert np.all(Cp[:, k:] == 7.0), (seed, fam, dt, k, pc)
