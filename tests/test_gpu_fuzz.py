@@ -10,7 +10,8 @@ duplicate and unsorted columns in wide rectangular shapes), with random
 sizes that end in ragged tails. Every variant and every V4 form is checked
 against the oracle within the bound (the window form bit for bit), in both
 storage precisions, and a multi-RHS product with random k and padded
-leading dimensions against the oracle's, padding left untouched."""
+leading dimensions against the oracle's, padding left untouched; and uneven
+batches of such matrices, with empty ones mixed in, in every launch mode."""
 import numpy as np
 import pytest
 
@@ -148,3 +149,52 @@ def test_fuzz_multi_rhs_padded(seed):
         ok, worst = oracle.bound_ok(Cp[:, :k], Cref, A.row_ptr, S)
         assert ok, (seed, fam, dt, k, pb, pc, worst)
         assert np.all(Cp[:, k:] == 7.0), (seed, fam, dt, k, pc)
+
+
+def _empty(n_rows, n_cols):
+    return crsgen.CRS(n_rows, n_cols, np.zeros(n_rows + 1, np.int32), np.zeros(0, np.int32),
+                      np.zeros(0))
+
+
+@pytest.mark.parametrize("dt", ["f64", "f32"])
+@pytest.mark.parametrize("seed", range(6))
+def test_fuzz_batch_every_mode(seed, dt):
+    """A batch of random size drawn from the same families, with matrices of
+    no rows and of no nonzeros mixed in: every matrix against the oracle, and
+    the persistent modes and the per-matrix launches bitwise equal to the
+    tile grid (repeated, so the dynamic kernel's counters reset themselves)."""
+    rng = np.random.default_rng(4000 + seed)
+    count = int(rng.integers(1, 150))
+    mats = [fuzz_matrix(int(s))[0] for s in rng.integers(0, 10_000, size=count)]
+    for pos, m in ((int(rng.integers(0, count + 1)), _empty(0, 7)),
+                   (int(rng.integers(0, count + 1)), _empty(300, 50))):
+        mats.insert(pos, m)
+    tdt = torch.float32 if dt == "f32" else torch.float64
+    if dt == "f32":
+        mats = [crsgen.CRS(m.n_rows, m.n_cols, m.row_ptr, m.col_idx, m.val.astype(np.float32))
+                for m in mats]
+    Bt = pkg.Batch(mats, val_dtype=tdt, device=DEV)
+    Bh = rng.uniform(-1, 1, size=int(Bt.n_cols.sum()))
+    if dt == "f32":
+        Bh = Bh.astype(np.float32)
+    B_all = torch.from_numpy(Bh).to(DEV)
+    C_all = torch.full((int(Bt.n_rows.sum()),), float("nan"), dtype=torch.float64, device=DEV)
+    Bd, Cd, bh, ch = Bt.pointers(B_all, C_all)
+    Bt.set_mode(pkg.SPMV_BATCH_TILE_GRID)
+    Bt.apply(Bd, Cd)
+    ref = C_all.clone()
+    got = ref.cpu().numpy()
+    for m, A in enumerate(mats):
+        b = Bh[Bt.col_off[m]:Bt.col_off[m + 1]]
+        Cref, S = oracle.spmv(A.n_rows, A.row_ptr, A.col_idx, A.val, b)
+        ok, worst = oracle.bound_ok(got[Bt.row_off[m]:Bt.row_off[m + 1]], Cref, A.row_ptr, S)
+        assert ok, (seed, dt, m, worst)
+    C_all.fill_(float("nan"))
+    Bt.apply_each(bh, ch)
+    assert torch.equal(C_all, ref), (seed, dt)
+    for mode in (pkg.SPMV_BATCH_STATIC, pkg.SPMV_BATCH_DYNAMIC):
+        Bt.set_mode(mode)
+        for _ in range(3):
+            C_all.fill_(float("nan"))
+            Bt.apply(Bd, Cd)
+            assert torch.equal(C_all, ref), (seed, dt, mode)
