@@ -138,11 +138,13 @@ def main():
     ap.add_argument("--calib-copy", action="store_true",
                     help="first run the plain copy kernel on 2 x 1 GiB (counter calibration)")
     ap.add_argument("--section",
-                    choices=["spmm", "batch", "batch-modes", "split", "config3-parts", "small"],
+                    choices=["spmm", "batch", "batch-modes", "split", "config3-parts", "small",
+                             "solvers"],
                     help="only the multi-RHS products, only the 4096-matrix batch, only "
                          "its one-launch modes, only the split product over shard sizes, or "
                          "only config 3 taken apart into its stencil and its random extras, or "
-                         "only the 2D Laplacian's product and multi-RHS products (profiling runs)")
+                         "only the 2D Laplacian's product and multi-RHS products, or only CG "
+                         "and Lanczos on it (profiling runs)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -181,6 +183,9 @@ def main():
         return
     if args.section == "split":
         print(json.dumps(run_split_section(pkg, pm, dev, stream)), flush=True)
+        return
+    if args.section == "solvers":
+        print(json.dumps(run_solvers(pkg, dev)), flush=True)
         return
     if args.section == "small":
         print(json.dumps({"laplace2d_256": run_small(pkg, pm, dev, stream),
