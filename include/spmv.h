@@ -109,15 +109,16 @@ typedef enum {
  * these flags force one form (setting both is SPMV_ERR_INVALID_ARG). */
 #define SPMV_FLAG_V4_STAGE_ON 0x40000u
 #define SPMV_FLAG_V4_STAGE_OFF 0x80000u
-/* V4 in its window form: super-blocks of 4096 rows, one 1024-lane workgroup
- * each, that copy the three (float32 plans: six) most used aligned 4096-column
+/* V4 in its window form: super-blocks of 4096 rows, one 512-lane workgroup
+ * each, that copy the two (float32 plans: three) most used aligned 4096-column
  * windows of B into LDS and gather from them where they can; each wavefront
- * streams 256 rows on its own and adds every row's products in CRS order (a
- * row with more than 64 entries in one 512-entry chunk is summed by its
- * wavefront as a tree). The windows are chosen at create from the columns of
- * each super-block. By default a plan takes this form when the windows hold
- * at least three quarters of the nonzeros and fewer than a quarter of the
- * row blocks fit the staging form exactly. Exclusive with the two flags above. */
+ * streams its 512 rows' nonzeros on its own, and each lane adds one row's
+ * products in CRS order, so every row equals the Sect. 1.2 loop bit for bit.
+ * The windows are chosen at create from the columns of each super-block. By
+ * default a plan takes this form when fewer than a quarter of its row blocks
+ * fit the staging form exactly, the windows hold at least 65% of the
+ * nonzeros and there are at least 512 super-blocks. Exclusive with the two
+ * flags above. */
 #define SPMV_FLAG_V4_WINDOWS 0x200000u
 /* With SPMV_FLAG_SELL: read every chunk of the V6 copy through its 4-byte
  * columns (the deltas are not built). Without SPMV_FLAG_SELL it is
