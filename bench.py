@@ -718,8 +718,14 @@ def run_solvers(pkg, dev):
     wsb = pkg.spmv_cg_workspace_size(n)
     ws = torch.empty(wsb, dtype=torch.uint8, device=dev)
     s = torch.cuda.Stream()
+    # the same system with V0 and V4 plans: two launches per CG iteration
+    # (search-direction update, product and p.Ap fused) against four
+    M0 = pkg.CRSMatrix.from_crs(L, flags=pkg.SPMV_FLAG_VARIANT(0), device=dev)
+    M4 = pkg.CRSMatrix.from_crs(L, flags=pkg.SPMV_FLAG_VARIANT(4), device=dev)
     res = {"variant_fp64": pkg.VARIANTS[M64.variant], "variant_fp32": pkg.VARIANTS[M32.variant]}
-    for tag, M, tol in (("cg_fp64", M64, 1e-10), ("cg_fp32_storage", M32, 1e-5)):
+    for tag, M, tol in (("cg_fp64", M64, 1e-10), ("cg_fp32_storage", M32, 1e-5),
+                        ("cg_fp64_v0_two_launches", M0, 1e-10),
+                        ("cg_fp64_v4_four_launches", M4, 1e-10)):
         for graph in (False, True):
             x = torch.zeros(n, dtype=torch.float64, device=dev)
             torch.cuda.synchronize()

@@ -230,10 +230,16 @@ int spmv_destroy(spmv_handle h);
  * Every vector operation and scalar stays on the device; an iteration is one
  * product with the plan's variant (an FP32-storage plan gets a float32 copy of
  * the search direction; the iteration itself is float64), two fixed-order dot
- * products and three vector updates. use_graph != 0 captures one iteration in
- * a HIP graph and replays it (needs a non-null stream). The recurrence
- * residual ||r||/||b|| is read back every check_every iterations (one sync
- * each); stops when it is <= tol or after maxit iterations. iters, relres:
+ * products and three vector updates, in four launches. For a plan running V0
+ * or V1 the search-direction update, the product (a lane per row, products
+ * added in CRS order: V0's arithmetic) and the first dot are one launch, so an
+ * iteration is two; with V0 its values equal the four-launch iteration's bit
+ * for bit. use_graph != 0 captures the iterations between two residual
+ * checks (the largest divisor of check_every up to 64) in one HIP graph and
+ * replays it, the same kernels in the same order (needs a non-null stream).
+ * The recurrence residual ||r||/||b|| is read back every check_every
+ * iterations (one sync each); stops when it is <= tol or after maxit
+ * iterations. iters, relres:
  * host out. workspace: spmv_cg_workspace_size(n) bytes, 256-byte aligned.
  * Results are bitwise reproducible for a given plan, b and x0.
  */
@@ -252,7 +258,7 @@ int spmv_cg_solve(spmv_handle h, const double* b, double* x, double tol, int32_t
  * calls an allocating routine. Iterations run as separate launches (no graph
  * mode). Arguments, results and synchronisation as spmv_cg_solve; the plan's
  * device must be current (else SPMV_ERR_STATE).
- * Limit: n <= 1,197,888 (28 bytes per row plus 13 KB), else
+ * Limit: n <= 931,680 (36 bytes per row plus 13 KB), else
  * SPMV_ERR_UNSUPPORTED. Every call on a GPU shares that GPU's array and the
  * array keeps the last call's contents (each call initialises what it reads):
  * calls that overlap in time on one GPU race, from any host thread or stream.

@@ -833,7 +833,7 @@ int spmv_cg_solve_noalloc(spmv_handle h, const double* b, double* x, double tol,
     return fail(SPMV_ERR_UNSUPPORTED,
                 "n = " + std::to_string(P.n_rows) + " needs " + std::to_string(need) +
                     " bytes of solver scratch; the library holds " +
-                    std::to_string(kNoAllocScratchBytes) + " (n <= 1197888)");
+                    std::to_string(kNoAllocScratchBytes) + " (n <= 931680)");
   int dev = 0;
   SPMV_HIP(hipGetDevice(&dev));
   if (dev != P.device) return fail(SPMV_ERR_STATE, "the plan's device must be current");

@@ -7,7 +7,10 @@
 // reproducible. The workgroup that finishes a reduction last (one counter
 // atomic per workgroup) sums the partials and updates the scalars in the same
 // launch, so an iteration is four launches: the product, the fused p.Ap
-// reduction, the fused x/r update with r.r, and the p update.
+// reduction, the fused x/r update with r.r, and the p update. For plans whose
+// product runs a lane per row or four lanes per row, the p update, the
+// product and the p.Ap reduction are one launch (k_cg_step), so an iteration
+// is two.
 #include <cmath>
 #include <vector>
 
@@ -127,7 +130,10 @@ __global__ __launch_bounds__(64) void k_clear_count(unsigned* count) {
 __global__ __launch_bounds__(kWG) void k_cg_init(const double* __restrict__ b,
                                                  const double* __restrict__ Ap,
                                                  double* __restrict__ r, double* __restrict__ p,
-                                                 float* __restrict__ p32, int64_t n) {
+                                                 float* __restrict__ p32, int64_t n,
+                                                 double* __restrict__ sc) {
+  // beta of the first step: k_cg_step forms p = r + 0 p
+  if (blockIdx.x == 0 && threadIdx.x == 0) sc[S_BETA] = 0.0;
   for (int64_t i = (int64_t)blockIdx.x * kWG + threadIdx.x; i < n;
        i += (int64_t)gridDim.x * kWG) {
     const double v = b[i] - Ap[i];
@@ -166,6 +172,63 @@ __global__ __launch_bounds__(kWG) void k_cg_p(double* __restrict__ p, float* __r
     p[i] = v;
     if (p32) p32[i] = (float)v;
   }
+}
+
+// One CG step in one launch, for plans whose product runs a lane per row
+// or four lanes per row: p = r + beta p is formed where it is used (at each
+// gathered column from r and the previous p, for the thread's own row into
+// pn), Ap = A p with a lane per row adding its products in CRS order (V0's
+// order), and p.Ap reduced over the same element partition and in the same
+// order as k_dot, then alpha = rr / p.Ap set by the last workgroup. With a
+// V0 plan every value equals the four-launch iteration's bit for bit.
+template <typename VT, typename BT>
+__global__ __launch_bounds__(kWG) void k_cg_step(const int32_t* __restrict__ rp,
+                                                 const int32_t* __restrict__ ci,
+                                                 const VT* __restrict__ val, int64_t n,
+                                                 const double* __restrict__ r,
+                                                 const double* __restrict__ p,
+                                                 double* __restrict__ pn, double* __restrict__ Ap,
+                                                 double* __restrict__ partials, Finish f) {
+  __shared__ double sh[4];
+  const double be = f.sc[S_BETA];
+  double s = 0.0;
+  for (int64_t i = (int64_t)blockIdx.x * kWG + threadIdx.x; i < n; i += (int64_t)kRed * kWG) {
+    const int32_t a = rp[i], e = rp[i + 1];
+    double acc = 0.0;
+    for (int32_t j = a; j < e; ++j) {
+      const int32_t c = ci[j];
+      const BT pc = (BT)fma(be, p[c], r[c]);
+      acc = fma(dev::widen(val[j]), dev::widen(pc), acc);
+    }
+    const double pi = fma(be, p[i], r[i]);
+    pn[i] = pi;
+    Ap[i] = acc;
+    s = fma(pi, acc, s);
+  }
+  s = block_sum(s, sh);
+  finish_if_last(partials, s, f, sh);
+}
+
+// After k_cg_step: x += alpha pn ; r -= alpha Ap ; p = pn ; r.r, then
+// beta = r.r / rr, rr = r.r
+__global__ __launch_bounds__(kWG) void k_cg_xr_pn(double* __restrict__ x, double* __restrict__ r,
+                                                  double* __restrict__ p,
+                                                  const double* __restrict__ pn,
+                                                  const double* __restrict__ Ap, int64_t n,
+                                                  double* __restrict__ partials, Finish f) {
+  __shared__ double sh[4];
+  const double a = f.sc[S_ALPHA];
+  double s = 0.0;
+  for (int64_t i = (int64_t)blockIdx.x * kWG + threadIdx.x; i < n; i += (int64_t)kRed * kWG) {
+    const double pi = pn[i];
+    x[i] = fma(a, pi, x[i]);
+    const double ri = fma(-a, Ap[i], r[i]);
+    r[i] = ri;
+    p[i] = pi;
+    s = fma(ri, ri, s);
+  }
+  s = block_sum(s, sh);
+  finish_if_last(partials, s, f, sh);
 }
 
 __global__ __launch_bounds__(kWG) void k_to_f32(float* __restrict__ d, const double* __restrict__ s,
@@ -236,13 +299,14 @@ struct SolverWs {
   double* r;
   double* p;
   double* Ap;
+  double* pn;  // the next search direction of the one-launch CG step
   float* p32;
 };
 
 size_t solver_ws_bytes(int64_t n, int64_t hist) {
   const size_t n1 = (size_t)std::max<int64_t>(n, 1);
   return kScBlock + align256(sizeof(double) * kRed) +
-         3 * align256(sizeof(double) * n1) + align256(sizeof(float) * n1) +
+         4 * align256(sizeof(double) * n1) + align256(sizeof(float) * n1) +
          align256(sizeof(double) * (size_t)std::max<int64_t>(hist, 1));
 }
 
@@ -261,6 +325,8 @@ SolverWs carve(void* ws, int64_t n) {
   c += align256(sizeof(double) * n1);
   w.Ap = reinterpret_cast<double*>(c);
   c += align256(sizeof(double) * n1);
+  w.pn = reinterpret_cast<double*>(c);
+  c += align256(sizeof(double) * n1);
   w.p32 = reinterpret_cast<float*>(c);
   return w;
 }
@@ -270,7 +336,7 @@ double* history(void* ws, int64_t n) {
   const size_t n1 = (size_t)std::max<int64_t>(n, 1);
   return reinterpret_cast<double*>(c + kScBlock +
                                    align256(sizeof(double) * kRed) +
-                                   3 * align256(sizeof(double) * n1) +
+                                   4 * align256(sizeof(double) * n1) +
                                    align256(sizeof(float) * n1));
 }
 
@@ -302,7 +368,26 @@ int dot(const double* x, const double* y, int64_t n, SolverWs& w, int op, int ds
 
 // one CG iteration: Ap = A p; alpha = rr/(p.Ap); x += alpha p; r -= alpha Ap;
 // beta = r.r/rr; rr = r.r; p = r + beta p
+bool cg_one_launch(const Plan& P) {
+  return P.variant == SPMV_V0_THREAD_ROW || P.variant == SPMV_V1_LANES4;
+}
+
 int cg_iteration(const Plan& P, double* x, SolverWs& w, int64_t n, hipStream_t s) {
+  if (cg_one_launch(P)) {
+    if (P.vdt == SPMV_F64)
+      k_cg_step<double, double><<<kRed, kWG, 0, s>>>(
+          P.row_ptr, P.col_idx, static_cast<const double*>(P.val), n, w.r, w.p, w.pn, w.Ap,
+          w.partials, fin(w, 2, 0, nullptr));
+    else
+      k_cg_step<float, float><<<kRed, kWG, 0, s>>>(
+          P.row_ptr, P.col_idx, static_cast<const float*>(P.val), n, w.r, w.p, w.pn, w.Ap,
+          w.partials, fin(w, 2, 0, nullptr));
+    SPMV_HIP(hipGetLastError());
+    k_cg_xr_pn<<<kRed, kWG, 0, s>>>(x, w.r, w.p, w.pn, w.Ap, n, w.partials,
+                                    fin(w, 3, 0, nullptr));
+    SPMV_HIP(hipGetLastError());
+    return SPMV_OK;
+  }
   int st = plan_apply_cast(P, w.p, w.p32, w.Ap, s);
   if (!st) st = dot(w.p, w.Ap, n, w, 2, 0, nullptr, s);
   if (st) return st;
@@ -332,7 +417,8 @@ int run_cg(const Plan& P, const double* b, double* x, double tol, int maxit, int
   int st = dot(b, b, n, w, 0, S_BB, nullptr, s);
   if (!st) st = plan_apply(P, x, w.p32, w.Ap, s);
   if (st) return st;
-  k_cg_init<<<vgrid(n), kWG, 0, s>>>(b, w.Ap, w.r, w.p, P.vdt == SPMV_F64 ? nullptr : w.p32, n);
+  k_cg_init<<<vgrid(n), kWG, 0, s>>>(b, w.Ap, w.r, w.p, P.vdt == SPMV_F64 ? nullptr : w.p32, n,
+                                     w.sc);
   SPMV_HIP(hipGetLastError());
   st = dot(w.r, w.r, n, w, 0, S_RR, nullptr, s);
   if (st) return st;
@@ -347,12 +433,22 @@ int run_cg(const Plan& P, const double* b, double* x, double tol, int maxit, int
     *iters = 0;
     return SPMV_OK;
   }
+  const int every = check_every > 0 ? check_every : 1;
+  // a graph holds the iterations between two residual checks (at most 64:
+  // the largest divisor of check_every up to 64), so one graph launch
+  // replaces that many iterations' launches
+  int per_graph = 1;
+  for (int d = std::min(every, 64); d >= 1; --d)
+    if (every % d == 0) {
+      per_graph = d;
+      break;
+    }
   hipGraphExec_t exec = nullptr;
   if (use_graph) {
     if (!s) return fail(SPMV_ERR_INVALID_ARG, "graph mode needs a non-null stream");
     hipGraph_t g = nullptr;
     SPMV_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
-    st = cg_iteration(P, x, w, n, s);
+    for (int k = 0; k < per_graph && !st; ++k) st = cg_iteration(P, x, w, n, s);
     hipError_t e = hipStreamEndCapture(s, &g);
     if (st) {
       if (g) hipGraphDestroy(g);
@@ -363,19 +459,22 @@ int run_cg(const Plan& P, const double* b, double* x, double tol, int maxit, int
     hipGraphDestroy(g);
     if (e != hipSuccess) return hip_fail(e, "hipGraphInstantiate");
   }
-  const int every = check_every > 0 ? check_every : 1;
   while (it < maxit) {
-    if (exec) {
+    if (exec && it + per_graph <= maxit) {
       hipError_t e = hipGraphLaunch(exec, s);
       if (e != hipSuccess) {
         hipGraphExecDestroy(exec);
         return hip_fail(e, "hipGraphLaunch");
       }
+      it += per_graph;
     } else {
       st = cg_iteration(P, x, w, n, s);
-      if (st) return st;
+      if (st) {
+        if (exec) hipGraphExecDestroy(exec);
+        return st;
+      }
+      ++it;
     }
-    ++it;
     if (it % every == 0 || it == maxit) {
       hipError_t e = hipMemcpyAsync(&rr, w.sc + S_RR, sizeof(double), hipMemcpyDeviceToHost, s);
       if (e == hipSuccess) e = hipStreamSynchronize(s);

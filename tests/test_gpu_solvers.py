@@ -132,13 +132,15 @@ def _cpu_cg(A, b, iters):
     return x, math.sqrt(rr) / np.linalg.norm(b)
 
 
+@pytest.mark.parametrize("variant", [4, 0, 1])
 @pytest.mark.parametrize("graph", [False, True])
-def test_cg_fixed_iterations_match_cpu_cg(lap128, graph):
+def test_cg_fixed_iterations_match_cpu_cg(lap128, graph, variant):
     """Each iteration's scalars come from the fused reductions (the last
     workgroup sums the partials); 25 iterations against a CPU CG pin every
-    alpha and beta along the way."""
+    alpha and beta along the way -- in four launches per iteration (V4) and
+    in two (V0, V1: search-direction update, product and p.Ap in one)."""
     A, xs, b = lap128
-    M = pkg.CRSMatrix.from_crs(A, flags=pkg.SPMV_FLAG_VARIANT(4), device=DEV)
+    M = pkg.CRSMatrix.from_crs(A, flags=pkg.SPMV_FLAG_VARIANT(variant), device=DEV)
     xr, rr_ref = _cpu_cg(A, b, 25)
     first = None
     for rep in range(5):  # the counters must be back at zero for every later solve
@@ -188,3 +190,35 @@ def test_cg_on_the_chunked_copy(lap128, dt):
     assert it1 == it2 and r1 == r2 and np.array_equal(x1, x2)
     Ax, _ = oracle.spmv(A.n_rows, A.row_ptr, A.col_idx, A.val, x1)
     assert np.linalg.norm(b - Ax) / np.linalg.norm(b) <= (1e-4 if dt == "f32" else 1e-9)
+
+
+def _diag_plan(d, variant, dt):
+    n = d.shape[0]
+    rp = np.arange(n + 1, dtype=np.int32)
+    val = d.astype(np.float32) if dt == "f32" else d
+    return pkg.CRSMatrix(n, n, rp, rp[:-1], val,
+                         val_dtype=torch.float32 if dt == "f32" else torch.float64,
+                         flags=pkg.SPMV_FLAG_VARIANT(variant), device=DEV)
+
+
+@pytest.mark.parametrize("dt", ["f64", "f32"])
+@pytest.mark.parametrize("n", [70_001, 300_007])
+def test_two_launch_cg_equals_four_launch(n, dt):
+    """On a diagonal matrix every variant's product is the same single
+    rounded product, so CG through the one-launch step (V0 plan) and through
+    the four launches (V4 plan) perform the same operations: x and the
+    residual equal bit for bit after 40 iterations, eager and graph-replayed
+    (300,007 rows take the reduction grid's stride loop twice)."""
+    rng = np.random.default_rng(n)
+    d = 1.0 + rng.integers(0, 4096, size=n) / 1024.0  # exact in float32 too
+    b = rng.uniform(-1, 1, size=n)
+    out = []
+    for v in (0, 4):
+        M = _diag_plan(d, v, dt)
+        for graph in (False, True):
+            x, it, rr = _cg(M, b, 0.0, maxit=40, graph=graph, check_every=8)
+            assert it == 40
+            out.append((x, rr))
+    for x, rr in out[1:]:
+        assert rr == out[0][1]
+        assert np.array_equal(x.view(np.int64), out[0][0].view(np.int64))

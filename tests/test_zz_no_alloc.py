@@ -1,9 +1,10 @@
 """spmv_cg_solve_noalloc (the solver scratch held by the library in a static
 device array) against spmv_cg_solve with a caller-supplied workspace: the
 same kernels in the same order, so the same iteration count, residual and x
-bit for bit -- on two calls in a row, the second with a smaller system, in
-float64 and float32 storage; a system beyond the scratch is refused and the
-largest one that fits runs."""
+bit for bit -- on calls in a row, each pair's second with a smaller system,
+through the four-launch iteration (V4 plans) and the two-launch one (V0
+plans), in float64 and float32 storage; a system beyond the scratch is
+refused and the largest one that fits runs."""
 import numpy as np
 import pytest
 
@@ -15,7 +16,7 @@ torch = pytest.importorskip("torch")
 import paper_1101_0091_amd as pkg  # noqa: E402
 
 DEV = "cuda:0"
-N_MAX = 1_197_888
+N_MAX = 931_680
 
 
 def _solve(M, b, tol, noalloc, check_every=10):
@@ -36,16 +37,16 @@ def _solve(M, b, tol, noalloc, check_every=10):
 @pytest.mark.parametrize("dt", ["f64", "f32"])
 def test_noalloc_cg_equals_workspace_cg(dt):
     tol = 1e-10 if dt == "f64" else 1e-5
-    for m in (256, 96):  # the second call is smaller than the first
+    for m, v in ((256, 4), (96, 4), (200, 0), (64, 0)):  # each second call smaller
         A = crsgen.laplace2d(m)
         xs = crsgen.uniform_vec(A.n_rows, 8)
         b, _ = oracle.spmv(A.n_rows, A.row_ptr, A.col_idx, A.val, xs)
         if dt == "f32":
             M = pkg.CRSMatrix(A.n_rows, A.n_cols, A.row_ptr, A.col_idx, A.val.astype(np.float32),
-                              val_dtype=torch.float32, flags=pkg.SPMV_FLAG_VARIANT(4),
+                              val_dtype=torch.float32, flags=pkg.SPMV_FLAG_VARIANT(v),
                               device=DEV)
         else:
-            M = pkg.CRSMatrix.from_crs(A, flags=pkg.SPMV_FLAG_VARIANT(4), device=DEV)
+            M = pkg.CRSMatrix.from_crs(A, flags=pkg.SPMV_FLAG_VARIANT(v), device=DEV)
         x_na, it_na, rr_na = _solve(M, b, tol, noalloc=True)
         x_ws, it_ws, rr_ws = _solve(M, b, tol, noalloc=False)
         assert it_na == it_ws and rr_na == rr_ws, (m, dt)
