@@ -195,10 +195,30 @@ __global__ __launch_bounds__(kWG) void k_cg_step(const int32_t* __restrict__ rp,
   for (int64_t i = (int64_t)blockIdx.x * kWG + threadIdx.x; i < n; i += (int64_t)kRed * kWG) {
     const int32_t a = rp[i], e = rp[i + 1];
     double acc = 0.0;
-    for (int32_t j = a; j < e; ++j) {
+    int32_t j = a;
+    // four entries at a time, every load issued before the first use (the
+    // products are still added one by one in CRS order)
+    for (; j + 4 <= e; j += 4) {
+      int32_t c[4];
+      VT v[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        c[u] = ci[j + u];
+        v[u] = val[j + u];
+      }
+      double pv[4], rv[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        pv[u] = p[c[u]];
+        rv[u] = r[c[u]];
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+        acc = fma(dev::widen(v[u]), dev::widen((BT)fma(be, pv[u], rv[u])), acc);
+    }
+    for (; j < e; ++j) {
       const int32_t c = ci[j];
-      const BT pc = (BT)fma(be, p[c], r[c]);
-      acc = fma(dev::widen(val[j]), dev::widen(pc), acc);
+      acc = fma(dev::widen(val[j]), dev::widen((BT)fma(be, p[c], r[c])), acc);
     }
     const double pi = fma(be, p[i], r[i]);
     pn[i] = pi;
