@@ -743,16 +743,18 @@ def run_solvers(pkg, dev):
     lb = pkg.spmv_lanczos_workspace_size(n, k)
     lws = torch.empty(lb, dtype=torch.uint8, device=dev)
     v0 = torch.from_numpy(crsgen.uniform_vec(n, 7)).to(dev)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    al, be = pkg.spmv_lanczos(M64.handle, v0, k, lws, lb)
-    t = time.perf_counter() - t0
     from scipy.linalg import eigvalsh_tridiagonal
-    th = eigvalsh_tridiagonal(al, be[:-1])
     c = np.cos(np.pi / 257)
-    res["lanczos_fp64"] = {"steps": k, "us_per_step": round(1e6 * t / k, 2),
-                           "max_ritz_err": float(abs(th[-1] - (4 + 4 * c))),
-                           "min_ritz_err": float(abs(th[0] - (4 - 4 * c)))}
+    for tag, M in (("lanczos_fp64", M64), ("lanczos_fp64_v0_two_launches", M0),
+                   ("lanczos_fp64_v4_four_launches", M4)):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        al, be = pkg.spmv_lanczos(M.handle, v0, k, lws, lb)
+        t = time.perf_counter() - t0
+        th = eigvalsh_tridiagonal(al, be[:-1])
+        res[tag] = {"steps": k, "us_per_step": round(1e6 * t / k, 2),
+                    "max_ritz_err": float(abs(th[-1] - (4 + 4 * c))),
+                    "min_ritz_err": float(abs(th[0] - (4 - 4 * c)))}
     log(f"solvers: {res}")
     return res
 

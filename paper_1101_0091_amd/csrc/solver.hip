@@ -10,7 +10,7 @@
 // reduction, the fused x/r update with r.r, and the p update. For plans whose
 // product runs a lane per row or four lanes per row, the p update, the
 // product and the p.Ap reduction are one launch (k_cg_step), so an iteration
-// is two.
+// is two; a Lanczos step likewise (k_lz_step, then k_lz_b).
 #include <cmath>
 #include <vector>
 
@@ -294,6 +294,59 @@ __global__ __launch_bounds__(kWG) void k_lz_b(double* __restrict__ w,
   finish_if_last(partials, s, f, sh);
 }
 
+// The first half of a Lanczos step in one launch, for plans whose product
+// runs a lane per row or four lanes per row: v_j = w / beta_j formed where it
+// is used (at each gathered column, and for the own row into vout) unless vin
+// already holds v_j (the first step), w = A v_j - beta_j v_{j-1} with a lane
+// per row adding its products in CRS order, and alpha_j = w.v_j over
+// k_lz_a's element partition and order. With a V0 plan every value equals the
+// four-launch step's (product, k_lz_a, k_lz_b, k_scale) bit for bit.
+template <typename VT, typename BT>
+__global__ __launch_bounds__(kWG) void k_lz_step(const int32_t* __restrict__ rp,
+                                                 const int32_t* __restrict__ ci,
+                                                 const VT* __restrict__ val, int64_t n,
+                                                 const double* __restrict__ win,
+                                                 const double* __restrict__ vin,
+                                                 const double* __restrict__ beta_j,
+                                                 double* __restrict__ vout,
+                                                 const double* __restrict__ vprev,
+                                                 double* __restrict__ wout,
+                                                 double* __restrict__ partials, Finish f) {
+  __shared__ double sh[4];
+  const double bj = *beta_j;
+  double s = 0.0;
+  for (int64_t i = (int64_t)blockIdx.x * kWG + threadIdx.x; i < n; i += (int64_t)kRed * kWG) {
+    const int32_t a = rp[i], e = rp[i + 1];
+    double acc = 0.0;
+    int32_t j = a;
+    for (; j + 4 <= e; j += 4) {
+      int32_t c[4];
+      VT v[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        c[u] = ci[j + u];
+        v[u] = val[j + u];
+      }
+      double x[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) x[u] = vin ? vin[c[u]] : win[c[u]] / bj;
+#pragma unroll
+      for (int u = 0; u < 4; ++u) acc = fma(dev::widen(v[u]), dev::widen((BT)x[u]), acc);
+    }
+    for (; j < e; ++j) {
+      const int32_t c = ci[j];
+      acc = fma(dev::widen(val[j]), dev::widen((BT)(vin ? vin[c] : win[c] / bj)), acc);
+    }
+    const double vi = vin ? vin[i] : win[i] / bj;
+    if (!vin) vout[i] = vi;
+    const double wi = fma(-bj, vprev[i], acc);
+    wout[i] = wi;
+    s = fma(wi, vi, s);
+  }
+  s = block_sum(s, sh);
+  finish_if_last(partials, s, f, sh);
+}
+
 // v_out = w / beta (beta = norm stored at *beta_next), with its float32 copy
 // for FP32-storage plans
 __global__ __launch_bounds__(kWG) void k_scale(double* __restrict__ out, float* __restrict__ out32,
@@ -386,14 +439,16 @@ int dot(const double* x, const double* y, int64_t n, SolverWs& w, int op, int ds
   return SPMV_OK;
 }
 
-// one CG iteration: Ap = A p; alpha = rr/(p.Ap); x += alpha p; r -= alpha Ap;
-// beta = r.r/rr; rr = r.r; p = r + beta p
-bool cg_one_launch(const Plan& P) {
+// plans whose product runs a lane per row or four lanes per row take the
+// one-launch CG and Lanczos steps (their products go a lane per row)
+bool one_launch_step(const Plan& P) {
   return P.variant == SPMV_V0_THREAD_ROW || P.variant == SPMV_V1_LANES4;
 }
 
+// one CG iteration: Ap = A p; alpha = rr/(p.Ap); x += alpha p; r -= alpha Ap;
+// beta = r.r/rr; rr = r.r; p = r + beta p
 int cg_iteration(const Plan& P, double* x, SolverWs& w, int64_t n, hipStream_t s) {
-  if (cg_one_launch(P)) {
+  if (one_launch_step(P)) {
     if (P.vdt == SPMV_F64)
       k_cg_step<double, double><<<kRed, kWG, 0, s>>>(
           P.row_ptr, P.col_idx, static_cast<const double*>(P.val), n, w.r, w.p, w.pn, w.Ap,
@@ -537,7 +592,33 @@ int run_lanczos(const Plan& P, const double* v0, int k, double* alpha, double* b
   static const double zero = 0.0;
   SPMV_HIP(hipMemcpyAsync(hb, &zero, sizeof(double), hipMemcpyHostToDevice, s));
   int prev = 0, cur = 1, nxt = 2;
-  for (int j = 0; j < k; ++j) {
+  if (one_launch_step(P)) {
+    // two launches per step; w alternates between two buffers, since a
+    // step forms v_j from the previous w while it writes the new one
+    double* wb[2] = {w.Ap, w.pn};
+    for (int j = 0; j < k; ++j) {
+      double* wo = wb[j & 1];
+      const double* wi = j == 0 ? nullptr : wb[(j & 1) ^ 1];
+      const double* vi = j == 0 ? V[cur] : nullptr;
+      if (P.vdt == SPMV_F64)
+        k_lz_step<double, double><<<kRed, kWG, 0, s>>>(
+            P.row_ptr, P.col_idx, static_cast<const double*>(P.val), n, wi, vi, hb + j, V[cur],
+            V[prev], wo, w.partials, fin(w, 0, S_TMP, ha + j));
+      else
+        k_lz_step<float, float><<<kRed, kWG, 0, s>>>(
+            P.row_ptr, P.col_idx, static_cast<const float*>(P.val), n, wi, vi, hb + j, V[cur],
+            V[prev], wo, w.partials, fin(w, 0, S_TMP, ha + j));
+      SPMV_HIP(hipGetLastError());
+      k_lz_b<<<kRed, kWG, 0, s>>>(wo, V[cur], ha + j, n, w.partials,
+                                  fin(w, 1, S_TMP, hb + j + 1));
+      SPMV_HIP(hipGetLastError());
+      const int t = prev;
+      prev = cur;
+      cur = nxt;
+      nxt = t;
+    }
+  }
+  for (int j = 0; j < k && !one_launch_step(P); ++j) {
     st = plan_apply_cast(P, V[cur], v32, wv, s);
     if (st) return st;
     k_lz_a<<<kRed, kWG, 0, s>>>(wv, V[cur], V[prev], hb + j, n, w.partials,

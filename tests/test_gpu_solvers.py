@@ -95,14 +95,17 @@ def test_cg_rejects_bad_arguments(lap128):
                           torch.empty(n, dtype=torch.uint8, device=DEV), n)
 
 
+@pytest.mark.parametrize("variant", [None, 0])
 @pytest.mark.parametrize("dt", ["f64", "f32"])
-def test_lanczos_extreme_eigenvalues(dt):
+def test_lanczos_extreme_eigenvalues(dt, variant):
+    """Default plan, and a V0 plan (two launches per step)."""
     from scipy.linalg import eigvalsh_tridiagonal
     m, k = 64, 300
     A = crsgen.laplace2d(m)
     tdt = torch.float32 if dt == "f32" else torch.float64
     val = A.val.astype(np.float32) if dt == "f32" else A.val
-    M = pkg.CRSMatrix(A.n_rows, A.n_cols, A.row_ptr, A.col_idx, val, val_dtype=tdt, device=DEV)
+    M = pkg.CRSMatrix(A.n_rows, A.n_cols, A.row_ptr, A.col_idx, val, val_dtype=tdt,
+                      flags=0 if variant is None else pkg.SPMV_FLAG_VARIANT(variant), device=DEV)
     v0 = torch.from_numpy(crsgen.uniform_vec(A.n_rows, 7)).to(DEV)
     nb = pkg.spmv_lanczos_workspace_size(A.n_rows, k)
     ws = torch.empty(nb, dtype=torch.uint8, device=DEV)
@@ -153,10 +156,12 @@ def test_cg_fixed_iterations_match_cpu_cg(lap128, graph, variant):
         assert np.array_equal(x, first[0]) and rr == first[1]  # run to run: bitwise
 
 
-def test_lanczos_first_steps_match_cpu():
+@pytest.mark.parametrize("variant", [None, 0])
+def test_lanczos_first_steps_match_cpu(variant):
     m, k = 48, 12
     A = crsgen.laplace2d(m)
-    M = pkg.CRSMatrix.from_crs(A, device=DEV)
+    M = pkg.CRSMatrix.from_crs(A, flags=0 if variant is None else pkg.SPMV_FLAG_VARIANT(variant),
+                               device=DEV)
     v0 = crsgen.uniform_vec(A.n_rows, 9)
     nb = pkg.spmv_lanczos_workspace_size(A.n_rows, k)
     ws = torch.empty(nb, dtype=torch.uint8, device=DEV)
@@ -222,3 +227,24 @@ def test_two_launch_cg_equals_four_launch(n, dt):
     for x, rr in out[1:]:
         assert rr == out[0][1]
         assert np.array_equal(x.view(np.int64), out[0][0].view(np.int64))
+
+
+@pytest.mark.parametrize("dt", ["f64", "f32"])
+def test_two_launch_lanczos_equals_four_launch(dt):
+    """The same argument for Lanczos: on a diagonal matrix the one-launch
+    step (V0 plan) and the four-launch step (V4 plan) give the same alpha and
+    beta bit for bit over 60 steps, in both storage precisions."""
+    rng = np.random.default_rng(11)
+    n = 90_001
+    d = 1.0 + rng.integers(0, 4096, size=n) / 1024.0
+    v0 = torch.from_numpy(rng.uniform(-1, 1, size=n)).to(DEV)
+    k = 60
+    nb = pkg.spmv_lanczos_workspace_size(n, k)
+    ws = torch.empty(nb, dtype=torch.uint8, device=DEV)
+    out = []
+    for v in (0, 4):
+        M = _diag_plan(d, v, dt)
+        out.append(pkg.spmv_lanczos(M.handle, v0, k, ws, nb))
+    (a0, b0), (a4, b4) = out
+    assert np.array_equal(np.asarray(a0).view(np.int64), np.asarray(a4).view(np.int64))
+    assert np.array_equal(np.asarray(b0).view(np.int64), np.asarray(b4).view(np.int64))
