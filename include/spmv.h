@@ -273,7 +273,12 @@ int spmv_cg_solve_noalloc(spmv_handle h, const double* b, double* x, double tol,
  * (beta[0..k-2] are the off-diagonals of T_k; beta[k-1] is the norm of the
  * last residual vector). The eigenvalues of T_k approximate the extreme
  * eigenvalues of a symmetric A. A zero beta (invariant subspace) makes the
- * following values non-finite. workspace: spmv_lanczos_workspace_size bytes.
+ * following values non-finite. A step is four launches (the product with the
+ * plan's variant, two fused reductions, the scaling of the next vector); for
+ * a plan running V0 or V1 it is two (the next vector formed where the product
+ * gathers it, the product a lane per row in CRS order, alpha; then beta),
+ * with V0 equal to the four-launch step bit for bit. workspace:
+ * spmv_lanczos_workspace_size bytes.
  */
 int spmv_lanczos_workspace_size(int64_t n, int32_t k, size_t* bytes);
 int spmv_lanczos(spmv_handle h, const double* v0, int32_t k, double* alpha, double* beta,
