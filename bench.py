@@ -420,6 +420,8 @@ def run_extra(A, B, M, pkg, pm, dev, stream, args):
     if wname != "hamiltonian_like_N6M":
         ex["hamiltonian_like_N6M"] = run_hamiltonian(pkg, pm, dev, stream)
         ex["rcm_mesh3d_280"] = run_rcm(pkg, pm, dev, stream, A=A, B=B)["mesh3d_280_permuted"]
+        ex["config3_parts"] = run_config3_parts(pkg, pm, dev, stream, steps)
+        ex["split_shards_hamiltonian_like_N6M"] = run_split_section(pkg, pm, dev, stream)
     ex["spmm_laplace2d_256"] = run_spmm_small(pkg, pm, dev, stream)
     ex["batch_4096"] = run_batch(pkg, pm, dev, stream)
     ex["laplace2d_256"] = run_small(pkg, pm, dev, stream)
