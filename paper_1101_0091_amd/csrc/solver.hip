@@ -617,21 +617,23 @@ int run_lanczos(const Plan& P, const double* v0, int k, double* alpha, double* b
       cur = nxt;
       nxt = t;
     }
-  }
-  for (int j = 0; j < k && !one_launch_step(P); ++j) {
-    st = plan_apply_cast(P, V[cur], v32, wv, s);
-    if (st) return st;
-    k_lz_a<<<kRed, kWG, 0, s>>>(wv, V[cur], V[prev], hb + j, n, w.partials,
-                                fin(w, 0, S_TMP, ha + j));
-    SPMV_HIP(hipGetLastError());
-    k_lz_b<<<kRed, kWG, 0, s>>>(wv, V[cur], ha + j, n, w.partials, fin(w, 1, S_TMP, hb + j + 1));
-    SPMV_HIP(hipGetLastError());
-    k_scale<<<vgrid(n), kWG, 0, s>>>(V[nxt], v32, wv, hb + j + 1, n);
-    SPMV_HIP(hipGetLastError());
-    const int t = prev;
-    prev = cur;
-    cur = nxt;
-    nxt = t;
+  } else {
+    for (int j = 0; j < k; ++j) {
+      st = plan_apply_cast(P, V[cur], v32, wv, s);
+      if (st) return st;
+      k_lz_a<<<kRed, kWG, 0, s>>>(wv, V[cur], V[prev], hb + j, n, w.partials,
+                                  fin(w, 0, S_TMP, ha + j));
+      SPMV_HIP(hipGetLastError());
+      k_lz_b<<<kRed, kWG, 0, s>>>(wv, V[cur], ha + j, n, w.partials,
+                                  fin(w, 1, S_TMP, hb + j + 1));
+      SPMV_HIP(hipGetLastError());
+      k_scale<<<vgrid(n), kWG, 0, s>>>(V[nxt], v32, wv, hb + j + 1, n);
+      SPMV_HIP(hipGetLastError());
+      const int t = prev;
+      prev = cur;
+      cur = nxt;
+      nxt = t;
+    }
   }
   std::vector<double> hh(2 * (size_t)k + 1);
   SPMV_HIP(hipMemcpyAsync(hh.data(), hist, sizeof(double) * hh.size(), hipMemcpyDeviceToHost, s));
