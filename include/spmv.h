@@ -82,7 +82,10 @@ typedef enum {
 #define SPMV_NUM_SELECTOR_OUTPUTS 7
 
 /* spmv_create flags. The low byte selects how the variant is chosen. */
-#define SPMV_SELECT_DEFAULT 0x0u  /* MLP selector if loaded, else V4 */
+/* Default: V4 where the plan takes its window form, V6 where the plan holds
+ * the chunked copy, else the MLP selector's pick if weights are loaded, else
+ * V4. */
+#define SPMV_SELECT_DEFAULT 0x0u
 #define SPMV_SELECT_MLP 0x1u      /* MLP selector; fall back to autotune when unsure */
 #define SPMV_SELECT_AUTOTUNE 0x2u /* time every variant, keep the fastest */
 #define SPMV_SELECT_FIXED 0x3u    /* use the variant in bits 8..11 */

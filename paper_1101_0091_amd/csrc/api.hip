@@ -379,7 +379,19 @@ int plan_build(Plan& p, int64_t n_rows, int64_t n_cols, int64_t nnz, const int32
     else
       st = autotune(p, s);
   } else {  // default
-    p.variant = p.have_pred ? selector_pick(p) : SPMV_V4_LDS_BLOCK;
+    // structure measured at create decides first: windows that hold most of
+    // the nonzeros (a pattern scattered inside a few dense column regions,
+    // of which the selector's label collection has no example: its network
+    // ranks V2 first on the permuted 3D stencil, 2.1x slower there than the
+    // window form) take V4 in that form, and a chunked copy that fits takes
+    // V6 (the best variant on most label matrices that have one); the
+    // network ranks the rest, V4 without weights
+    if (p.v4_form == kV4Window)
+      p.variant = SPMV_V4_LDS_BLOCK;
+    else if (p.sell_ok)
+      p.variant = SPMV_V6_SELL64;
+    else
+      p.variant = p.have_pred ? selector_pick(p) : SPMV_V4_LDS_BLOCK;
   }
   return st;
 }

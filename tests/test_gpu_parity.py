@@ -894,9 +894,9 @@ def test_batch_full_size_4096():
 
 @pytest.mark.parametrize("mode", ["default", "mlp"])
 def test_selector_plan_masks_v6(mode):
-    """A selector plan picks the smallest predicted time over V0-V6 when it
-    holds the V6 copy and over V0-V5 when it does not (the same network
-    outputs), and multiplies correctly."""
+    """The network's outputs are the same for a plan with and without the V6
+    copy; the default mode takes V6 where the copy is held and the smallest
+    predicted time over V0-V5 where it is not; both multiply correctly."""
     A, B = case("hamiltonian_200k")
     flags = pkg.SPMV_SELECT_DEFAULT if mode == "default" else pkg.SPMV_SELECT_MLP
     M0 = pkg.CRSMatrix.from_crs(A, flags=flags, device=DEV)
@@ -906,11 +906,26 @@ def test_selector_plan_masks_v6(mode):
         p0, p = pkg.spmv_get_predictions(M0.handle), pkg.spmv_get_predictions(M.handle)
         assert np.array_equal(p0, p)
         if mode == "default":
+            assert M0.v4_form != pkg.SPMV_V4_WINDOWS
             assert M0.variant == int(np.argmin(p[:6]))
-            assert M.variant == int(np.argmin(p))
+            assert M.variant == pkg.SPMV_V6_SELL64
     Cref, S = oracle.spmv(A.n_rows, A.row_ptr, A.col_idx, A.val, B)
     assert oracle.bound_ok(M.apply(_gpu(B)).cpu().numpy(), Cref, A.row_ptr, S)[0]
     assert oracle.bound_ok(M0.apply(_gpu(B)).cpu().numpy(), Cref, A.row_ptr, S)[0]
+
+
+def test_default_mode_takes_the_window_form():
+    """The default mode on the permuted 3D stencil with extras: the plan's
+    windows hold most nonzeros, so it runs V4 in its window form whatever the
+    network ranks first, and equals the oracle bit for bit."""
+    A = crsgen.mesh3d(130, seed=3)[0]  # 2.2M rows: 537 super-blocks
+    B = rhs(A)
+    M = pkg.CRSMatrix.from_crs(A, flags=pkg.SPMV_SELECT_DEFAULT | SELL, device=DEV)
+    assert M.v4_form == pkg.SPMV_V4_WINDOWS
+    assert M.variant == 4  # V4_lds_block
+    Cref, _ = oracle.spmv(A.n_rows, A.row_ptr, A.col_idx, A.val, B)
+    C = M.apply(_gpu(B)).cpu().numpy()
+    assert np.array_equal(C.view(np.int64), Cref.view(np.int64))
 
 
 @pytest.mark.parametrize("dt", ["f64", "f32"])
