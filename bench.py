@@ -36,6 +36,10 @@ PAPER_CPU = {"hardware": "Intel Xeon X5550 (Nehalem EP, 4 cores, 2.66 GHz), one 
              "spmv_gflops": 2.25, "spmv_gbs": 18.1, "stream_triad_gbs": 21.2,
              "model_bound_gflops_at_18.1GBs": 2.66}
 SELL = 0  # plan flag requesting the V6 chunked copy; set in main()
+# multi-RHS products kept for the accuracy report: per (precision, k) the GPU's
+# C on a seeded row sample, with the sample's rows of A (see spmm_samples)
+SPMM_SAMPLES: list = []
+SPMM_SAMPLE_ROWS = 4096
 
 
 def log(msg):
@@ -429,22 +433,43 @@ def run_extra(A, B, M, pkg, pm, dev, stream, args):
     return ex
 
 
-def run_spmm(A, M, pkg, pm, dev, stream, ks, sv):
+def sample_rows(A):
+    """A seeded sample of rows (the first and last included) and those rows of
+    A as a CRS matrix of their own."""
+    import numpy as np
+
+    import crsgen
+    rng = np.random.default_rng(17)
+    m = min(SPMM_SAMPLE_ROWS, A.n_rows)
+    rows = np.unique(np.concatenate([[0, A.n_rows - 1],
+                                     rng.choice(A.n_rows, size=m, replace=False)]))
+    lens = (A.row_ptr[rows + 1] - A.row_ptr[rows]).astype(np.int64)
+    rp = np.concatenate([[0], np.cumsum(lens)]).astype(np.int32)
+    idx = np.concatenate([np.arange(A.row_ptr[r], A.row_ptr[r + 1]) for r in rows])
+    return rows, crsgen.CRS(len(rows), A.n_cols, rp, A.col_idx[idx], A.val[idx])
+
+
+def run_spmm(A, M, pkg, pm, dev, stream, ks, sv, keep=False):
     """C = A B for k right-hand sides (B and C row-major, ldb = ldc = k) with
     plan M; per k the time, FP64 GFlop/s and the fraction of 8 TB/s on the CRS
-    compulsory bytes of k columns (B read once, C written once)."""
+    compulsory bytes of k columns (B read once, C written once). keep: hold C
+    on a row sample for the accuracy report."""
     import numpy as np
     import torch
 
     import crsgen
     bdt, code = (np.float32, pkg.SPMV_F32) if sv == 4 else (np.float64, pkg.SPMV_F64)
     out = {"variant": variant_name(pkg, M)}
+    rows, sub = sample_rows(A) if keep else (None, None)
     for k in ks:
         Bk = torch.from_numpy(crsgen.uniform_vec(A.n_cols * k, 4).reshape(A.n_cols, k)
                               .astype(bdt)).to(dev)
         Ck = torch.empty((A.n_rows, k), dtype=torch.float64, device=dev)
         per, _ = time_launches(lambda: pkg.spmm_apply(M.handle, k, Bk, k, code, Ck, k), 20, 3,
                                stream)
+        if keep:
+            SPMM_SAMPLES.append({"sv": sv, "k": k, "sub": sub,
+                                 "C": Ck[torch.from_numpy(rows).to(dev)].cpu().numpy()})
         t = float(np.median(per)) / 1000
         comp = pm.compulsory_bytes(A.n_rows, A.n_cols, A.nnz, k, sv, sv)
         out[str(k)] = {"us": round(t * 1e6, 1), "fp64_gflops": round(pm.gflops(A.nnz, t, k), 1),
@@ -603,8 +628,7 @@ def run_hamiltonian(pkg, pm, dev, stream):
                                            lambda: pkg.spmv_apply(M.handle, Bd, code, C), stream,
                                            sv, wname)
         M.variant, M.v4_form = picked, pform
-        if tag == "fp64":
-            rec["spmm"] = run_spmm(A, M, pkg, pm, dev, stream, (2, 4, 8, 16, 32), sv)
+        rec["spmm"] = run_spmm(A, M, pkg, pm, dev, stream, (1, 2, 4, 8, 16, 32), sv, keep=True)
         res[tag] = rec
         log(f"hamiltonian {tag}: {rec}")
         del M, Bd
@@ -1009,7 +1033,56 @@ def cpu_baseline(A, B, gpu_results=None):
                "fp32_storage_rel_2norm": float(np.linalg.norm(c32 - Cref) /
                                                np.linalg.norm(Cref))}
         log(f"accuracy vs the oracle: {acc}")
+    if SPMM_SAMPLES:
+        acc = dict(acc or {})
+        acc["spmm_hamiltonian_like_N6M"] = spmm_accuracy(SPMM_SAMPLES)
     return base, scheme, acc
+
+
+def spmm_accuracy(samples):
+    """Per precision and k, the multi-RHS products on their row samples against
+    the oracle's FP64 product of the FP64 inputs, column by column: FP64
+    against the per-row bound 8 nnz_row 2^-53 S_i, FP32 storage as each
+    column's max |dC| / S_i and relative 2-norm (reported, not bounded)."""
+    import numpy as np
+
+    import crsgen
+    import oracle
+    out = {}
+    for k in sorted({s["k"] for s in samples}):
+        Bh = None
+        for s in samples:
+            if s["k"] != k:
+                continue
+            sub = s["sub"]
+            if Bh is None:  # the B the timed products read, in FP64
+                Bh = crsgen.uniform_vec(sub.n_cols * k, 4).reshape(sub.n_cols, k)
+                Cref, S = oracle.spmm(sub.n_rows, sub.row_ptr, sub.col_idx, sub.val, Bh)
+            out.setdefault("fp64" if s["sv"] == 8 else "fp32_storage", {})[str(k)] = \
+                spmm_column_errors(s, sub, Cref, S)
+        del Bh
+    out["sample"] = f"{samples[0]['sub'].n_rows} seeded rows of the N = 6.0M matrix per product"
+    return out
+
+
+def spmm_column_errors(s, sub, Cref, S):
+    import numpy as np
+
+    import oracle
+    d = np.abs(s["C"] - Cref)
+    if s["sv"] == 8:
+        res = [oracle.bound_ok(s["C"][:, j], Cref[:, j], sub.row_ptr, S[:, j])
+               for j in range(Cref.shape[1])]
+        return {"within_bound": all(ok for ok, _ in res),
+                "worst_error_over_bound": max(w for _, w in res)}
+    ratio = np.where(S > 0, d / np.maximum(S, 1e-300), 0.0)
+    rel = np.linalg.norm(s["C"] - Cref, axis=0) / np.linalg.norm(Cref, axis=0)
+    return {"max_err_over_S_per_column": [float(f"{x:.3g}") for x in ratio.max(axis=0)],
+            "rel_2norm_per_column": [float(f"{x:.3g}") for x in rel]}
+
+
+if __name__ == "__main__":
+    main()
 
 
 if __name__ == "__main__":

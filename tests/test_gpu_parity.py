@@ -274,6 +274,30 @@ def test_spmm_from_v6_copy(name, k, dt):
     assert np.all(Ca[:, k:] == 7.0)
 
 
+@pytest.mark.parametrize("flags", [pkg.SPMV_FLAG_VARIANT(6) | pkg.SPMV_FLAG_SELL,
+                                   pkg.SPMV_FLAG_VARIANT(4) | pkg.SPMV_FLAG_V4_WINDOWS,
+                                   pkg.SPMV_FLAG_VARIANT(2)])
+def test_spmm_single_column_is_the_single_product(flags):
+    """k = 1 with unit leading dimensions runs the plan's single product: the
+    same bits as spmv_apply; a strided single column takes the multi-RHS
+    kernels and stays within the bound."""
+    A, B = case("hamiltonian_200k")
+    Cref, S = oracle.spmv(A.n_rows, A.row_ptr, A.col_idx, A.val, B)
+    M = pkg.CRSMatrix.from_crs(A, flags=flags, device=DEV)
+    Bd = _gpu(B)
+    C1 = M.apply(Bd)
+    Cm = torch.full((A.n_rows, 1), float("nan"), dtype=torch.float64, device=DEV)
+    pkg.spmm_apply(M.handle, 1, Bd.view(A.n_cols, 1), 1, M.code, Cm, 1)
+    assert torch.equal(Cm[:, 0], C1)
+    Bs = torch.zeros((A.n_cols, 2), dtype=torch.float64, device=DEV)
+    Bs[:, 0] = Bd
+    Cs = torch.full((A.n_rows, 2), 7.0, dtype=torch.float64, device=DEV)
+    pkg.spmm_apply(M.handle, 1, Bs, 2, M.code, Cs, 2)
+    Cs = Cs.cpu().numpy()
+    assert oracle.bound_ok(Cs[:, 0], Cref, A.row_ptr, S)[0]
+    assert np.all(Cs[:, 1] == 7.0)
+
+
 @pytest.mark.parametrize("dt", ["f64", "f32"])
 @pytest.mark.parametrize("k", [2, 4, 6, 8, 16])
 def test_spmm_from_v6_copy_misaligned_B(k, dt):
