@@ -570,40 +570,91 @@ __device__ __forceinline__ void sell_spmm_rows(int64_t a, int32_t w, int lane, i
   // waits for that load before the next one is issued)
   constexpr bool kPinV = !std::is_same<VT, double>::value;
   constexpr bool kPinB = !std::is_same<BT, double>::value;
+  // a lane's G slots of a full group are contiguous (values, columns and
+  // deltas): one vector load each, as in the single-vector kernels
+  // (Hamiltonian-like matrix, 6M rows, against one load per slot: float64
+  // k = 2/3 241/353 -> 213/308 us, float32 storage k = 2/3/4 209/302/280 ->
+  // 126/230/196 us)
+  using VG = typename std::conditional<G == 2, f64x2, f32x4>::type;
+  using CG = typename std::conditional<G == 2, i32x2, i32x4>::type;
+  using DG = typename std::conditional<
+      G == 2, typename std::conditional<DB == 16, uint32_t, uint16_t>::type,
+      typename std::conditional<DB == 16, u32x2, uint32_t>::type>::type;
+  const int32_t GQ = w - w % G;
   for (int32_t j = 0; j < w; j += U) {
     VT vr[U];
     int32_t c[U];
     if constexpr (DB > 0) {
-      // deltas held as 32-bit words and decoded after every load is issued
+      // deltas held as loaded and decoded after every load is issued
+      DG dg[U / G];
       uint32_t d[U];
       int32_t b[U];
 #pragma unroll
-      for (int u = 0; u < U; ++u) {
-        if (j + u < w) {
-          const int64_t o = slot_offset<G>(j + u, lane, w);
-          vr[u] = dev::ld_stream(sval + a * kChunk + o);
-          d[u] = dev::ld_stream(dp + o);
-          b[u] = bp[j + u];
+      for (int u = 0; u < U; u += G) {
+        const int32_t j0 = j + u;
+        if (j0 + G <= GQ) {
+          const int64_t o = G * ((int64_t)(j0 / G) * kChunk + lane);
+          const VG q = dev::ld_stream(reinterpret_cast<const VG*>(sval + a * kChunk + o));
+          dg[u / G] = dev::ld_stream(reinterpret_cast<const DG*>(dp + o));
+#pragma unroll
+          for (int t = 0; t < G; ++t) {
+            vr[u + t] = q[t];
+            d[u + t] = 0xFFFFFFFFu;  // taken from dg below
+            b[u + t] = bp[j0 + t];
+          }
         } else {
-          vr[u] = (VT)0;
-          d[u] = kPad<DB>;
-          b[u] = 0;
+          dg[u / G] = DG{};
+#pragma unroll
+          for (int t = 0; t < G; ++t) {
+            if (j0 + t < w) {
+              const int64_t o = slot_offset<G>(j0 + t, lane, w);
+              vr[u + t] = dev::ld_stream(sval + a * kChunk + o);
+              d[u + t] = dev::ld_stream(dp + o);
+              b[u + t] = bp[j0 + t];
+            } else {
+              vr[u + t] = (VT)0;
+              d[u + t] = kPad<DB>;
+              b[u + t] = 0;
+            }
+          }
         }
       }
 #pragma unroll
+      for (int u = 0; u < U / G; ++u) asm volatile("" : "+v"(dg[u]));
+#pragma unroll
       for (int u = 0; u < U; ++u) asm volatile("" : "+v"(d[u]));
 #pragma unroll
-      for (int u = 0; u < U; ++u) c[u] = delta_col<DB>(d[u], b[u]);
+      for (int u = 0; u < U; u += G) {
+        const bool full = j + u + G <= GQ;
+#pragma unroll
+        for (int t = 0; t < G; ++t)
+          c[u + t] = delta_col<DB>(full ? delta_field<DB>(dg[u / G], t) : d[u + t], b[u + t]);
+      }
     } else {
 #pragma unroll
-      for (int u = 0; u < U; ++u) {
-        if (j + u < w) {
-          const int64_t o = a * kChunk + slot_offset<G>(j + u, lane, w);
-          vr[u] = dev::ld_stream(sval + o);
-          c[u] = dev::ld_stream(sci + o);
+      for (int u = 0; u < U; u += G) {
+        const int32_t j0 = j + u;
+        if (j0 + G <= GQ) {
+          const int64_t o = a * kChunk + G * ((int64_t)(j0 / G) * kChunk + lane);
+          const VG q = dev::ld_stream(reinterpret_cast<const VG*>(sval + o));
+          const CG cq = dev::ld_stream(reinterpret_cast<const CG*>(sci + o));
+#pragma unroll
+          for (int t = 0; t < G; ++t) {
+            vr[u + t] = q[t];
+            c[u + t] = cq[t];
+          }
         } else {
-          vr[u] = (VT)0;
-          c[u] = -1;
+#pragma unroll
+          for (int t = 0; t < G; ++t) {
+            if (j0 + t < w) {
+              const int64_t o = a * kChunk + slot_offset<G>(j0 + t, lane, w);
+              vr[u + t] = dev::ld_stream(sval + o);
+              c[u + t] = dev::ld_stream(sci + o);
+            } else {
+              vr[u + t] = (VT)0;
+              c[u + t] = -1;
+            }
+          }
         }
       }
     }
@@ -776,39 +827,91 @@ __device__ __forceinline__ void sell_spmm_lanes_rows(int64_t a, int32_t w, int r
   using DT = typename std::conditional<DB == 16, uint16_t, uint8_t>::type;
   const DT* dp = reinterpret_cast<const DT*>(sdl + a * kChunk);
   const int32_t* bp = sbase + a;
+  // a row's G slots of a full group are contiguous: one vector load each
+  // (Hamiltonian-like matrix, 6M rows, against one load per slot: float32
+  // k = 8/16/32 434/724/1420 -> 366/697/1383 us, float64 k = 4 370 -> 361;
+  // float64 with 8 or 16 lanes per row 1243/2682 -> 1284/2713 at k = 16/32,
+  // so those keep one load per slot)
+  constexpr bool kVec = G == 4 || LPR <= 4;
+  using VG = typename std::conditional<G == 2, f64x2, f32x4>::type;
+  using CG = typename std::conditional<G == 2, i32x2, i32x4>::type;
+  using DG = typename std::conditional<
+      G == 2, typename std::conditional<DB == 16, uint32_t, uint16_t>::type,
+      typename std::conditional<DB == 16, u32x2, uint32_t>::type>::type;
+  const int32_t GQ = w - w % G;
   for (int32_t j = 0; j < w; j += kSpmmLU) {
     VT vr[kSpmmLU];
     int32_t c[kSpmmLU];
     if constexpr (DB > 0) {
+      DG dg[kSpmmLU / G];
       uint32_t d[kSpmmLU];
       int32_t b[kSpmmLU];
 #pragma unroll
-      for (int u = 0; u < kSpmmLU; ++u) {
-        if (j + u < w) {
-          const int64_t o = slot_offset<G>(j + u, row, w);
-          vr[u] = dev::ld_stream(sval + a * kChunk + o);
-          d[u] = dev::ld_stream(dp + o);
-          b[u] = bp[j + u];
+      for (int u = 0; u < kSpmmLU; u += G) {
+        const int32_t j0 = j + u;
+        if (kVec && j0 + G <= GQ) {
+          const int64_t o = G * ((int64_t)(j0 / G) * kChunk + row);
+          const VG q = dev::ld_stream(reinterpret_cast<const VG*>(sval + a * kChunk + o));
+          dg[u / G] = dev::ld_stream(reinterpret_cast<const DG*>(dp + o));
+#pragma unroll
+          for (int t = 0; t < G; ++t) {
+            vr[u + t] = q[t];
+            d[u + t] = 0xFFFFFFFFu;  // taken from dg below
+            b[u + t] = bp[j0 + t];
+          }
         } else {
-          vr[u] = (VT)0;
-          d[u] = kPad<DB>;
-          b[u] = 0;
+          dg[u / G] = DG{};
+#pragma unroll
+          for (int t = 0; t < G; ++t) {
+            if (j0 + t < w) {
+              const int64_t o = slot_offset<G>(j0 + t, row, w);
+              vr[u + t] = dev::ld_stream(sval + a * kChunk + o);
+              d[u + t] = dev::ld_stream(dp + o);
+              b[u + t] = bp[j0 + t];
+            } else {
+              vr[u + t] = (VT)0;
+              d[u + t] = kPad<DB>;
+              b[u + t] = 0;
+            }
+          }
         }
       }
 #pragma unroll
+      for (int u = 0; u < kSpmmLU / G; ++u) asm volatile("" : "+v"(dg[u]));
+#pragma unroll
       for (int u = 0; u < kSpmmLU; ++u) asm volatile("" : "+v"(d[u]));
 #pragma unroll
-      for (int u = 0; u < kSpmmLU; ++u) c[u] = delta_col<DB>(d[u], b[u]);
+      for (int u = 0; u < kSpmmLU; u += G) {
+        const bool full = kVec && j + u + G <= GQ;
+#pragma unroll
+        for (int t = 0; t < G; ++t)
+          c[u + t] = delta_col<DB>(full ? delta_field<DB>(dg[u / G], t) : d[u + t], b[u + t]);
+      }
     } else {
 #pragma unroll
-      for (int u = 0; u < kSpmmLU; ++u) {
-        if (j + u < w) {
-          const int64_t o = a * kChunk + slot_offset<G>(j + u, row, w);
-          vr[u] = dev::ld_stream(sval + o);
-          c[u] = dev::ld_stream(sci + o);
+      for (int u = 0; u < kSpmmLU; u += G) {
+        const int32_t j0 = j + u;
+        if (kVec && j0 + G <= GQ) {
+          const int64_t o = a * kChunk + G * ((int64_t)(j0 / G) * kChunk + row);
+          const VG q = dev::ld_stream(reinterpret_cast<const VG*>(sval + o));
+          const CG cq = dev::ld_stream(reinterpret_cast<const CG*>(sci + o));
+#pragma unroll
+          for (int t = 0; t < G; ++t) {
+            vr[u + t] = q[t];
+            c[u + t] = cq[t];
+          }
         } else {
-          vr[u] = (VT)0;
-          c[u] = -1;
+#pragma unroll
+          for (int t = 0; t < G; ++t) {
+            if (j0 + t < w) {
+              const int64_t o = a * kChunk + slot_offset<G>(j0 + t, row, w);
+              vr[u + t] = dev::ld_stream(sval + o);
+              c[u + t] = dev::ld_stream(sci + o);
+            } else {
+              vr[u + t] = (VT)0;
+              c[u + t] = -1;
+            }
+          }
         }
       }
     }
