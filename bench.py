@@ -1083,7 +1083,3 @@ def spmm_column_errors(s, sub, Cref, S):
 
 if __name__ == "__main__":
     main()
-
-
-if __name__ == "__main__":
-    main()

@@ -50,3 +50,12 @@ def test_mesh_stencil_mask_separates_the_extras():
         assert np.array_equal(np.concatenate([[0], np.cumsum(lens)]), S.row_ptr)
         assert np.array_equal(A.col_idx[st], S.col_idx)
         assert (~st).sum() == A.nnz - S.nnz > 0
+
+
+def test_bench_runs_main_once():
+    """One entry point at module level: the bench prints one JSON line."""
+    import ast
+    src = open(os.path.join(ROOT, "bench.py")).read()
+    calls = [n for n in ast.parse(src).body
+             if isinstance(n, ast.If) and "__main__" in ast.unparse(n.test)]
+    assert len(calls) == 1
