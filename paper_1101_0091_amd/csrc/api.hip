@@ -444,7 +444,7 @@ int spmm_apply(spmv_handle h, int32_t k, const void* B, int64_t ldb, int b_dtype
   // lane per row (5-point Laplacians, 262k and 1M rows: the copy took 1.1-1.3x
   // as long at k = 4 and 1.5-1.8x at k = 8; a 15-entry-per-row matrix ran
   // 1.1-2x faster from the copy)
-  // (lane groups per row, one 16-byte B vector per lane: k = 4, 8, 16, 32
+  // (lane groups per row, one 16-byte B vector per lane: k = 8, 16, 32
   // in float64, 8 .. 64 in float32, aligned operands)
   if (p.variant == SPMV_V6_SELL64 && p.sell_ok && p.nnz >= 8 * p.n_rows &&
       (k <= 8 || sell_spmm_lanes_fit(p, k, B, ldb, C, ldc)))

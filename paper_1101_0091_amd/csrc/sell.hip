@@ -829,7 +829,7 @@ __device__ __forceinline__ void sell_spmm_lanes_rows(int64_t a, int32_t w, int r
   const int32_t* bp = sbase + a;
   // a row's G slots of a full group are contiguous: one vector load each
   // (Hamiltonian-like matrix, 6M rows, against one load per slot: float32
-  // k = 8/16/32 434/724/1420 -> 366/697/1383 us, float64 k = 4 370 -> 361;
+  // k = 8/16/32 434/724/1420 -> 366/697/1383 us, float64 k = 8 653 -> 651;
   // float64 with 8 or 16 lanes per row 1243/2682 -> 1284/2713 at k = 16/32,
   // so those keep one load per slot)
   constexpr bool kVec = G == 4 || LPR <= 4;
@@ -1049,9 +1049,13 @@ template <typename VT, typename BT>
 int sell_spmm_typed(const Plan& p, int k, const BT* B, int64_t ldb, double* C, int64_t ldc,
                     hipStream_t s) {
   // lane groups: k a multiple of the vector width, at most 16 lanes per row
-  // in one pass, B and C aligned to 16-byte vectors
+  // in one pass, B and C aligned to 16-byte vectors; float64 from 4 lanes per
+  // row (k = 8) on: at k = 4 one lane per row with two 16-byte B loads per
+  // slot is faster (Hamiltonian-like matrix, 6M rows: 315 against 361 us;
+  // float32 at 2 lanes per row, k = 8, the other way: 361 against 427 us)
   constexpr int CPL = 16 / sizeof(BT);
-  const bool lanes_ok = k % CPL == 0 && k >= 2 * CPL && k <= 16 * CPL &&
+  constexpr int kMinLanes = std::is_same<BT, double>::value ? 4 : 2;
+  const bool lanes_ok = k % CPL == 0 && k >= kMinLanes * CPL && k <= 16 * CPL &&
                         (double)p.sell_nch * (k / CPL) * kChunk < 4294967295.0 &&
                         reinterpret_cast<uintptr_t>(B) % 16 == 0 && ldb % CPL == 0 &&
                         reinterpret_cast<uintptr_t>(C) % 16 == 0 && ldc % 2 == 0;

@@ -242,7 +242,7 @@ def test_spmm_vs_oracle(k, dt):
 def test_spmm_from_v6_copy(name, k, dt):
     """A plan running V6 multiplies blocks of right-hand sides from its chunked
     copy when its rows average at least 8 entries (lane groups per row for
-    k = 4, 8, 16, 32 in float64 and 8 .. 64 in float32; else column blocks of
+    k = 8, 16, 32 in float64 and 8 .. 64 in float32; else column blocks of
     up to 8, vector loads of B row segments, a scalar partial last block),
     else with the row-group kernel (the 5-point Laplacian); also with padded
     leading dimensions, odd (scalar paths) and aligned (lane groups)."""
