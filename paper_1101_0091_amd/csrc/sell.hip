@@ -799,20 +799,20 @@ __global__ __launch_bounds__(kWG) void k_sell_spmm(int64_t nch, int64_t n,
 }
 
 // Multi-RHS from the chunked copy with LPR lanes per row: lane g of a row
-// owns the CPL columns c0 + g CPL .. (one 16-byte vector of B: 2 float64 or
-// 4 float32), so the LPR lanes of a row read its B row segment as one
-// contiguous piece, and the 64 / LPR rows of a wavefront (consecutive rows of
-// one chunk) read consecutive segments where their columns are consecutive.
-// Wavefront w takes part w % LPR of chunk w / LPR. A row's entries are taken
-// kSpmmLU per round, all their loads issued before the first is used; the
-// lanes of a row load the same value and column (one memory access).
-// Needs B, C, ldb and ldc aligned to the vector (checked by the caller) and
-// c0 + LPR CPL <= k. With remap set, each XCD takes a contiguous range of
+// owns the VPL CPL columns c0 + g VPL CPL .. (VPL 16-byte vectors of B of
+// CPL = 2 float64 or 4 float32 each), so the LPR lanes of a row read its B
+// row segment as one contiguous piece, and the 64 / LPR rows of a
+// wavefront (consecutive rows of one chunk) read consecutive segments where
+// their columns are consecutive. Wavefront w takes part w % LPR of chunk
+// w / LPR. A row's entries are taken kSpmmLU per round, all their loads
+// issued before the first is used; the lanes of a row load the same value
+// and column (one memory access). Needs B, C, ldb and ldc aligned to the
+// vector (checked by the caller) and c0 + LPR VPL CPL <= k. With remap set, each XCD takes a contiguous range of
 // chunks (instead of every eighth workgroup), so that B rows shared by rows a
 // few thousand apart (offset diagonals) can meet again in that XCD's L2.
 constexpr int kSpmmLU = 16;
 
-template <typename VT, typename BT, int LPR, int DB>
+template <typename VT, typename BT, int LPR, int DB, int VPL>
 __device__ __forceinline__ void sell_spmm_lanes_rows(int64_t a, int32_t w, int row, int g,
                                                      int32_t c0,
                                                      const int32_t* __restrict__ sci,
@@ -915,34 +915,43 @@ __device__ __forceinline__ void sell_spmm_lanes_rows(int64_t a, int32_t w, int r
         }
       }
     }
-    V x[kSpmmLU];
+    V x[kSpmmLU][VPL];
 #pragma unroll
     for (int u = 0; u < kSpmmLU; ++u) {
-      x[u] = V{};
-      if (c[u] >= 0)
-        x[u] = *reinterpret_cast<const V*>(B + (int64_t)c[u] * ldb + c0 + g * CPL);
+#pragma unroll
+      for (int q = 0; q < VPL; ++q) {
+        x[u][q] = V{};
+        if (c[u] >= 0)
+          x[u][q] = *reinterpret_cast<const V*>(B + (int64_t)c[u] * ldb + c0 +
+                                                (g * VPL + q) * CPL);
+      }
     }
     // the values and segments in their own types until every load is issued
 #pragma unroll
     for (int u = 0; u < kSpmmLU; ++u) {
       asm volatile("" : "+v"(vr[u]));
-      asm volatile("" : "+v"(x[u]));
+#pragma unroll
+      for (int q = 0; q < VPL; ++q) asm volatile("" : "+v"(x[u][q]));
     }
     // masked slots add fma(0, 0, acc) = acc exactly (acc is never -0)
 #pragma unroll
     for (int u = 0; u < kSpmmLU; ++u) {
       const double v = dev::widen(vr[u]);
-      acc[0] = fma(v, (double)x[u][0], acc[0]);
-      acc[1] = fma(v, (double)x[u][1], acc[1]);
-      if constexpr (CPL == 4) {
-        acc[2] = fma(v, (double)x[u][2], acc[2]);
-        acc[3] = fma(v, (double)x[u][3], acc[3]);
+#pragma unroll
+      for (int q = 0; q < VPL; ++q) {
+        double* aq = acc + q * CPL;
+        aq[0] = fma(v, (double)x[u][q][0], aq[0]);
+        aq[1] = fma(v, (double)x[u][q][1], aq[1]);
+        if constexpr (CPL == 4) {
+          aq[2] = fma(v, (double)x[u][q][2], aq[2]);
+          aq[3] = fma(v, (double)x[u][q][3], aq[3]);
+        }
       }
     }
   }
 }
 
-template <typename VT, typename BT, int LPR>
+template <typename VT, typename BT, int LPR, int VPL>
 __global__ __launch_bounds__(kWG) void k_sell_spmm_lanes(
     int64_t nch, int64_t n, const int32_t* __restrict__ off, const int32_t* __restrict__ sci,
     const int32_t* __restrict__ flag, const int32_t* __restrict__ sbase,
@@ -959,21 +968,25 @@ __global__ __launch_bounds__(kWG) void k_sell_spmm_lanes(
   const int g = lane % LPR;
   const int64_t a = off[chunk];
   const int32_t w = (int32_t)(off[chunk + 1] - a);
-  double acc[CPL];
+  double acc[CPL * VPL];
 #pragma unroll
-  for (int t = 0; t < CPL; ++t) acc[t] = 0.0;
+  for (int t = 0; t < CPL * VPL; ++t) acc[t] = 0.0;
   const int db = flag ? flag[chunk] : 0;
   if (db == 8)
-    sell_spmm_lanes_rows<VT, BT, LPR, 8>(a, w, row, g, c0, sci, sdl, sbase, sval, B, ldb, acc);
+    sell_spmm_lanes_rows<VT, BT, LPR, 8, VPL>(a, w, row, g, c0, sci, sdl, sbase, sval, B, ldb,
+                                              acc);
   else if (db == 16)
-    sell_spmm_lanes_rows<VT, BT, LPR, 16>(a, w, row, g, c0, sci, sdl, sbase, sval, B, ldb, acc);
+    sell_spmm_lanes_rows<VT, BT, LPR, 16, VPL>(a, w, row, g, c0, sci, sdl, sbase, sval, B, ldb,
+                                               acc);
   else
-    sell_spmm_lanes_rows<VT, BT, LPR, 0>(a, w, row, g, c0, sci, sdl, sbase, sval, B, ldb, acc);
+    sell_spmm_lanes_rows<VT, BT, LPR, 0, VPL>(a, w, row, g, c0, sci, sdl, sbase, sval, B, ldb,
+                                              acc);
   const int64_t r = chunk * kChunk + row;
   if (r < n) {
-    double* out = C + r * ldc + c0 + g * CPL;
+    double* out = C + r * ldc + c0 + g * CPL * VPL;
 #pragma unroll
-    for (int t = 0; t < CPL; t += 2) *reinterpret_cast<f64x2*>(out + t) = f64x2{acc[t], acc[t + 1]};
+    for (int t = 0; t < CPL * VPL; t += 2)
+      *reinterpret_cast<f64x2*>(out + t) = f64x2{acc[t], acc[t + 1]};
   }
 }
 
@@ -1030,15 +1043,15 @@ int sell_spmm_pass(const Plan& p, int k, int c0, const BT* B, int64_t ldb, doubl
   return SPMV_OK;
 }
 
-template <typename VT, typename BT, int LPR>
+template <typename VT, typename BT, int LPR, int VPL = 1>
 int sell_spmm_lanes_pass(const Plan& p, int c0, const BT* B, int64_t ldb, double* C,
                          int64_t ldc, hipStream_t s) {
   const int64_t threads = p.sell_nch * LPR * kChunk;
   // contiguous chunk ranges per XCD once B outgrows the 256 MB last-level
   // cache (measured on the Hamiltonian-like matrix: 12% faster at 768 MB of
   // B, 3% slower at 384 MB)
-  const int remap = (double)p.n_cols * (LPR * 16) > 512.0 * (1 << 20);
-  k_sell_spmm_lanes<VT, BT, LPR><<<(unsigned)((threads + kWG - 1) / kWG), kWG, 0, s>>>(
+  const int remap = (double)p.n_cols * (LPR * VPL * 16) > 512.0 * (1 << 20);
+  k_sell_spmm_lanes<VT, BT, LPR, VPL><<<(unsigned)((threads + kWG - 1) / kWG), kWG, 0, s>>>(
       p.sell_nch, p.n_rows, p.sell_off, p.sell_ci, p.sell_wide ? nullptr : p.sell_flag,
       p.sell_base, p.sell_dl, static_cast<const VT*>(p.sell_val), B, ldb, C, ldc, c0, remap);
   SPMV_HIP(hipGetLastError());
@@ -1059,6 +1072,17 @@ int sell_spmm_typed(const Plan& p, int k, const BT* B, int64_t ldb, double* C, i
                         (double)p.sell_nch * (k / CPL) * kChunk < 4294967295.0 &&
                         reinterpret_cast<uintptr_t>(B) % 16 == 0 && ldb % CPL == 0 &&
                         reinterpret_cast<uintptr_t>(C) % 16 == 0 && ldc % 2 == 0;
+  // float64: two B vectors (4 columns) per lane, half the lanes per row
+  // (Hamiltonian-like matrix, 6M rows, k = 8/16/32: 653/1251/2671 -> 593/
+  // 1216/2591 us; float32 with two quads per lane 5-11% slower at k = 16..64)
+  if (lanes_ok && std::is_same<BT, double>::value) {
+    switch (k / CPL) {
+      case 4: return sell_spmm_lanes_pass<VT, BT, 2, 2>(p, 0, B, ldb, C, ldc, s);
+      case 8: return sell_spmm_lanes_pass<VT, BT, 4, 2>(p, 0, B, ldb, C, ldc, s);
+      case 16: return sell_spmm_lanes_pass<VT, BT, 8, 2>(p, 0, B, ldb, C, ldc, s);
+      default: break;
+    }
+  }
   if (lanes_ok) {
     switch (k / CPL) {
       case 2: return sell_spmm_lanes_pass<VT, BT, 2>(p, 0, B, ldb, C, ldc, s);
