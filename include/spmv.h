@@ -177,7 +177,8 @@ int spmv_apply(spmv_handle h, const void* B, int b_dtype, double* C, void* strea
  * for 0 <= c < k. Requires k >= 1, ldb >= k, ldc >= k. The matrix stream is
  * read once for all k columns: from the V6 copy when the plan runs V6, k <= 8
  * and the rows average at least 8 entries, else from the CRS arrays. k = 1
- * with ldb = ldc = 1 is spmv_apply (the plan's variant and form, same results).
+ * with ldb = ldc = 1 is spmv_apply (the plan's variant and form, same results)
+ * unless the plan runs V6 with rows averaging fewer than 8 entries.
  */
 int spmm_apply(spmv_handle h, int32_t k, const void* B, int64_t ldb, int b_dtype, double* C,
                int64_t ldc, void* stream);

@@ -435,8 +435,12 @@ int spmm_apply(spmv_handle h, int32_t k, const void* B, int64_t ldb, int b_dtype
   if ((int64_t)p.n_rows * ldc > INT64_MAX / 2) return fail(SPMV_ERR_UNSUPPORTED, "C too large");
   // one contiguous right-hand side is the single product, in the plan's own
   // variant and form (Hamiltonian-like matrix, 6M rows, from the V6 copy:
-  // 160 us against 216 us through the one-column block kernel)
-  if (k == 1 && ldb == 1 && ldc == 1) return launch_spmv(p, p.variant, B, C, as_stream(stream));
+  // 160 us against 216 us through the one-column block kernel), except on a
+  // V6 plan with short rows, where the row-group kernel below is faster
+  // (256x256 Laplacian, graph-replayed: 2.40 against 2.80 us)
+  const bool short_v6 = p.variant == SPMV_V6_SELL64 && p.nnz < 8 * p.n_rows;
+  if (k == 1 && ldb == 1 && ldc == 1 && !short_v6)
+    return launch_spmv(p, p.variant, B, C, as_stream(stream));
   // a plan running V6 multiplies up to 8 right-hand sides from its chunked copy
   // (one pass over it) when its rows average at least 8 entries; wider blocks
   // use the row-group kernel, which reads the matrix once for any k, and so

@@ -278,9 +278,10 @@ def test_spmm_from_v6_copy(name, k, dt):
                                    pkg.SPMV_FLAG_VARIANT(4) | pkg.SPMV_FLAG_V4_WINDOWS,
                                    pkg.SPMV_FLAG_VARIANT(2)])
 def test_spmm_single_column_is_the_single_product(flags):
-    """k = 1 with unit leading dimensions runs the plan's single product: the
-    same bits as spmv_apply; a strided single column takes the multi-RHS
-    kernels and stays within the bound."""
+    """k = 1 with unit leading dimensions runs the plan's single product (rows
+    averaging at least 8 entries here): the same bits as spmv_apply; a
+    strided single column takes the multi-RHS kernels and stays within the
+    bound."""
     A, B = case("hamiltonian_200k")
     Cref, S = oracle.spmv(A.n_rows, A.row_ptr, A.col_idx, A.val, B)
     M = pkg.CRSMatrix.from_crs(A, flags=flags, device=DEV)
