@@ -807,9 +807,10 @@ __global__ __launch_bounds__(kWG) void k_sell_spmm(int64_t nch, int64_t n,
 // w / LPR. A row's entries are taken kSpmmLU per round, all their loads
 // issued before the first is used; the lanes of a row load the same value
 // and column (one memory access). Needs B, C, ldb and ldc aligned to the
-// vector (checked by the caller) and c0 + LPR VPL CPL <= k. With remap set, each XCD takes a contiguous range of
-// chunks (instead of every eighth workgroup), so that B rows shared by rows a
-// few thousand apart (offset diagonals) can meet again in that XCD's L2.
+// vector (checked by the caller) and c0 + LPR VPL CPL <= k. With remap set,
+// each XCD takes a contiguous range of chunks (instead of every eighth
+// workgroup), so that B rows shared by rows a few thousand apart (offset
+// diagonals) can meet again in that XCD's L2.
 constexpr int kSpmmLU = 16;
 
 template <typename VT, typename BT, int LPR, int DB, int VPL>
